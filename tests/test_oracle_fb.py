@@ -1,0 +1,168 @@
+"""Pins of the oracle's Algorithm 8 (Sec. 3.2), its power-iteration step and the
+gradient-regulariser prox, on tiny grids where dense linear algebra is exact.
+
+The limits checked here are fixed by the mathematics, not by the oracle:
+the normal equations (A^T Lambda A + lambda I) h = A^T Lambda G for the
+l2-regularised problem without constraints, the KKT conditions with the
+positivity constraint, the largest eigenvalue of A^T Lambda A for the power
+iteration, and the closed-form Dirichlet spectrum of the 7-point Laplacian.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import rel_l2
+import synth
+
+
+def tiny(oracle, n=(6, 6, 4), n_angles=6, ns=8, T=0.25):
+    nx, ny, nz = n
+    return oracle.Geometry(nx=nx, ny=ny, nz=nz, dx=0.1, T=T, angles=synth.uniform_angles(n_angles), ns=ns)
+
+
+def dense(apply, in_shape):
+    n = int(np.prod(in_shape))
+    cols = []
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        cols.append(np.asarray(apply(e.reshape(in_shape))).ravel())
+    return np.array(cols).T
+
+
+@pytest.fixture(scope="module")
+def problem(oracle):
+    g = tiny(oracle)
+    rng = np.random.default_rng(21)
+    c = rng.uniform(0.85, 1.15, size=g.vol_shape)
+    A = dense(lambda f: oracle.forward(g, c, f), g.vol_shape)
+    Lam = dense(lambda d: oracle.ramp(g, d), g.data_shape)
+    H = A.T @ Lam @ A
+    h_true = np.abs(rng.normal(size=g.vol_shape))
+    G = (A @ h_true.ravel()).reshape(g.data_shape) + 0.05 * rng.normal(size=g.data_shape)
+    return dict(g=g, c=c, A=A, Lam=Lam, H=0.5 * (H + H.T), G=G)
+
+
+def test_dense_adjoint_equals_transpose(oracle, problem):
+    g, c, A = problem["g"], problem["c"], problem["A"]
+    AT = dense(lambda d: oracle.adjoint(g, c, d), g.data_shape)
+    assert np.max(np.abs(AT - A.T)) <= 1e-12 * np.max(np.abs(A))
+
+
+def test_power_iteration_converges_to_top_eigenvalue(oracle, problem):
+    g, c, H = problem["g"], problem["c"], problem["H"]
+    lam_max = np.linalg.eigvalsh(H).max()
+    L20, hist = oracle.power(g, c, 20)
+    assert np.all(np.diff(hist) >= -1e-12 * lam_max)     # Rayleigh-type estimate increases
+    assert L20 <= lam_max * (1 + 1e-12)
+    L_long, _ = oracle.power(g, c, 1500)
+    assert L_long == pytest.approx(lam_max, rel=1e-10)
+
+
+def test_fb_without_constraint_converges_to_normal_equations(oracle, problem):
+    g, c, H, A, Lam, G = (problem[k] for k in ("g", "c", "H", "A", "Lam", "G"))
+    lam_max = np.linalg.eigvalsh(H).max()
+    lam = 0.3 * lam_max
+    s = 1.0 / lam_max
+    ref = np.linalg.solve(H + lam * np.eye(H.shape[0]), A.T @ Lam @ G.ravel())
+    h, obj, s_used = oracle.fb(g, c, G, lam, step=s, n_iter=400, flags=oracle.PRECOND)
+    assert s_used == s
+    assert rel_l2(h.ravel(), ref) <= 1e-10
+    assert np.all(np.diff(obj) <= 1e-12 * abs(obj[0]))   # FB with s <= 1/L decreases the objective
+
+
+def test_fb_with_positivity_satisfies_kkt(oracle, problem):
+    g, c, H, A, Lam, G = (problem[k] for k in ("g", "c", "H", "A", "Lam", "G"))
+    lam_max = np.linalg.eigvalsh(H).max()
+    lam = 0.3 * lam_max
+    h, obj, _ = oracle.fb(g, c, G, lam, step=1.0 / lam_max, n_iter=600,
+                          flags=oracle.PRECOND | oracle.POSITIVITY)
+    h = h.ravel()
+    grad = H @ h - A.T @ Lam @ G.ravel() + lam * h
+    scale = np.max(np.abs(A.T @ Lam @ G.ravel()))
+    assert h.min() >= 0
+    pos = h > 1e-12 * np.max(h)
+    assert np.max(np.abs(grad[pos])) <= 1e-8 * scale
+    assert grad[~pos].min() >= -1e-8 * scale
+    assert (~pos).sum() > 0                               # the constraint is active somewhere
+
+
+def test_fb_without_precond_uses_plain_least_squares(oracle, problem):
+    g, c, A, G = (problem[k] for k in ("g", "c", "A", "G"))
+    H = A.T @ A
+    lam_max = np.linalg.eigvalsh(H).max()
+    lam = 0.3 * lam_max
+    ref = np.linalg.solve(H + lam * np.eye(H.shape[0]), A.T @ G.ravel())
+    h, _, _ = oracle.fb(g, c, G, lam, step=1.0 / lam_max, n_iter=400, flags=0)
+    assert rel_l2(h.ravel(), ref) <= 1e-10
+
+
+def test_fb_objective_at_exact_solution(oracle, problem):
+    # with noise-free data and h0 = h_true the residual vanishes: J_0 = lambda/2 ||h_true||^2
+    g, c, A = problem["g"], problem["c"], problem["A"]
+    h_true = synth.random_field(g.vol_shape, 22)
+    G = (A @ h_true.ravel()).reshape(g.data_shape)
+    _, obj, _ = oracle.fb(g, c, G, 0.7, step=1e-3, n_iter=1, flags=oracle.PRECOND, h0=h_true)
+    assert obj[0] == pytest.approx(0.35 * np.sum(h_true ** 2), rel=1e-10)
+
+
+def test_fb_detector_mask_equals_masked_least_squares(oracle, problem):
+    g, c, A, Lam, G = (problem[k] for k in ("g", "c", "A", "Lam", "G"))
+    mask = np.ones(g.data_shape, dtype=np.uint8)
+    mask[:, :, 3:5] = 0                                  # a missing central stripe of bins
+    M = np.diag(mask.ravel().astype(np.float64))
+    H = A.T @ M @ Lam @ M @ A
+    H = 0.5 * (H + H.T)
+    lam_max = np.linalg.eigvalsh(H).max()
+    lam = 0.3 * lam_max
+    ref = np.linalg.solve(H + lam * np.eye(H.shape[0]), A.T @ M @ Lam @ M @ G.ravel())
+    h, _, _ = oracle.fb(g, c, G, lam, step=1.0 / lam_max, n_iter=400, flags=oracle.PRECOND, det_mask=mask)
+    assert rel_l2(h.ravel(), ref) <= 1e-10
+    L, _ = oracle.power(g, c, 1500, det_mask=mask)
+    assert L == pytest.approx(lam_max, rel=1e-8)
+
+
+def test_fb_support_mask_zeroes_outside(oracle, problem):
+    g, c, G = problem["g"], problem["c"], problem["G"]
+    sup = np.zeros(g.vol_shape, dtype=np.uint8)
+    sup[1:3, 2:5, 1:5] = 1
+    h, _, _ = oracle.fb(g, c, G, 1e-3, n_iter=3, support=sup)
+    assert np.all(h[sup == 0] == 0.0)
+    assert np.any(h[sup == 1] != 0.0)
+
+
+# ---------------------------------------------------------------- gradient regulariser
+def test_neg_lap7_dirichlet_spectrum(oracle):
+    g = oracle.Geometry(nx=5, ny=4, nz=3, dx=0.2, T=0.1, angles=synth.uniform_angles(2))
+    M = dense(lambda f: oracle.neg_lap7(g, f), g.vol_shape)
+    assert np.max(np.abs(M - M.T)) == 0.0
+    ev = np.sort(np.linalg.eigvalsh(M))
+    one = lambda n: (2 - 2 * np.cos(np.arange(1, n + 1) * math.pi / (n + 1))) / g.dx ** 2
+    ref = np.sort((one(5)[None, None, :] + one(4)[None, :, None] + one(3)[:, None, None]).ravel())
+    assert np.max(np.abs(ev - ref)) <= 1e-11 * ref.max()
+
+
+def test_prox_grad_solves_its_equation(oracle):
+    g = oracle.Geometry(nx=9, ny=8, nz=7, dx=0.1, T=0.1, angles=synth.uniform_angles(2))
+    f = synth.random_field(g.vol_shape, 23)
+    tau = 0.01
+    h = oracle.prox_grad(g, tau, f)
+    res = h + tau * oracle.neg_lap7(g, h) - f
+    assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(f)
+    # prox minimises 1/2||h - f||^2 + tau/2 ||D h||^2: compare against random perturbations
+    def F(u):
+        return 0.5 * np.sum((u - f) ** 2) + 0.5 * tau * np.sum(u * oracle.neg_lap7(g, u))
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        assert F(h) < F(h + 1e-3 * rng.normal(size=h.shape))
+
+
+def test_fb_gradient_regulariser_converges_to_normal_equations(oracle, problem):
+    g, c, H, A, Lam, G = (problem[k] for k in ("g", "c", "H", "A", "Lam", "G"))
+    D = dense(lambda f: oracle.neg_lap7(g, f), g.vol_shape)
+    lam_max = np.linalg.eigvalsh(H).max()
+    lam = 0.05 * lam_max * g.dx ** 2
+    ref = np.linalg.solve(H + lam * D, A.T @ Lam @ G.ravel())
+    h, _, _ = oracle.fb(g, c, G, lam, step=1.0 / lam_max, n_iter=2000, flags=oracle.PRECOND | oracle.REG_GRAD)
+    assert rel_l2(h.ravel(), ref) <= 1e-8
