@@ -1,0 +1,191 @@
+"""Benchmark of the one-step full-field PAT hot path on one MI355X.
+
+A step is one iteration of Algorithm 8 (forward wave solve, projection,
+residual + ramp filter + FP64 objective, backprojection, adjoint wave solve,
+prox update) on the 256^3 workload: 256 angles, T = 0.5, FP32 fields with
+FP64 reductions, seeded synthetic phantom (balls + vessel-like tubes) and
+sound speed (5 Gaussian bumps clamped to [0.8, 1.2]).  The step size comes
+from a 20-step power iteration done before the timed region.
+
+Prints one JSON line.  See --help.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "wave-op Gpt-updates/s; FB iter/s at 256³ FP32 vs FP64; recon p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--recipe", default="c256", help="synthetic workload recipe (c128, c256, c384)")
+    ap.add_argument("--dtype", default="float32", choices=["float32", "float64"])
+    ap.add_argument("--fp64-compare", type=int, default=1, help="also time FB iterations in FP64 (1/0)")
+    ap.add_argument("--cpu-baseline", type=int, default=1, help="time the oracle on a bounded sample (1/0)")
+    ap.add_argument("--naive-stencil", action="store_true")
+    ap.add_argument("--seed", type=int, default=3001)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(args, torch, ff, synth, dtype):
+    case = synth.make_case(args.recipe, args.seed)
+    dev = torch.device("cuda:0")
+    c = torch.from_numpy(case.c).to(dev, dtype)
+    plan = ff.Plan(c, case.dx, case.T, case.angles, naive_stencil=args.naive_stencil)
+    h_true = torch.from_numpy(case.h_true).to(dev, dtype)
+    clean = plan.forward(h_true)
+    sigma = case.noise_level * float(clean.double().mean())
+    G = clean + sigma * torch.from_numpy(case.noise).to(dev, dtype)
+    torch.cuda.synchronize()
+    return case, plan, G
+
+
+def time_fb(torch, plan, G, lam, steps, warmup):
+    h = torch.zeros(plan.shape, dtype=plan.dtype, device=G.device)
+    t0 = time.perf_counter()
+    res = plan.reconstruct(G, lam, 0, step=0.0, n_power=20, h0=h)        # power iteration -> step
+    torch.cuda.synchronize()
+    t_power = time.perf_counter() - t0
+    if warmup:
+        plan.reconstruct(G, lam, warmup, h0=h, use_plan_step=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = plan.reconstruct(G, lam, steps, h0=h, use_plan_step=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return t, t_power, out
+
+
+def time_wave(torch, plan, reps=3):
+    """Average duration of one leapfrog-step launch, from HIP events around
+    back-to-back W_T applications on the stream the kernels run on."""
+    x = torch.randn(plan.shape, dtype=plan.dtype, device="cuda")
+    y = torch.empty_like(x)
+    plan.wave(x, out=y)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.wave(x, out=y, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    return ms / 1e3 / (reps * plan.nt)
+
+
+def cpu_baseline(case, plan_nt):
+    """Oracle (FP64, OpenMP) on a bounded sample of the same workload, scaled to FB iter/s:
+    8 leapfrog steps, then X and X^T over 8 of the angles, then Lambda on those rows."""
+    import numpy as np
+    import oracle
+    n = case.n
+    sub = case.angles[:: max(1, len(case.angles) // 8)][:8]
+    T8 = 8 * case.T / plan_nt                       # exactly 8 steps at the workload's dt
+    g8 = oracle.Geometry(nx=n, ny=n, nz=n, dx=case.dx, T=T8, angles=sub)
+    t0 = time.perf_counter(); oracle.wave(g8, case.c, case.h_true); t_wave = time.perf_counter() - t0
+    t0 = time.perf_counter(); d = oracle.project(g8, case.h_true); t_proj = time.perf_counter() - t0
+    t0 = time.perf_counter(); oracle.backproject(g8, d); t_bp = time.perf_counter() - t0
+    t0 = time.perf_counter(); oracle.ramp(g8, d); t_ramp = time.perf_counter() - t0
+    ratio = len(case.angles) / len(sub)
+    t_iter = 2 * plan_nt * t_wave / 8 + ratio * (t_proj + t_bp + t_ramp)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / t_iter, "unit": "FB iter/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{n}^3 FP64: 8 of {plan_nt} leapfrog steps ({t_wave:.1f}s), X/X^T/Lambda on "
+                       f"{len(sub)} of {len(case.angles)} angles ({t_proj + t_bp + t_ramp:.1f}s); "
+                       f"scaled to one FB iteration (2 wave solves + X + X^T + Lambda)")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the sharded design is described in DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    import paper_1901_06503_amd as ff
+    import synth
+
+    dtype = torch.float32 if args.dtype == "float32" else torch.float64
+    log(f"inputs {args.recipe} {args.dtype}")
+    case, plan, G = make_inputs(args, torch, ff, synth, dtype)
+    N, nang = case.n, len(case.angles)
+    log(f"N={N} angles={nang} nt={plan.nt} dt={plan.dt:.6g}")
+    t, t_power, out = time_fb(torch, plan, G, case.lam, args.steps, args.warmup)
+    ms = 1e3 * t / args.steps
+    log(f"FB {args.steps} iterations: {t:.3f}s ({ms:.2f} ms/iter), power iteration {t_power:.3f}s")
+
+    t_launch = time_wave(torch, plan)
+    esz = 4 if dtype == torch.float32 else 8
+    bytes_per_launch = 4 * esz * N ** 3              # read p(k), p(k-1), k'; write p(k+1)
+    achieved = bytes_per_launch / t_launch / 1e9
+    gpt = N ** 3 / t_launch / 1e9
+    log(f"wave step {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s, {gpt:.1f} Gpt-updates/s")
+
+    fp64 = None
+    if args.fp64_compare and dtype == torch.float32:
+        plan.close()
+        del G
+        torch.cuda.empty_cache()
+        case64, plan64, G64 = make_inputs(args, torch, ff, synth, torch.float64)
+        k64 = max(2, args.steps // 4)
+        t64, _, _ = time_fb(torch, plan64, G64, case.lam, k64, 1)
+        fp64 = {"fb_iter_per_s": k64 / t64, "ms_per_iter": 1e3 * t64 / k64, "steps": k64,
+                "wave_gpt_updates_per_s": N ** 3 / time_wave(torch, plan64) / 1e9}
+        plan64.close()
+        log(f"FP64: {fp64}")
+
+    cpu = None
+    if args.cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        cpu = cpu_baseline(case, plan.nt)
+        log(f"cpu baseline {cpu}")
+
+    line = {
+        "metric": METRIC,
+        "value": args.steps / t,
+        "unit": "FB iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if dtype == torch.float32 else "f64",
+        "data": "synthetic (seeded phantom: balls + tubes, smoothed; c: Gaussian bumps)",
+        "config": {"workload": f"{N}^3 grid, {nang} angles, T={case.T}, Algorithm 8 with positivity + "
+                               f"lambda={case.lam} l2 prox, FP32 fields + FP64 reductions",
+                   "grid": N, "angles": nang, "nt": plan.nt, "power_steps": 20,
+                   "stencil": "naive" if args.naive_stencil else "blocked"},
+        "wave_gpt_updates_per_s": gpt,
+        "power_iteration_s": t_power,
+        "fp64": fp64,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "wave_step", "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": t_launch * 1e6},
+        "cpu_baseline": cpu,
+        "objective_last": float(out.objective[-1]) if len(out.objective) else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

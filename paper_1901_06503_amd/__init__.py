@@ -1,0 +1,213 @@
+"""ffpat: one-step full-field photoacoustic reconstruction on AMD MI355X.
+
+Python binding of libffpat (C ABI in include/ffpat.h).  Tensors are torch
+device tensors used as plain device memory; every operator runs in the
+library's HIP kernels on the caller's current stream.
+
+Method: Haltmeier, Zangerl, Nuster, Nguyen, "Photoacoustic image
+reconstruction from full field data in heterogeneous media" (2019):
+forward operator A = X W_T (Problem 1, eq. fm), its transpose, the ramp
+preconditioner (Sec. 3.1) and Algorithm 8 (Sec. 3.2).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import FfpatError, POSITIVITY, PRECOND, REG_GRAD, USE_PLAN_STEP
+
+__all__ = ["Plan", "FfpatError", "ReconResult", "workspace_bytes", "version", "POSITIVITY", "PRECOND",
+           "REG_GRAD", "USE_PLAN_STEP"]
+
+
+def version() -> str:
+    return _lib.load().ffpat_version().decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _make_geom(nx, ny, nz, dx, T, angles, ns, ds, cfl, ndim, dtype_code, flags):
+    ang = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))
+    g = _lib.Geom(int(nx), int(ny), int(nz), int(ndim), float(dx), float(T), float(cfl), int(ang.size),
+                  ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(ns), float(ds), int(dtype_code),
+                  int(flags))
+    return g, ang
+
+
+def workspace_bytes(shape, dx, T, angles, ns=0, ds=0.0, cfl=0.3, ndim=3, dtype="float32") -> int:
+    """Device bytes a plan of this geometry allocates (admission by HBM footprint)."""
+    nz, ny, nx = shape
+    code = _lib.F64 if str(dtype).endswith("64") else _lib.F32
+    g, _keep = _make_geom(nx, ny, nz, dx, T, angles, ns, ds, cfl, ndim, code, 0)
+    out = ctypes.c_size_t()
+    _lib.check(_lib.load().ffpat_workspace_bytes(ctypes.byref(g), ctypes.byref(out)))
+    return int(out.value)
+
+
+@dataclass
+class ReconResult:
+    h: "object"            # torch tensor, h_K
+    objective: np.ndarray  # J_0 .. J_{K-1} (FP64)
+    step: float            # step size s used
+
+
+class Plan:
+    """Geometry + sound speed resident on one GPU, with the operators of the path.
+
+    c: sound speed c(x) > 0 as a contiguous [nz][ny][nx] device tensor; its
+    dtype (float32 or float64) sets the precision of every field.
+    """
+
+    def __init__(self, c, dx, T, angles, ns=0, ds=0.0, cfl=0.3, ndim=3, naive_stencil=False, stream=None):
+        torch = _torch()
+        if not (isinstance(c, torch.Tensor) and c.is_cuda):
+            raise TypeError("c must be a device tensor")
+        if c.dtype not in (torch.float32, torch.float64):
+            raise TypeError("c must be float32 or float64")
+        if c.dim() != 3:
+            raise ValueError("c must be [nz][ny][nx]")
+        c = c.contiguous()
+        self.dtype = c.dtype
+        self.device = c.device
+        nz, ny, nx = c.shape
+        code = _lib.F64 if c.dtype == torch.float64 else _lib.F32
+        flags = _lib.PLAN_NAIVE_STENCIL if naive_stencil else 0
+        self._lib = _lib.load()
+        g, self._angles = _make_geom(nx, ny, nz, dx, T, angles, ns, ds, cfl, ndim, code, flags)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(c.device):
+            _lib.check(self._lib.ffpat_plan_create(ctypes.byref(g), ctypes.c_void_p(c.data_ptr()),
+                                                   ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(handle)))
+        self._h = handle
+        self.shape = (nz, ny, nx)
+        self.n_angles = int(self._angles.size)
+        self.ns = int(ns) if ns else int(nx)
+        self.data_shape = (self.n_angles, nz, self.ns)
+        self.dx, self.T = float(dx), float(T)
+        nt = ctypes.c_int32(); dt = ctypes.c_double(); cm = ctypes.c_double()
+        _lib.check(self._lib.ffpat_plan_info(self._h, ctypes.byref(nt), ctypes.byref(dt), ctypes.byref(cm)))
+        self.nt, self.dt, self.cmax = nt.value, dt.value, cm.value
+
+    # ------------------------------------------------------------------ helpers
+    def _check_tensor(self, t, shape, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a device tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} is on {t.device}, plan on {self.device}")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} has dtype {t.dtype}, plan uses {self.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def _empty(self, shape):
+        return _torch().empty(shape, dtype=self.dtype, device=self.device)
+
+    def _call(self, fn, src, src_shape, dst, dst_shape, stream, name):
+        self._check_tensor(src, src_shape, name)
+        if dst is None:
+            dst = self._empty(dst_shape)
+        self._check_tensor(dst, dst_shape, "out")
+        _lib.check(fn(self._h, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                      ctypes.c_void_p(_stream_handle(stream))))
+        return dst
+
+    # ------------------------------------------------------------------ operators
+    def forward(self, h, out=None, stream=None):
+        """g = X W_T h."""
+        return self._call(self._lib.ffpat_forward, h, self.shape, out, self.data_shape, stream, "h")
+
+    def adjoint(self, g, out=None, stream=None):
+        """h = W_T^T X^T g."""
+        return self._call(self._lib.ffpat_adjoint, g, self.data_shape, out, self.shape, stream, "g")
+
+    def wave(self, h, out=None, stream=None):
+        """p = W_T h."""
+        return self._call(self._lib.ffpat_wave, h, self.shape, out, self.shape, stream, "h")
+
+    def wave_adjoint(self, g, out=None, stream=None):
+        """q = W_T^T g."""
+        return self._call(self._lib.ffpat_wave_adjoint, g, self.shape, out, self.shape, stream, "g")
+
+    def project(self, v, out=None, stream=None):
+        """g = X v."""
+        return self._call(self._lib.ffpat_project, v, self.shape, out, self.data_shape, stream, "v")
+
+    def backproject(self, g, out=None, stream=None):
+        """v = X^T g."""
+        return self._call(self._lib.ffpat_backproject, g, self.data_shape, out, self.shape, stream, "g")
+
+    def ramp(self, r, out=None, stream=None):
+        """y = Lambda r."""
+        return self._call(self._lib.ffpat_ramp, r, self.data_shape, out, self.data_shape, stream, "r")
+
+    def reconstruct(self, G, lam, n_iter, step=0.0, n_power=20, positivity=True, precond=True,
+                    support=None, det_mask=None, h0=None, use_plan_step=False, stream=None,
+                    want_objective=True) -> ReconResult:
+        """Algorithm 8: K = n_iter forward-backward iterations from h0 (zeros by default)."""
+        torch = _torch()
+        self._check_tensor(G, self.data_shape, "G")
+        h = torch.zeros(self.shape, dtype=self.dtype, device=self.device) if h0 is None else h0
+        self._check_tensor(h, self.shape, "h0")
+        flags = (POSITIVITY if positivity else 0) | (PRECOND if precond else 0)
+        if use_plan_step:
+            flags |= USE_PLAN_STEP
+        sup = 0
+        if support is not None:
+            self._check_mask(support, self.shape, "support")
+            sup = support.data_ptr()
+        msk = 0
+        if det_mask is not None:
+            self._check_mask(det_mask, self.data_shape, "det_mask")
+            msk = det_mask.data_ptr()
+        obj = np.zeros(max(int(n_iter), 1), dtype=np.float64)
+        prm = _lib.FbParams(float(lam), float(step), int(n_iter), int(n_power), flags,
+                            ctypes.c_void_p(sup or None), ctypes.c_void_p(msk or None),
+                            obj.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_objective else None)
+        s = ctypes.c_double()
+        _lib.check(self._lib.ffpat_reconstruct(self._h, ctypes.c_void_p(G.data_ptr()), ctypes.byref(prm),
+                                               ctypes.c_void_p(h.data_ptr()), ctypes.byref(s),
+                                               ctypes.c_void_p(_stream_handle(stream))))
+        return ReconResult(h=h, objective=obj[:int(n_iter)], step=s.value)
+
+    def _check_mask(self, m, shape, name):
+        torch = _torch()
+        if not isinstance(m, torch.Tensor) or not m.is_cuda or m.dtype != torch.uint8:
+            raise TypeError(f"{name} must be a uint8 device tensor")
+        if tuple(m.shape) != tuple(shape) or not m.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {tuple(shape)}")
+        if m.device != self.device:
+            raise ValueError(f"{name} is on {m.device}, plan on {self.device}")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(self._lib.ffpat_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

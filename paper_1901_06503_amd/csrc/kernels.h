@@ -1,0 +1,123 @@
+// Kernel launchers of libffpat (gfx950).  Device code lives in kernels_*.hip;
+// the plan and the C ABI (plan.hip) call only these launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace ffpat {
+
+// Grid extents and strides shared by the volume kernels.
+struct Dims {
+  int nx, ny, nz;
+  int ndim;  // 3, or 2 for the z-invariant mode (no z coupling in the Laplacian)
+  size_t nvox() const { return (size_t)nx * ny * nz; }
+};
+
+// Per-angle parameters, computed on the host in double precision.
+//
+// Projector (Joseph form of the footprint): the ray of bin j crosses marched
+// line r (a row y_r if !major_x, a column x_r if major_x) at index position
+//     u = u0 + j * uj + r * ur
+// along the other axis; the ray sum is w * sum_r lerp(line_r, u), w = dx / m.
+//
+// Backprojector: voxel (i, k) projects to bin position t = b0 + i * bi + k * bk;
+// bin j receives weight w * max(0, 1 - |j - t| * inv_hw), hw = m dx / ds bins.
+struct AngleParams {
+  double u0, uj, ur;
+  double b0, bi, bk;
+  double hw, inv_hw;
+  double w;
+  int major_x;
+  int pad_;
+};
+
+enum StepMode : int {
+  STEP_FIRST = 0,       // out = p + 1/2 k' S(p)
+  STEP_LEAP = 1,        // out = 2 p - prev + k' S(p)      (out may alias prev)
+  STEP_FIRST_DIV = 2,   // out = (p + 1/2 k' S(p)) / k'
+  STEP_LEAP_DIV = 3     // out = (2 p - prev + k' S(p)) / k'
+};
+
+enum StencilKind : int { STENCIL_BLOCKED = 0, STENCIL_NAIVE = 1 };
+
+// One leapfrog step; k' = (c dt)^2 / (12 dx^2); S = integer 13-point (9-point
+// in 2D) fourth-order stencil with zero values outside the grid.
+template <typename T>
+hipError_t launch_wave_step(StencilKind kind, StepMode mode, const Dims &d, const T *p, const T *prev,
+                            T *out, const T *kap, hipStream_t s);
+
+// k' = (c dt)^2 / (12 dx^2) from c, and c range / finiteness into stats[0..2]
+// (min, max, count of non-finite or non-positive values) via block partials.
+template <typename T>
+hipError_t launch_make_kappa(const Dims &d, const T *c, double dt, double dx, T *kap, hipStream_t s);
+template <typename T>
+hipError_t launch_c_stats(const Dims &d, const T *c, double *partials, int nblocks, double *stats, hipStream_t s);
+
+// g[a][z][j] = X vol (Joseph ray march).
+template <typename T>
+hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *vol, T *g,
+                          hipStream_t s);
+
+// vol = X^T g, optionally multiplied point-wise by kap (when kap != nullptr).
+template <typename T>
+hipError_t launch_backproject(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *g, T *vol,
+                              const T *kap, hipStream_t s);
+
+// r = mask * (g - G) (G may be null, mask may be null); y = mask * Lambda r (or
+// y = r when taps == nullptr).  y may alias g.  row_partials[row] = sum_j r_j y_j
+// when non-null.
+template <typename T>
+hipError_t launch_residual_ramp(int rows, int ns, const T *g, const T *G, const uint8_t *mask, const T *taps,
+                                T *y, double *row_partials, hipStream_t s);
+
+// Reductions and element-wise updates (FP64 partials, fixed order).
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceThreads = 256;
+
+template <typename T>
+hipError_t launch_sumsq(const T *x, size_t n, double *partials, hipStream_t s);  // kReduceBlocks partials
+template <typename T>
+hipError_t launch_dot(const T *x, const T *y, size_t n, double *partials, hipStream_t s);
+
+// out[0] = scale * sum(partials[0..n)) (single block, fixed order).
+hipError_t launch_reduce_to(const double *partials, int n, double scale, double *out, hipStream_t s);
+
+// objective[k] = 0.5 * data + lambda * 0.5 * reg (values read on the device);
+// flags nonfinite in scalars.
+hipError_t launch_objective(const double *data_sum, const double *reg_sum, double lambda, double *obj_k,
+                            double *nonfinite_flag, hipStream_t s);
+
+// L = sqrt(sumsq); step = 1 / L.
+hipError_t launch_power_finish(const double *sumsq, double *L, double *step, double *nonfinite_flag,
+                               hipStream_t s);
+
+template <typename T>
+hipError_t launch_fill(T *x, size_t n, double value, hipStream_t s);
+// y = x / sqrt(*sumsq)
+template <typename T>
+hipError_t launch_normalize(const T *x, T *y, size_t n, const double *sumsq, hipStream_t s);
+
+// h <- prox_{s lambda R}(h - s grad) for R = 1/2||h||^2 (+ positivity), support mask.
+template <typename T>
+hipError_t launch_prox_l2(T *h, const T *grad, size_t n, const double *step, double lambda, int positivity,
+                          const uint8_t *support, hipStream_t s);
+
+// f = h - s * grad (gradient regulariser path; prox applied afterwards).
+template <typename T>
+hipError_t launch_grad_step(const T *h, const T *grad, T *f, size_t n, const double *step, hipStream_t s);
+
+// y = x.
+template <typename T>
+hipError_t launch_copy(const T *x, T *y, size_t n, hipStream_t s);
+
+}  // namespace ffpat
+
+namespace ffpat {
+// y = x * k point-wise (k = k' for the conjugated transpose of W).
+template <typename T>
+hipError_t launch_mul(const T *x, const T *k, T *y, size_t n, hipStream_t s);
+// dst[0] = v (a kernel, so that the write can sit inside a captured graph).
+hipError_t launch_set(double *dst, double v, hipStream_t s);
+}  // namespace ffpat

@@ -1,0 +1,364 @@
+// Leapfrog time stepping of the variable-speed wave equation (Sec. 2.1,
+// eq. wave1/wave2), fourth-order in space, on gfx950.
+//
+//   S(p)   = sum over axes of (-p[-2] + 16 p[-1] - 30 p[0] + 16 p[+1] - p[+2]),
+//            zero outside the grid (integer coefficients; 1/(12 dx^2) and
+//            (c dt)^2 are folded into k' = (c dt)^2 / (12 dx^2)).
+//   first  p1      = p0 + 1/2 k' S(p0)         (zero initial velocity)
+//   leap   p(k+1)  = 2 p(k) - p(k-1) + k' S(p(k))
+//
+// The step is HBM-bound (16 B per point update in FP32: read p(k), p(k-1),
+// k', write p(k+1)).  Two kernels:
+//   * wave_step_naive: one thread per point, 13 global loads (cache-reliant).
+//   * wave_step_blocked: 2.5D blocking.  A work-group owns a TX x TY tile of
+//     x-y columns and marches along z; the plane under update sits in LDS
+//     with a 2-point halo, the four z-neighbours of each column stay in
+//     registers, so every p(k) value is fetched from HBM about once.
+#include "kernels.h"
+
+#include <cfloat>
+#include <cstdlib>
+
+namespace ffpat {
+
+template <typename T, int NDIM, int MODE>
+__global__ void __launch_bounds__(256)
+wave_step_naive(const T *__restrict__ p, const T *prev, T *out, const T *__restrict__ kap, int nx, int ny, int nz)
+{
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= nx || y >= ny) return;
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  const size_t idx = (size_t)z * sz + (size_t)y * sy + x;
+
+  const T c0 = p[idx];
+  T s1 = T(0), s2 = T(0);
+  if (x >= 1) s1 += p[idx - 1];
+  if (x + 1 < nx) s1 += p[idx + 1];
+  if (x >= 2) s2 += p[idx - 2];
+  if (x + 2 < nx) s2 += p[idx + 2];
+  if (y >= 1) s1 += p[idx - sy];
+  if (y + 1 < ny) s1 += p[idx + sy];
+  if (y >= 2) s2 += p[idx - 2 * sy];
+  if (y + 2 < ny) s2 += p[idx + 2 * sy];
+  if (NDIM == 3) {
+    if (z >= 1) s1 += p[idx - sz];
+    if (z + 1 < nz) s1 += p[idx + sz];
+    if (z >= 2) s2 += p[idx - 2 * sz];
+    if (z + 2 < nz) s2 += p[idx + 2 * sz];
+  }
+  const T S = T(16) * s1 - s2 - T(NDIM == 3 ? 90 : 60) * c0;
+  const T k = kap[idx];
+  T v;
+  if (MODE == STEP_FIRST || MODE == STEP_FIRST_DIV) v = c0 + T(0.5) * k * S;
+  else v = T(2) * c0 - prev[idx] + k * S;
+  if (MODE == STEP_FIRST_DIV || MODE == STEP_LEAP_DIV) v = v / k;
+  out[idx] = v;
+}
+
+template <typename T, int NDIM>
+static hipError_t naive_dispatch(StepMode mode, const Dims &d, const T *p, const T *prev, T *out, const T *kap,
+                                 hipStream_t s)
+{
+  dim3 block(64, 4, 1);
+  dim3 grid((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
+  switch (mode) {
+    case STEP_FIRST: wave_step_naive<T, NDIM, STEP_FIRST><<<grid, block, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz); break;
+    case STEP_LEAP: wave_step_naive<T, NDIM, STEP_LEAP><<<grid, block, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz); break;
+    case STEP_FIRST_DIV: wave_step_naive<T, NDIM, STEP_FIRST_DIV><<<grid, block, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz); break;
+    case STEP_LEAP_DIV: wave_step_naive<T, NDIM, STEP_LEAP_DIV><<<grid, block, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz); break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 2.5D-blocked step.  Work-group = 256 threads = 4 wavefronts; tile = 64 x BY
+// columns (BY = 4 RY), each wavefront owns whole 64-wide rows (coalesced).
+// The group marches z over [zbeg, zbeg + zchunk): plane z of p(k) sits in LDS
+// with a 2-point x/y halo (double-buffered, one barrier per plane); the
+// values at z-2..z+2 of the thread's RY columns stay in registers; p(k) at
+// z+3, p(k-1) and k' are fetched ahead of use.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ld3(const T *__restrict__ p, int x, int y, int z, int nx, int ny, int nz)
+{
+  return (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) ? p[((size_t)z * ny + y) * nx + x] : T(0);
+}
+
+template <typename T, int NDIM, int MODE, int RY>
+__global__ void __launch_bounds__(256)
+wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__restrict__ kap, int nx, int ny, int nz,
+                  int zchunk, int tiles_x, int tiles_y, int n_tiles)
+{
+  constexpr int BX = 64, TYN = 4, BY = TYN * RY;
+  constexpr int LW = BX + 4, LH = BY + 4;
+  __shared__ T lds[2][LH * LW];
+
+  // XCD-aware tile order: consecutive work-groups are dealt round-robin to
+  // the 8 XCDs; give each XCD a contiguous range of tiles (z-chunk fastest)
+  // so that neighbouring tiles share that XCD's L2.
+  const int b = blockIdx.x;
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int t = (b % 8) * per_xcd + b / 8;
+  if (t >= n_tiles) return;                      // whole group exits together
+  const int n_zc = (nz + zchunk - 1) / zchunk;
+  const int zc = t % n_zc;
+  const int txy = t / n_zc;
+  const int bxi = txy % tiles_x, byi = txy / tiles_x;
+  (void)tiles_y;
+
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int x0 = bxi * BX, y0 = byi * BY;
+  const int x = x0 + tx;
+  const int zbeg = zc * zchunk;
+  const int zend = min(nz, zbeg + zchunk);
+  const size_t plane = (size_t)nx * ny;
+
+  T w[RY][5];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int y = y0 + ty + TYN * r;
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+      w[r][q] = (NDIM == 3 || q == 2) ? ld3(p, x, y, zbeg - 2 + q, nx, ny, nz) : T(0);
+  }
+
+  int buf = 0;
+  for (int z = zbeg; z < zend; ++z, buf ^= 1) {
+    T *L = lds[buf];
+    // interior of plane z from registers
+#pragma unroll
+    for (int r = 0; r < RY; ++r) L[(ty + TYN * r + 2) * LW + tx + 2] = w[r][2];
+    // halo of plane z: rows y0-2, y0-1, y0+BY, y0+BY+1 (full width), then
+    // columns x0-2, x0-1, x0+BX, x0+BX+1 of the interior rows
+    for (int e = threadIdx.x; e < 4 * LW + 4 * BY; e += 256) {
+      int lr, lc;
+      if (e < 4 * LW) {
+        const int hr = e / LW;
+        lr = hr < 2 ? hr : BY + hr;
+        lc = e - hr * LW;
+      } else {
+        const int e2 = e - 4 * LW;
+        const int hc = e2 / BY;
+        lc = hc < 2 ? hc : BX + hc;
+        lr = 2 + (e2 - hc * BY);
+      }
+      L[lr * LW + lc] = ld3(p, x0 + lc - 2, y0 + lr - 2, z, nx, ny, nz);
+    }
+    // values needed later in this step and by the next plane
+    T nxt[RY], pv[RY], kv[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int y = y0 + ty + TYN * r;
+      const bool in = x < nx && y < ny;
+      const size_t idx = (size_t)z * plane + (size_t)y * nx + x;
+      // 3D: plane z+3 enters the window; 2D: the next centre plane z+1
+      nxt[r] = ld3(p, x, y, NDIM == 3 ? z + 3 : z + 1, nx, ny, nz);
+      kv[r] = in ? kap[idx] : T(1);
+      pv[r] = (in && (MODE == STEP_LEAP || MODE == STEP_LEAP_DIV)) ? prev[idx] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int y = y0 + ty + TYN * r;
+      const T *c = &L[(ty + TYN * r + 2) * LW + tx + 2];
+      T s1 = (c[-1] + c[1]) + (c[-LW] + c[LW]);
+      T s2 = (c[-2] + c[2]) + (c[-2 * LW] + c[2 * LW]);
+      if (NDIM == 3) {
+        s1 += w[r][1] + w[r][3];
+        s2 += w[r][0] + w[r][4];
+      }
+      const T c0 = w[r][2];
+      const T S = T(16) * s1 - s2 - T(NDIM == 3 ? 90 : 60) * c0;
+      T v;
+      if (MODE == STEP_FIRST || MODE == STEP_FIRST_DIV) v = c0 + T(0.5) * kv[r] * S;
+      else v = T(2) * c0 - pv[r] + kv[r] * S;
+      if (MODE == STEP_FIRST_DIV || MODE == STEP_LEAP_DIV) v = v / kv[r];
+      if (x < nx && y < ny) out[(size_t)z * plane + (size_t)y * nx + x] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      if (NDIM == 3) {
+        w[r][0] = w[r][1];
+        w[r][1] = w[r][2];
+        w[r][2] = w[r][3];
+        w[r][3] = w[r][4];
+        w[r][4] = nxt[r];
+      } else {
+        w[r][2] = nxt[r];
+      }
+    }
+  }
+}
+
+// Tunables of the blocked kernel (set once per process from the environment
+// for sweeps; the defaults are the measured best on MI355X).
+struct BlockedConfig {
+  int ry = 4;        // rows per thread: tile height 4 * ry
+  int zchunk = 0;    // planes per work-group; 0 = choose from the grid size
+};
+
+static BlockedConfig blocked_config()
+{
+  static BlockedConfig cfg = [] {
+    BlockedConfig c;
+    if (const char *e = getenv("FFPAT_STENCIL_RY")) c.ry = atoi(e);
+    if (const char *e = getenv("FFPAT_STENCIL_ZCHUNK")) c.zchunk = atoi(e);
+    if (c.ry != 2 && c.ry != 4 && c.ry != 8) c.ry = 4;
+    if (c.zchunk < 0) c.zchunk = 0;
+    return c;
+  }();
+  return cfg;
+}
+
+template <typename T, int NDIM, int RY>
+static hipError_t blocked_dispatch(StepMode mode, const Dims &d, const T *p, const T *prev, T *out, const T *kap,
+                                   int zchunk, hipStream_t s)
+{
+  constexpr int BY = 4 * RY;
+  const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + BY - 1) / BY;
+  if (zchunk <= 0) {
+    // aim at >= 2048 work-groups (8 per CU), at least 4 planes per group
+    const long xy = (long)tiles_x * tiles_y;
+    long want_zc = (2048 + xy - 1) / xy;
+    int zc = (int)((d.nz + want_zc - 1) / want_zc);
+    zchunk = zc < 4 ? 4 : zc;
+  }
+  if (zchunk > d.nz) zchunk = d.nz;
+  const int n_zc = (d.nz + zchunk - 1) / zchunk;
+  const int n_tiles = tiles_x * tiles_y * n_zc;
+  const int grid = ((n_tiles + 7) / 8) * 8;
+  switch (mode) {
+    case STEP_FIRST: wave_step_blocked<T, NDIM, STEP_FIRST, RY><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles); break;
+    case STEP_LEAP: wave_step_blocked<T, NDIM, STEP_LEAP, RY><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles); break;
+    case STEP_FIRST_DIV: wave_step_blocked<T, NDIM, STEP_FIRST_DIV, RY><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles); break;
+    case STEP_LEAP_DIV: wave_step_blocked<T, NDIM, STEP_LEAP_DIV, RY><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int NDIM>
+static hipError_t blocked_select(StepMode mode, const Dims &d, const T *p, const T *prev, T *out, const T *kap,
+                                 hipStream_t s)
+{
+  const BlockedConfig cfg = blocked_config();
+  switch (cfg.ry) {
+    case 2: return blocked_dispatch<T, NDIM, 2>(mode, d, p, prev, out, kap, cfg.zchunk, s);
+    case 8: return blocked_dispatch<T, NDIM, 8>(mode, d, p, prev, out, kap, cfg.zchunk, s);
+    default: return blocked_dispatch<T, NDIM, 4>(mode, d, p, prev, out, kap, cfg.zchunk, s);
+  }
+}
+
+template <typename T>
+hipError_t launch_wave_step(StencilKind kind, StepMode mode, const Dims &d, const T *p, const T *prev, T *out,
+                            const T *kap, hipStream_t s)
+{
+  if (kind == STENCIL_NAIVE) {
+    if (d.ndim == 2) return naive_dispatch<T, 2>(mode, d, p, prev, out, kap, s);
+    return naive_dispatch<T, 3>(mode, d, p, prev, out, kap, s);
+  }
+  if (d.ndim == 2) return blocked_select<T, 2>(mode, d, p, prev, out, kap, s);
+  return blocked_select<T, 3>(mode, d, p, prev, out, kap, s);
+}
+
+// ---------------------------------------------------------------------------
+// Plan set-up: k' from c, and the range / validity of c.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void make_kappa_kernel(const T *__restrict__ c, size_t n, double dt2_over_12dx2, T *__restrict__ kap)
+{
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double cv = (double)c[i];
+    kap[i] = (T)(cv * cv * dt2_over_12dx2);
+  }
+}
+
+template <typename T>
+hipError_t launch_make_kappa(const Dims &d, const T *c, double dt, double dx, T *kap, hipStream_t s)
+{
+  make_kappa_kernel<T><<<1024, 256, 0, s>>>(c, d.nvox(), dt * dt / (12.0 * dx * dx), kap);
+  return hipGetLastError();
+}
+
+// partials laid out as [3][nblocks]: min, max, bad count.
+template <typename T>
+__global__ void __launch_bounds__(256) c_stats_partial(const T *__restrict__ c, size_t n, double *partials, int nblocks)
+{
+  __shared__ double smin[256], smax[256], sbad[256];
+  double mn = DBL_MAX, mx = -DBL_MAX, bad = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double v = (double)c[i];
+    if (!(v > 0.0) || !isfinite(v)) bad += 1.0;
+    else {
+      mn = fmin(mn, v);
+      mx = fmax(mx, v);
+    }
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+      sbad[threadIdx.x] += sbad[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = smin[0];
+    partials[nblocks + blockIdx.x] = smax[0];
+    partials[2 * nblocks + blockIdx.x] = sbad[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) c_stats_final(const double *partials, int nblocks, double *stats)
+{
+  __shared__ double smin[256], smax[256], sbad[256];
+  double mn = DBL_MAX, mx = -DBL_MAX, bad = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) {
+    mn = fmin(mn, partials[i]);
+    mx = fmax(mx, partials[nblocks + i]);
+    bad += partials[2 * nblocks + i];
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+      sbad[threadIdx.x] += sbad[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stats[0] = smin[0];
+    stats[1] = smax[0];
+    stats[2] = sbad[0];
+  }
+}
+
+template <typename T>
+hipError_t launch_c_stats(const Dims &d, const T *c, double *partials, int nblocks, double *stats, hipStream_t s)
+{
+  c_stats_partial<T><<<nblocks, 256, 0, s>>>(c, d.nvox(), partials, nblocks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  c_stats_final<<<1, 256, 0, s>>>(partials, nblocks, stats);
+  return hipGetLastError();
+}
+
+#define FFPAT_INST(T)                                                                                        \
+  template hipError_t launch_wave_step<T>(StencilKind, StepMode, const Dims &, const T *, const T *, T *,  \
+                                          const T *, hipStream_t);                                          \
+  template hipError_t launch_make_kappa<T>(const Dims &, const T *, double, double, T *, hipStream_t);     \
+  template hipError_t launch_c_stats<T>(const Dims &, const T *, double *, int, double *, hipStream_t);
+FFPAT_INST(float)
+FFPAT_INST(double)
+#undef FFPAT_INST
+
+}  // namespace ffpat

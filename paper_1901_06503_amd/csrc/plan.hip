@@ -1,0 +1,624 @@
+// Plan, operator composition, Algorithm 8 driver and the C ABI of libffpat.
+//
+// Operators (Haltmeier, Zangerl, Nuster, Nguyen 2019):
+//   W_T       initial-to-final-time wave operator (eq. Wo): n_t leapfrog steps
+//   W_T^T     Euclidean transpose: the scheme is a polynomial in K L
+//             (K = diag((c dt)^2)), so W_T^T = K^-1 W_T K; the same stepper
+//             runs on k' g and the last step divides by k' (Sec. 3.1: the
+//             adjoint is a wave solve started from the data at time T)
+//   X, X^T    plane-wise X-ray transform (eq. Radon) and backprojection
+//   Lambda    ramp filter along s (Sec. 3.1)
+//   A = X W_T, A^T = W_T^T X^T
+//   Alg. 8    h <- prox_{s lambda R}(h - s A^T chi Lambda chi (A h - G))
+//
+// Workspace per plan (all device, one allocation): k', four volumes, one
+// data array, Ram-Lak taps, per-angle parameters, FP64 partials and scalars.
+// No host synchronisation inside the operators or the iteration; device
+// scalars (step, L, norms, objective) stay on the device until the end.
+#include "kernels.h"
+#include "../../include/ffpat.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace ffpat;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+  return fail(FFPAT_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);   \
+  } while (0)
+
+// Device scalar slots
+enum { SC_STEP = 0, SC_L = 1, SC_REG = 2, SC_DATA = 3, SC_NONFINITE = 4, SC_SUMSQ = 5, SC_COUNT = 8 };
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev)
+  {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard()
+  {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+struct Layout {
+  size_t kap, vol[4], dat, taps, ap, partials, scalars, total;
+  size_t n_partials;
+};
+
+}  // namespace
+
+struct ffpat_plan {
+  int device = 0;
+  Dims d{};
+  int dtype = FFPAT_F32;
+  size_t esz = 4;
+  int n_angles = 0, ns = 0;
+  double dx = 0, ds = 0, T = 0, cfl = 0;
+  uint32_t flags = 0;
+  int nt = 0;
+  double dt = 0, cmax = 0, cmin = 0;
+  size_t nvox = 0, ndat = 0;
+  int rows = 0;
+  StencilKind stencil = STENCIL_BLOCKED;
+  Layout lay{};
+  unsigned char *base = nullptr;
+  double *obj = nullptr;  // objective history (device), capacity obj_cap
+  int obj_cap = 0;
+  bool has_step = false;
+
+  void *vol(int i) const { return base + lay.vol[i]; }
+  void *kap() const { return base + lay.kap; }
+  void *dat() const { return base + lay.dat; }
+  void *taps() const { return base + lay.taps; }
+  AngleParams *ap() const { return reinterpret_cast<AngleParams *>(base + lay.ap); }
+  double *partials() const { return reinterpret_cast<double *>(base + lay.partials); }
+  double *scalars() const { return reinterpret_cast<double *>(base + lay.scalars); }
+};
+
+namespace {
+
+struct Resolved {
+  Dims d;
+  int dtype, n_angles, ns;
+  double dx, ds, T, cfl;
+  uint32_t flags;
+};
+
+int resolve(const ffpat_geom *g, Resolved *r)
+{
+  if (!g) return fail(FFPAT_EINVAL, "geometry is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(FFPAT_EINVAL, "grid sizes must be >= 1");
+  if (g->nz > 65535) return fail(FFPAT_EINVAL, "nz must be <= 65535");
+  const int ndim = g->ndim == 0 ? 3 : g->ndim;
+  if (ndim != 2 && ndim != 3) return fail(FFPAT_EINVAL, "ndim must be 2 or 3");
+  if (!(g->dx > 0) || !std::isfinite(g->dx)) return fail(FFPAT_EINVAL, "dx must be finite and > 0");
+  if (!(g->T > 0) || !std::isfinite(g->T)) return fail(FFPAT_EINVAL, "T must be finite and > 0");
+  const double cfl = g->cfl == 0 ? 0.3 : g->cfl;
+  const double cfl_max = ndim == 3 ? 0.5 : std::sqrt(3.0 / 8.0);
+  if (!(cfl > 0) || !(cfl < cfl_max))
+    return fail(FFPAT_ECFL, "cfl %g outside (0, %g): the leapfrog scheme would be unstable", cfl, cfl_max);
+  if (g->n_angles < 1 || g->n_angles > 65535) return fail(FFPAT_EINVAL, "n_angles must be in [1, 65535]");
+  if (!g->angles) return fail(FFPAT_EINVAL, "angles is NULL");
+  for (int a = 0; a < g->n_angles; ++a)
+    if (!std::isfinite(g->angles[a])) return fail(FFPAT_EINVAL, "angle %d is not finite", a);
+  const int ns = g->ns == 0 ? g->nx : g->ns;
+  if (ns < 1 || ns > 8192) return fail(FFPAT_EINVAL, "ns must be in [1, 8192]");
+  const double ds = g->ds == 0 ? g->dx : g->ds;
+  if (!(ds > 0) || !std::isfinite(ds)) return fail(FFPAT_EINVAL, "ds must be finite and > 0");
+  if (g->dtype != FFPAT_F32 && g->dtype != FFPAT_F64) return fail(FFPAT_EDTYPE, "unknown dtype %d", g->dtype);
+  const size_t nvox = (size_t)g->nx * g->ny * g->nz;
+  const size_t ndat = (size_t)g->n_angles * g->nz * ns;
+  if (nvox > ((size_t)1 << 33) || ndat > ((size_t)1 << 33)) return fail(FFPAT_EINVAL, "problem too large");
+  r->d = Dims{g->nx, g->ny, g->nz, ndim};
+  r->dtype = g->dtype;
+  r->n_angles = g->n_angles;
+  r->ns = ns;
+  r->dx = g->dx;
+  r->ds = ds;
+  r->T = g->T;
+  r->cfl = cfl;
+  r->flags = g->flags;
+  return FFPAT_OK;
+}
+
+Layout layout(const Resolved &r)
+{
+  Layout L{};
+  const size_t esz = r.dtype == FFPAT_F64 ? 8 : 4;
+  const size_t nvox = r.d.nvox();
+  const size_t ndat = (size_t)r.n_angles * r.d.nz * r.ns;
+  const size_t rows = (size_t)r.n_angles * r.d.nz;
+  size_t off = 0;
+  L.kap = off; off = align_up(off + nvox * esz);
+  for (int i = 0; i < 4; ++i) { L.vol[i] = off; off = align_up(off + nvox * esz); }
+  L.dat = off; off = align_up(off + ndat * esz);
+  L.taps = off; off = align_up(off + (size_t)r.ns * esz);
+  L.ap = off; off = align_up(off + (size_t)r.n_angles * sizeof(AngleParams));
+  L.n_partials = rows > (size_t)3 * kReduceBlocks ? rows : (size_t)3 * kReduceBlocks;
+  L.partials = off; off = align_up(off + L.n_partials * sizeof(double));
+  L.scalars = off; off = align_up(off + SC_COUNT * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// Per-angle geometry in double precision (see AngleParams).
+AngleParams angle_params(double phi, const Resolved &r)
+{
+  AngleParams P{};
+  const double ca = std::cos(phi), sa = std::sin(phi);
+  const double m = std::fmax(std::fabs(ca), std::fabs(sa));
+  const double cx = 0.5 * (r.d.nx - 1), cy = 0.5 * (r.d.ny - 1), cs = 0.5 * (r.ns - 1);
+  const double dx = r.dx, ds = r.ds;
+  P.w = dx / m;
+  P.major_x = std::fabs(sa) > std::fabs(ca) ? 1 : 0;
+  if (!P.major_x) {
+    // rows y_r; x* = (s_j - y_r sin) / cos, u = x*/dx + cx
+    P.uj = ds / (dx * ca);
+    P.ur = -sa / ca;
+    P.u0 = cx - cs * ds / (dx * ca) + cy * sa / ca;
+  } else {
+    // columns x_r; y* = (s_j - x_r cos) / sin, u = y*/dx + cy
+    P.uj = ds / (dx * sa);
+    P.ur = -ca / sa;
+    P.u0 = cy - cs * ds / (dx * sa) + cx * ca / sa;
+  }
+  // bin position of voxel (i, k): t = (x_i cos + y_k sin) / ds + cs
+  P.bi = dx * ca / ds;
+  P.bk = dx * sa / ds;
+  P.b0 = cs - cx * dx * ca / ds - cy * dx * sa / ds;
+  P.hw = m * dx / ds;
+  P.inv_hw = 1.0 / P.hw;
+  return P;
+}
+
+// Ram-Lak taps times pi / (n_angles dx^2): makes X^T Lambda X ~ I (filtered
+// backprojection over [0, pi) with the ray-sum weights of X).
+template <typename T>
+std::vector<T> ramp_taps(const Resolved &r)
+{
+  const double C = M_PI / ((double)r.n_angles * r.dx * r.dx);
+  std::vector<T> t((size_t)r.ns);
+  for (int n = 0; n < r.ns; ++n) {
+    double h = 0.0;
+    if (n == 0) h = 0.25;
+    else if (n % 2 == 1) h = -1.0 / (M_PI * M_PI * (double)n * (double)n);
+    t[(size_t)n] = (T)(C * h);
+  }
+  return t;
+}
+
+// ------------------------------------------------------------------ operators
+template <typename T>
+int wave_forward(ffpat_plan *P, const T *in, T *out, T *ws, hipStream_t s)
+{
+  const T *kap = static_cast<const T *>(P->kap());
+  const int nt = P->nt;
+  T *X1 = (nt % 2 == 1) ? out : ws;
+  T *X2 = (nt % 2 == 1) ? ws : out;
+  HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, in, nullptr, X1, kap, s));
+  const T *pm1 = in;
+  T *pk = X1;
+  for (int k = 1; k < nt; ++k) {
+    T *dst = (k == 1) ? X2 : const_cast<T *>(pm1);
+    HIP_TRY(launch_wave_step<T>(P->stencil, STEP_LEAP, P->d, pk, pm1, dst, kap, s));
+    pm1 = pk;
+    pk = dst;
+  }
+  return FFPAT_OK;
+}
+
+// out = K^-1 W_T K g given b = k' g already in `b` (overwritten), ws scratch.
+template <typename T>
+int wave_adjoint_from_scaled(ffpat_plan *P, T *b, T *out, T *ws, hipStream_t s)
+{
+  const T *kap = static_cast<const T *>(P->kap());
+  const int nt = P->nt;
+  if (nt == 1) {
+    HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST_DIV, P->d, b, nullptr, out, kap, s));
+    return FFPAT_OK;
+  }
+  HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, b, nullptr, ws, kap, s));
+  T *pm1 = b, *pk = ws;
+  for (int k = 1; k < nt; ++k) {
+    const bool last = (k == nt - 1);
+    T *dst = last ? out : pm1;
+    HIP_TRY(launch_wave_step<T>(P->stencil, last ? STEP_LEAP_DIV : STEP_LEAP, P->d, pk, pm1, dst, kap, s));
+    pm1 = pk;
+    pk = dst;
+  }
+  return FFPAT_OK;
+}
+
+template <typename T>
+int wave_adjoint_op(ffpat_plan *P, const T *g, T *q, hipStream_t s)
+{
+  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1));
+  HIP_TRY(launch_mul<T>(g, static_cast<const T *>(P->kap()), V1, P->nvox, s));
+  return wave_adjoint_from_scaled<T>(P, V1, q, V2, s);
+}
+
+template <typename T>
+int op_forward(ffpat_plan *P, const T *h, T *g, hipStream_t s)
+{
+  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1));
+  int rc = wave_forward<T>(P, h, V2, V1, s);
+  if (rc) return rc;
+  HIP_TRY(launch_project<T>(P->d, P->n_angles, P->ns, P->ap(), V2, g, s));
+  return FFPAT_OK;
+}
+
+template <typename T>
+int op_adjoint(ffpat_plan *P, const T *g, T *h, hipStream_t s)
+{
+  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1));
+  HIP_TRY(launch_backproject<T>(P->d, P->n_angles, P->ns, P->ap(), g, V1, static_cast<const T *>(P->kap()), s));
+  return wave_adjoint_from_scaled<T>(P, V1, h, V2, s);
+}
+
+// y = chi Lambda chi (A v) or chi (A v - G): the data-space part of one iteration.
+template <typename T>
+int data_residual(ffpat_plan *P, const T *v, const T *G, const uint8_t *mask, bool precond, double *row_partials,
+                  hipStream_t s)
+{
+  T *D = static_cast<T *>(P->dat());
+  int rc = op_forward<T>(P, v, D, s);
+  if (rc) return rc;
+  HIP_TRY(launch_residual_ramp<T>(P->rows, P->ns, D, G, mask, precond ? static_cast<const T *>(P->taps()) : nullptr,
+                                  D, row_partials, s));
+  return FFPAT_OK;
+}
+
+template <typename T>
+int power_iteration(ffpat_plan *P, int n_power, bool precond, const uint8_t *mask, hipStream_t s)
+{
+  T *V3 = static_cast<T *>(P->vol(2)), *V4 = static_cast<T *>(P->vol(3));
+  T *D = static_cast<T *>(P->dat());
+  double *sc = P->scalars();
+  HIP_TRY(launch_fill<T>(V4, P->nvox, 1.0 / std::sqrt((double)P->nvox), s));
+  for (int it = 0; it < n_power; ++it) {
+    int rc = data_residual<T>(P, V4, nullptr, mask, precond, nullptr, s);
+    if (rc) return rc;
+    rc = op_adjoint<T>(P, D, V3, s);
+    if (rc) return rc;
+    HIP_TRY(launch_sumsq<T>(V3, P->nvox, P->partials(), s));
+    HIP_TRY(launch_reduce_to(P->partials(), kReduceBlocks, 1.0, sc + SC_SUMSQ, s));
+    HIP_TRY(launch_normalize<T>(V3, V4, P->nvox, sc + SC_SUMSQ, s));
+  }
+  HIP_TRY(launch_power_finish(sc + SC_SUMSQ, sc + SC_L, sc + SC_STEP, sc + SC_NONFINITE, s));
+  return FFPAT_OK;
+}
+
+template <typename T>
+int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, int k, hipStream_t s)
+{
+  const bool precond = prm->flags & FFPAT_PRECOND;
+  T *V3 = static_cast<T *>(P->vol(2));
+  T *D = static_cast<T *>(P->dat());
+  double *sc = P->scalars();
+  // R(h_k) for the objective
+  HIP_TRY(launch_sumsq<T>(h, P->nvox, P->partials(), s));
+  HIP_TRY(launch_reduce_to(P->partials(), kReduceBlocks, 1.0, sc + SC_REG, s));
+  // r = chi (A h - G), y = chi Lambda r, data term
+  int rc = data_residual<T>(P, h, G, prm->det_mask, precond, P->partials(), s);
+  if (rc) return rc;
+  HIP_TRY(launch_reduce_to(P->partials(), P->rows, 1.0, sc + SC_DATA, s));
+  HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->obj + k, sc + SC_NONFINITE, s));
+  // gradient A^T y, then the prox step
+  rc = op_adjoint<T>(P, D, V3, s);
+  if (rc) return rc;
+  HIP_TRY(launch_prox_l2<T>(h, V3, P->nvox, sc + SC_STEP, prm->lambda, (prm->flags & FFPAT_POSITIVITY) ? 1 : 0,
+                            prm->support, s));
+  return FFPAT_OK;
+}
+
+template <typename T>
+int reconstruct(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, double *step_used, hipStream_t s)
+{
+  const bool precond = prm->flags & FFPAT_PRECOND;
+  double *sc = P->scalars();
+  HIP_TRY(launch_set(sc + SC_NONFINITE, 0.0, s));
+  if (prm->flags & FFPAT_USE_PLAN_STEP) {
+    if (!P->has_step) return fail(FFPAT_EINVAL, "FFPAT_USE_PLAN_STEP but the plan holds no step yet");
+  } else if (prm->step > 0) {
+    HIP_TRY(launch_set(sc + SC_STEP, prm->step, s));
+  } else {
+    int rc = power_iteration<T>(P, prm->n_power > 0 ? prm->n_power : 20, precond, prm->det_mask, s);
+    if (rc) return rc;
+  }
+  P->has_step = true;
+  if (prm->n_iter > P->obj_cap) {
+    if (P->obj) {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipFree(P->obj));
+      P->obj = nullptr;
+      P->obj_cap = 0;
+    }
+    HIP_TRY(hipMalloc(&P->obj, sizeof(double) * (size_t)prm->n_iter));
+    P->obj_cap = prm->n_iter;
+  }
+  for (int k = 0; k < prm->n_iter; ++k) {
+    int rc = fb_iteration<T>(P, G, h, prm, k, s);
+    if (rc) return rc;
+  }
+  double host_sc[SC_COUNT];
+  HIP_TRY(hipMemcpyAsync(host_sc, sc, sizeof host_sc, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (prm->objective && prm->n_iter > 0)
+    HIP_TRY(hipMemcpy(prm->objective, P->obj, sizeof(double) * (size_t)prm->n_iter, hipMemcpyDeviceToHost));
+  if (step_used) *step_used = host_sc[SC_STEP];
+  if (host_sc[SC_NONFINITE] != 0.0 || !std::isfinite(host_sc[SC_STEP]))
+    return fail(FFPAT_EDIVERGED, "non-finite objective, norm or step during reconstruction");
+  return FFPAT_OK;
+}
+
+bool is_f64(const ffpat_plan *P) { return P->dtype == FFPAT_F64; }
+
+#define CHECK_PLAN(P)                                               \
+  do {                                                              \
+    if (!(P)) return fail(FFPAT_EINVAL, "plan is NULL");            \
+  } while (0)
+#define CHECK_PTR(p, name)                                          \
+  do {                                                              \
+    if (!(p)) return fail(FFPAT_EINVAL, "%s is NULL", name);        \
+  } while (0)
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+const char *ffpat_version(void) { return "ffpat 0.1 (gfx950)"; }
+
+const char *ffpat_last_error(void) { return g_last_error.c_str(); }
+
+int ffpat_workspace_bytes(const ffpat_geom *geom, size_t *bytes)
+{
+  Resolved r;
+  int rc = resolve(geom, &r);
+  if (rc) return rc;
+  CHECK_PTR(bytes, "bytes");
+  *bytes = layout(r).total;
+  return FFPAT_OK;
+}
+
+int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, ffpat_plan **out)
+{
+  CHECK_PTR(out, "out");
+  *out = nullptr;
+  Resolved r;
+  int rc = resolve(geom, &r);
+  if (rc) return rc;
+  CHECK_PTR(c_dev, "c_dev");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  ffpat_plan *P = new (std::nothrow) ffpat_plan();
+  if (!P) return fail(FFPAT_ENOMEM, "host allocation failed");
+  HIP_TRY(hipGetDevice(&P->device));
+  P->d = r.d;
+  P->dtype = r.dtype;
+  P->esz = r.dtype == FFPAT_F64 ? 8 : 4;
+  P->n_angles = r.n_angles;
+  P->ns = r.ns;
+  P->dx = r.dx;
+  P->ds = r.ds;
+  P->T = r.T;
+  P->cfl = r.cfl;
+  P->flags = r.flags;
+  P->stencil = (r.flags & FFPAT_PLAN_NAIVE_STENCIL) ? STENCIL_NAIVE : STENCIL_BLOCKED;
+  P->nvox = r.d.nvox();
+  P->ndat = (size_t)r.n_angles * r.d.nz * r.ns;
+  P->rows = r.n_angles * r.d.nz;
+  P->lay = layout(r);
+
+  hipError_t e = hipMalloc(&P->base, P->lay.total);
+  if (e != hipSuccess) {
+    delete P;
+    return fail(FFPAT_ENOMEM, "hipMalloc(%zu) failed: %s", P->lay.total, hipGetErrorString(e));
+  }
+  auto cleanup = [&](int code) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(P->base);
+    delete P;
+    return code;
+  };
+
+  // c range and validity (the one host read of the plan set-up)
+  double stats[3];
+  double *sc = P->scalars();
+  if (is_f64(P)) e = launch_c_stats<double>(P->d, static_cast<const double *>(c_dev), P->partials(), kReduceBlocks, sc, s);
+  else e = launch_c_stats<float>(P->d, static_cast<const float *>(c_dev), P->partials(), kReduceBlocks, sc, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(stats, sc, sizeof stats, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "sound-speed statistics"));
+  if (stats[2] != 0.0) return cleanup(fail(FFPAT_EINVAL, "c has %.0f non-finite or non-positive values", stats[2]));
+  P->cmin = stats[0];
+  P->cmax = stats[1];
+
+  // time grid: dt = cfl dx / c_max, rounded so that n_t dt = T exactly
+  const double x = P->T * P->cmax / (P->cfl * P->dx);
+  double n = std::ceil(x * (1.0 - 1e-12));
+  if (n < 1.0) n = 1.0;
+  if (n > 1e7) return cleanup(fail(FFPAT_EINVAL, "n_t = %g time steps is unreasonably large", n));
+  P->nt = (int)n;
+  P->dt = P->T / n;
+
+  if (is_f64(P)) e = launch_make_kappa<double>(P->d, static_cast<const double *>(c_dev), P->dt, P->dx, static_cast<double *>(P->kap()), s);
+  else e = launch_make_kappa<float>(P->d, static_cast<const float *>(c_dev), P->dt, P->dx, static_cast<float *>(P->kap()), s);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "make_kappa"));
+
+  std::vector<AngleParams> ap((size_t)r.n_angles);
+  for (int a = 0; a < r.n_angles; ++a) ap[(size_t)a] = angle_params(geom->angles[a], r);
+  if (is_f64(P)) {
+    std::vector<double> t = ramp_taps<double>(r);
+    e = hipMemcpyAsync(P->taps(), t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->ap(), ap.data(), ap.size() * sizeof(AngleParams), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  } else {
+    std::vector<float> t = ramp_taps<float>(r);
+    e = hipMemcpyAsync(P->taps(), t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->ap(), ap.data(), ap.size() * sizeof(AngleParams), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  if (e != hipSuccess) return cleanup(hip_fail(e, "plan upload"));
+  *out = P;
+  return FFPAT_OK;
+}
+
+int ffpat_plan_info(const ffpat_plan *plan, int32_t *nt, double *dt, double *cmax)
+{
+  CHECK_PLAN(plan);
+  if (nt) *nt = plan->nt;
+  if (dt) *dt = plan->dt;
+  if (cmax) *cmax = plan->cmax;
+  return FFPAT_OK;
+}
+
+int ffpat_plan_destroy(ffpat_plan *plan)
+{
+  if (!plan) return FFPAT_OK;
+  DeviceGuard guard(plan->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (plan->obj) (void)hipFree(plan->obj);
+  (void)hipFree(plan->base);
+  delete plan;
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  return FFPAT_OK;
+}
+
+#define DISPATCH(P, CALL_F, CALL_D) (is_f64(P) ? (CALL_D) : (CALL_F))
+
+int ffpat_forward(ffpat_plan *plan, const void *h_dev, void *g_dev, void *stream)
+{
+  CHECK_PLAN(plan);
+  CHECK_PTR(h_dev, "h_dev");
+  CHECK_PTR(g_dev, "g_dev");
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return DISPATCH(plan, op_forward<float>(plan, (const float *)h_dev, (float *)g_dev, s),
+                  op_forward<double>(plan, (const double *)h_dev, (double *)g_dev, s));
+}
+
+int ffpat_adjoint(ffpat_plan *plan, const void *g_dev, void *h_dev, void *stream)
+{
+  CHECK_PLAN(plan);
+  CHECK_PTR(h_dev, "h_dev");
+  CHECK_PTR(g_dev, "g_dev");
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return DISPATCH(plan, op_adjoint<float>(plan, (const float *)g_dev, (float *)h_dev, s),
+                  op_adjoint<double>(plan, (const double *)g_dev, (double *)h_dev, s));
+}
+
+int ffpat_wave(ffpat_plan *plan, const void *h_dev, void *p_dev, void *stream)
+{
+  CHECK_PLAN(plan);
+  CHECK_PTR(h_dev, "h_dev");
+  CHECK_PTR(p_dev, "p_dev");
+  if (h_dev == p_dev) return fail(FFPAT_EINVAL, "h_dev and p_dev must not overlap");
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return DISPATCH(plan, wave_forward<float>(plan, (const float *)h_dev, (float *)p_dev, (float *)plan->vol(0), s),
+                  wave_forward<double>(plan, (const double *)h_dev, (double *)p_dev, (double *)plan->vol(0), s));
+}
+
+int ffpat_wave_adjoint(ffpat_plan *plan, const void *g_dev, void *q_dev, void *stream)
+{
+  CHECK_PLAN(plan);
+  CHECK_PTR(g_dev, "g_dev");
+  CHECK_PTR(q_dev, "q_dev");
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return DISPATCH(plan, wave_adjoint_op<float>(plan, (const float *)g_dev, (float *)q_dev, s),
+                  wave_adjoint_op<double>(plan, (const double *)g_dev, (double *)q_dev, s));
+}
+
+int ffpat_project(ffpat_plan *plan, const void *vol_dev, void *g_dev, void *stream)
+{
+  CHECK_PLAN(plan);
+  CHECK_PTR(vol_dev, "vol_dev");
+  CHECK_PTR(g_dev, "g_dev");
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = DISPATCH(plan,
+      launch_project<float>(plan->d, plan->n_angles, plan->ns, plan->ap(), (const float *)vol_dev, (float *)g_dev, s),
+      launch_project<double>(plan->d, plan->n_angles, plan->ns, plan->ap(), (const double *)vol_dev, (double *)g_dev, s));
+  return e == hipSuccess ? FFPAT_OK : hip_fail(e, "project");
+}
+
+int ffpat_backproject(ffpat_plan *plan, const void *g_dev, void *vol_dev, void *stream)
+{
+  CHECK_PLAN(plan);
+  CHECK_PTR(vol_dev, "vol_dev");
+  CHECK_PTR(g_dev, "g_dev");
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = DISPATCH(plan,
+      launch_backproject<float>(plan->d, plan->n_angles, plan->ns, plan->ap(), (const float *)g_dev, (float *)vol_dev, nullptr, s),
+      launch_backproject<double>(plan->d, plan->n_angles, plan->ns, plan->ap(), (const double *)g_dev, (double *)vol_dev, nullptr, s));
+  return e == hipSuccess ? FFPAT_OK : hip_fail(e, "backproject");
+}
+
+int ffpat_ramp(ffpat_plan *plan, const void *r_dev, void *y_dev, void *stream)
+{
+  CHECK_PLAN(plan);
+  CHECK_PTR(r_dev, "r_dev");
+  CHECK_PTR(y_dev, "y_dev");
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = DISPATCH(plan,
+      launch_residual_ramp<float>(plan->rows, plan->ns, (const float *)r_dev, nullptr, nullptr, (const float *)plan->taps(), (float *)y_dev, nullptr, s),
+      launch_residual_ramp<double>(plan->rows, plan->ns, (const double *)r_dev, nullptr, nullptr, (const double *)plan->taps(), (double *)y_dev, nullptr, s));
+  return e == hipSuccess ? FFPAT_OK : hip_fail(e, "ramp");
+}
+
+int ffpat_reconstruct(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev,
+                      double *step_used, void *stream)
+{
+  CHECK_PLAN(plan);
+  CHECK_PTR(params, "params");
+  CHECK_PTR(G_dev, "G_dev");
+  CHECK_PTR(h_dev, "h_dev");
+  if (params->n_iter < 0) return fail(FFPAT_EINVAL, "n_iter must be >= 0");
+  if (params->n_power < 0) return fail(FFPAT_EINVAL, "n_power must be >= 0");
+  if (!(params->lambda >= 0) || !std::isfinite(params->lambda)) return fail(FFPAT_EINVAL, "lambda must be finite and >= 0");
+  if (!std::isfinite(params->step)) return fail(FFPAT_EINVAL, "step must be finite");
+  if (params->flags & FFPAT_REG_GRAD) return fail(FFPAT_EINVAL, "FFPAT_REG_GRAD is not available in this build");
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return DISPATCH(plan, reconstruct<float>(plan, (const float *)G_dev, params, (float *)h_dev, step_used, s),
+                  reconstruct<double>(plan, (const double *)G_dev, params, (double *)h_dev, step_used, s));
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must build, load and export every function include/ffpat.h
+declares; argument validation must reject bad input before touching any
+device memory (so these calls are safe without a GPU).
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ffpat.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ffpat_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1901_06503_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1901_06503_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["ffpat_forward", "ffpat_adjoint", "ffpat_reconstruct", "ffpat_plan_create",
+                     "ffpat_plan_destroy", "ffpat_workspace_bytes", "ffpat_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    from paper_1901_06503_amd import _lib
+    assert set(_lib.SIGNATURES) == set(declared_functions())
+
+
+def test_version(lib):
+    assert b"gfx950" in lib.ffpat_version()
+
+
+def _geom(nx=32, ny=30, nz=20, dx=0.05, T=0.5, cfl=0.3, n_angles=16, ns=0, ds=0.0, dtype=0, ndim=3,
+          angles=None):
+    from paper_1901_06503_amd import _lib
+    ang = np.linspace(0, math.pi, n_angles, endpoint=False) if angles is None else np.asarray(angles, float)
+    g = _lib.Geom(nx, ny, nz, ndim, dx, T, cfl, n_angles, ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                  ns, ds, dtype, 0)
+    return g, ang
+
+
+def test_workspace_bytes_accounts_for_all_buffers(lib):
+    g, _a = _geom(nx=64, ny=64, nz=64, n_angles=64)
+    out = ctypes.c_size_t()
+    assert lib.ffpat_workspace_bytes(ctypes.byref(g), ctypes.byref(out)) == 0
+    nvox, ndat = 64 ** 3, 64 ** 3
+    assert out.value >= (5 * nvox + ndat) * 4
+    assert out.value < (5 * nvox + ndat) * 4 + 2 * 1024 * 1024
+    g64, _b = _geom(nx=64, ny=64, nz=64, n_angles=64, dtype=1)
+    out64 = ctypes.c_size_t()
+    assert lib.ffpat_workspace_bytes(ctypes.byref(g64), ctypes.byref(out64)) == 0
+    assert out64.value > 1.9 * out.value
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(cfl=0.5), -2), (dict(cfl=0.7), -2), (dict(cfl=-0.1), -2),
+    (dict(cfl=0.6, ndim=2), 0), (dict(cfl=0.62, ndim=2), -2),
+    (dict(nx=0), -1), (dict(dx=0.0), -1), (dict(dx=float("nan")), -1), (dict(T=-1.0), -1),
+    (dict(n_angles=0), -1), (dict(ns=-3), -1), (dict(ds=-1.0), -1), (dict(dtype=7), -6), (dict(ndim=4), -1),
+    (dict(angles=[0.0, float("inf")], n_angles=2), -1),
+])
+def test_geometry_validation(lib, kw, status):
+    g, _a = _geom(**kw)
+    out = ctypes.c_size_t()
+    assert lib.ffpat_workspace_bytes(ctypes.byref(g), ctypes.byref(out)) == status
+    if status != 0:
+        assert lib.ffpat_last_error() != b""
+
+
+def test_plan_create_rejects_before_device_work(lib):
+    # invalid geometry with a non-null dummy pointer: rejected on the host, nothing dereferenced
+    g, _a = _geom(cfl=0.9)
+    plan = ctypes.c_void_p()
+    rc = lib.ffpat_plan_create(ctypes.byref(g), ctypes.c_void_p(0x1000), None, ctypes.byref(plan))
+    assert rc == -2 and not plan.value
+    g2, _b = _geom()
+    rc = lib.ffpat_plan_create(ctypes.byref(g2), None, None, ctypes.byref(plan))
+    assert rc == -1 and b"c_dev" in lib.ffpat_last_error()
+
+
+def test_null_plan_is_rejected(lib):
+    for name in ["ffpat_forward", "ffpat_adjoint", "ffpat_wave", "ffpat_wave_adjoint", "ffpat_project",
+                 "ffpat_backproject", "ffpat_ramp"]:
+        assert getattr(lib, name)(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == -1
+    assert lib.ffpat_plan_destroy(None) == 0
+
+
+def test_python_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1901_06503_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()

@@ -1,0 +1,230 @@
+"""GPU parity: every operator of the HIP library against the FP64 oracle.
+
+Inputs are seeded (synth), identical on both sides (FP32 cases feed the
+oracle the FP32-rounded values).  Tolerances (relative L2):
+  FP64: 1e-12 per operator, 1e-10 for reconstructions;
+  FP32: 1e-5 for anything containing the wave solve, 2e-6 for X, X^T, Lambda,
+        1e-4 for reconstructions after a fixed iteration count.
+Grids are ragged on purpose (several 64-wide tiles plus a tail, odd ny, nz).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import rel_l2, rounded, to_dev, to_np
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+F32, F64 = torch.float32, torch.float64
+TOL_WAVE = {F32: 1e-5, F64: 1e-12}
+TOL_X = {F32: 2e-6, F64: 1e-12}
+
+SHAPES = [(23, 37, 70), (48, 48, 48), (9, 131, 67)]   # (nz, ny, nx)
+
+
+def make_case(shape, seed, n_angles=13, ns=None, ds_ratio=1.0, T=0.35, cfl=0.3):
+    nz, ny, nx = shape
+    dx = synth.grid_spacing(max(shape))
+    rng = np.random.default_rng(seed)
+    c = synth.sound_speed(shape, dx, rng, 3, 0.2, (0.8, 1.2))
+    h = synth.gaussian_smooth(synth.balls(shape, dx, rng, 5), 1.0) + 0.1 * rng.standard_normal(shape)
+    angles = np.sort(rng.uniform(0, math.pi, n_angles))
+    angles[0] = 0.0
+    if n_angles > 3:
+        angles[1] = math.pi / 4
+        angles[2] = math.pi / 2
+    ns = ns or nx
+    return dict(shape=shape, dx=dx, ds=ds_ratio * dx, ns=ns, T=T, cfl=cfl, c=c, h=h, angles=angles, rng=rng)
+
+
+def oracle_geom(oracle, k, ndim=3):
+    nz, ny, nx = k["shape"]
+    return oracle.Geometry(nx=nx, ny=ny, nz=nz, dx=k["dx"], T=k["T"], angles=k["angles"], cfl=k["cfl"],
+                           ns=k["ns"], ds=k["ds"], ndim=ndim)
+
+
+def gpu_plan(k, dtype, naive=False, ndim=3):
+    import paper_1901_06503_amd as ff
+    return ff.Plan(to_dev(k["c"], dtype), k["dx"], k["T"], k["angles"], ns=k["ns"], ds=k["ds"], cfl=k["cfl"],
+                   ndim=ndim, naive_stencil=naive)
+
+
+def _case_tag(shape, dtype, naive):
+    print(f"[parity] shape={shape} dtype={dtype} naive={naive}", flush=True)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_plan_time_grid_matches_oracle(oracle, shape, dtype):
+    k = make_case(shape, 1)
+    with gpu_plan(k, dtype) as P:
+        nt, dt, cmax = oracle.plan_info(oracle_geom(oracle, k), rounded(k["c"], dtype))
+        assert P.nt == nt
+        assert P.dt == dt
+        assert P.cmax == cmax
+
+
+@pytest.mark.parametrize("naive", [False, True])
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_wave_and_transpose(oracle, shape, dtype, naive):
+    _case_tag(shape, dtype, naive)
+    k = make_case(shape, 2)
+    g = oracle_geom(oracle, k)
+    c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
+    with gpu_plan(k, dtype, naive) as P:
+        p = to_np(P.wave(to_dev(h, dtype)))
+        assert rel_l2(p, oracle.wave(g, c, h)) <= TOL_WAVE[dtype]
+        q = to_np(P.wave_adjoint(to_dev(h, dtype)))
+        assert rel_l2(q, oracle.wave_T(g, c, h)) <= TOL_WAVE[dtype]
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("ds_ratio,ns_extra", [(1.0, 0), (0.83, 7), (1.3, -5)])
+def test_project_backproject(oracle, shape, dtype, ds_ratio, ns_extra):
+    nz, ny, nx = shape
+    k = make_case(shape, 3, n_angles=17, ns=nx + ns_extra, ds_ratio=ds_ratio)
+    g = oracle_geom(oracle, k)
+    v = rounded(k["h"], dtype)
+    d = rounded(k["rng"].standard_normal(g.data_shape), dtype)
+    with gpu_plan(k, dtype) as P:
+        gp = to_np(P.project(to_dev(v, dtype)))
+        assert rel_l2(gp, oracle.project(g, v)) <= TOL_X[dtype]
+        bp = to_np(P.backproject(to_dev(d, dtype)))
+        assert rel_l2(bp, oracle.backproject(g, d)) <= TOL_X[dtype]
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("ns", [1, 2, 48, 257, 700])
+def test_ramp(oracle, dtype, ns):
+    k = make_case((5, 8, 8), 4, n_angles=7, ns=ns)
+    g = oracle_geom(oracle, k)
+    r = rounded(k["rng"].standard_normal(g.data_shape), dtype)
+    with gpu_plan(k, dtype) as P:
+        y = to_np(P.ramp(to_dev(r, dtype)))
+        assert rel_l2(y, oracle.ramp(g, r)) <= TOL_X[dtype]
+        # in place
+        t = to_dev(r, dtype)
+        P.ramp(t, out=t)
+        assert rel_l2(to_np(t), oracle.ramp(g, r)) <= TOL_X[dtype]
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("shape", SHAPES[:2])
+def test_forward_adjoint(oracle, shape, dtype):
+    k = make_case(shape, 5, n_angles=19)
+    g = oracle_geom(oracle, k)
+    c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
+    d = rounded(k["rng"].standard_normal(g.data_shape), dtype)
+    with gpu_plan(k, dtype) as P:
+        A = to_np(P.forward(to_dev(h, dtype)))
+        assert rel_l2(A, oracle.forward(g, c, h)) <= TOL_WAVE[dtype]
+        AT = to_np(P.adjoint(to_dev(d, dtype)))
+        assert rel_l2(AT, oracle.adjoint(g, c, d)) <= TOL_WAVE[dtype]
+
+
+def test_gpu_dot_test_fp64():
+    k = make_case((31, 40, 66), 6, n_angles=23)
+    h = k["h"]
+    d = k["rng"].standard_normal((23, 31, 66))
+    with gpu_plan(k, F64) as P:
+        lhs = float(torch.sum(P.forward(to_dev(h, F64)) * to_dev(d, F64)))
+        rhs = float(torch.sum(to_dev(h, F64) * P.adjoint(to_dev(d, F64))))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_edge_single_step_single_angle_single_plane(oracle, dtype):
+    # n_t = 1 (tiny T), one angle, one z plane, ns = 1
+    k = make_case((1, 12, 10), 7, n_angles=1, ns=1, T=0.005)
+    g = oracle_geom(oracle, k)
+    c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
+    d = rounded(k["rng"].standard_normal(g.data_shape), dtype)
+    with gpu_plan(k, dtype) as P:
+        assert P.nt == 1
+        assert rel_l2(to_np(P.forward(to_dev(h, dtype))), oracle.forward(g, c, h)) <= TOL_WAVE[dtype]
+        assert rel_l2(to_np(P.adjoint(to_dev(d, dtype))), oracle.adjoint(g, c, d)) <= TOL_WAVE[dtype]
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_edge_two_steps_and_tiny_grid(oracle, dtype):
+    k = make_case((3, 2, 5), 8, n_angles=4)
+    k["T"] = 1.5 * k["cfl"] * k["dx"] / float(rounded(k["c"], dtype).max())   # between one and two steps
+    g = oracle_geom(oracle, k)
+    c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
+    with gpu_plan(k, dtype) as P:
+        assert P.nt == 2
+        assert rel_l2(to_np(P.wave(to_dev(h, dtype))), oracle.wave(g, c, h)) <= TOL_WAVE[dtype]
+        assert rel_l2(to_np(P.wave_adjoint(to_dev(h, dtype))), oracle.wave_T(g, c, h)) <= TOL_WAVE[dtype]
+
+
+@pytest.mark.parametrize("naive", [False, True])
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_two_dimensional_mode(oracle, dtype, naive):
+    k = make_case((11, 50, 66), 9, n_angles=11)
+    g = oracle_geom(oracle, k, ndim=2)
+    c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
+    with gpu_plan(k, dtype, naive=naive, ndim=2) as P:
+        assert rel_l2(to_np(P.wave(to_dev(h, dtype))), oracle.wave(g, c, h)) <= TOL_WAVE[dtype]
+        assert rel_l2(to_np(P.forward(to_dev(h, dtype))), oracle.forward(g, c, h)) <= TOL_WAVE[dtype]
+
+
+# ---------------------------------------------------------------- Algorithm 8
+def _fb_case(oracle, shape, n_angles, seed, dtype, eta=0.01):
+    k = make_case(shape, seed, n_angles=n_angles, T=0.5)
+    k["h"] = np.abs(k["h"])
+    g = oracle_geom(oracle, k)
+    c = rounded(k["c"], dtype)
+    clean = oracle.forward(g, c, rounded(k["h"], dtype))
+    G = clean + eta * np.mean(clean) * k["rng"].standard_normal(clean.shape)
+    return k, g, c, rounded(G, dtype)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_reconstruct_matches_oracle(oracle, dtype):
+    k, g, c, G = _fb_case(oracle, (20, 26, 30), 16, 10, dtype)
+    lam, K = 1e-3, 5
+    h_ref, obj_ref, s_ref = oracle.fb(g, c, G, lam, step=0.0, n_iter=K, n_power=20,
+                                      flags=oracle.POSITIVITY | oracle.PRECOND)
+    with gpu_plan(k, dtype) as P:
+        res = P.reconstruct(to_dev(G, dtype), lam, K, step=0.0, n_power=20)
+    tol = 1e-10 if dtype == F64 else 1e-4
+    assert res.step == pytest.approx(s_ref, rel=tol)
+    assert rel_l2(to_np(res.h), h_ref) <= tol
+    assert np.allclose(res.objective, obj_ref, rtol=tol, atol=0)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_reconstruct_masks_and_fixed_step(oracle, dtype):
+    k, g, c, G = _fb_case(oracle, (12, 21, 34), 9, 11, dtype)
+    sup = np.zeros(g.vol_shape, dtype=np.uint8)
+    sup[2:-2, 3:-3, 4:-4] = 1
+    det = np.ones(g.data_shape, dtype=np.uint8)
+    det[:, :, 14:20] = 0
+    h_ref, obj_ref, _ = oracle.fb(g, c, G, 0.05, step=0.02, n_iter=4, flags=oracle.PRECOND,
+                                  support=sup, det_mask=det)
+    with gpu_plan(k, dtype) as P:
+        res = P.reconstruct(to_dev(G, dtype), 0.05, 4, step=0.02, positivity=False,
+                            support=torch.from_numpy(sup).cuda(), det_mask=torch.from_numpy(det).cuda())
+    tol = 1e-10 if dtype == F64 else 1e-4
+    assert res.step == 0.02
+    assert rel_l2(to_np(res.h), h_ref) <= tol
+    assert np.allclose(res.objective, obj_ref, rtol=tol, atol=0)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_reconstruct_resume_is_bitwise_continuous(dtype):
+    # (h, k, s) is the whole state: 2 + 3 iterations from the stored step == 5 iterations
+    k = make_case((10, 16, 20), 12, n_angles=8)
+    G = to_dev(np.abs(k["rng"].standard_normal((8, 10, 20))), dtype)
+    with gpu_plan(k, dtype) as P:
+        full = P.reconstruct(G, 1e-3, 5)
+        part = P.reconstruct(G, 1e-3, 2)
+        part2 = P.reconstruct(G, 1e-3, 3, h0=part.h, use_plan_step=True)
+    assert part2.step == full.step
+    assert torch.equal(part2.h, full.h)
+    assert np.array_equal(np.concatenate([part.objective, part2.objective]), full.objective)
