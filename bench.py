@@ -36,7 +36,63 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1, help="time the oracle on a bounded sample (1/0)")
     ap.add_argument("--naive-stencil", action="store_true")
     ap.add_argument("--seed", type=int, default=3001)
+    ap.add_argument("--mode", default="fb", choices=["fb", "wave", "copy"],
+                    help="fb: the benchmark; wave: only W_T applications (for counter runs); "
+                         "copy: a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--reps", type=int, default=2, help="applications in --mode wave / copies in --mode copy")
     return ap.parse_args()
+
+
+def run_wave_only(args):
+    """Applies W_T `reps` times on the workload (n_t leapfrog launches each) and exits."""
+    import torch
+    import paper_1901_06503_amd as ff
+    import synth
+    import numpy as np
+    dtype = torch.float32 if args.dtype == "float32" else torch.float64
+    r = synth.RECIPES[args.recipe]
+    n = r["n"]
+    dx = synth.grid_spacing(n)
+    c = synth.sound_speed((n, n, n), dx, np.random.default_rng(args.seed), r["bumps"], r["amp"], r["clamp"])
+    plan = ff.Plan(torch.from_numpy(c).to("cuda", dtype), dx, r["T"], synth.uniform_angles(r["n_angles"]),
+                   naive_stencil=args.naive_stencil)
+    h = torch.randn((n, n, n), dtype=dtype, device="cuda")
+    out = torch.empty_like(h)
+    plan.wave(h, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    for _ in range(args.reps):
+        plan.wave(h, out=out, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / (args.reps * plan.nt)
+    nbytes = 4 * (4 if dtype == torch.float32 else 8) * n ** 3
+    env = {k: v for k, v in os.environ.items() if k.startswith("FFPAT_")}
+    print(json.dumps({"mode": "wave", "n": n, "nt": plan.nt, "reps": args.reps, "us_per_launch": us,
+                      "GBps": nbytes / us / 1e3, "bytes_per_launch": nbytes, "env": env}), flush=True)
+
+
+def run_copy_only(args):
+    """Copies a 1 GiB buffer `reps` times (1 GiB read + 1 GiB written per copy)."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for r in range(args.reps):
+        b.copy_(a)
+    e1.record(stream)
+    e1.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / args.reps
+    log(f"{args.reps} copies done")
+    print(json.dumps({"mode": "copy", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n,
+                      "reps": args.reps, "GBps_read_plus_write": 8 * n / s / 1e9}))
 
 
 def log(msg):
@@ -114,6 +170,10 @@ def cpu_baseline(case, plan_nt):
 
 def main():
     args = parse()
+    if args.mode == "wave":
+        return run_wave_only(args)
+    if args.mode == "copy":
+        return run_copy_only(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the sharded design is described in DESIGN.md)"}))

@@ -24,14 +24,24 @@ struct Dims {
 //
 // Backprojector: voxel (i, k) projects to bin position t = b0 + i * bi + k * bk;
 // bin j receives weight w * max(0, 1 - |j - t| * inv_hw), hw = m dx / ds bins.
+//
+// The FP32 kernels step positions in exact 32.32 fixed point (increments are
+// integers, so no rounding accumulates along a ray): ur_fix = ur * 2^32 and
+// the backprojector's b0/bi/bk likewise, in bins.
 struct AngleParams {
   double u0, uj, ur;
   double b0, bi, bk;
   double hw, inv_hw;
   double w;
+  long long ur_fix, b0_fix, bi_fix, bk_fix;
   int major_x;
   int pad_;
 };
+
+// Zero-padded copies read by the projector (line pads) and the backprojector
+// (detector-row pads); the pads are zeroed once and never written again.
+constexpr int kLinePadL = 3, kLinePadR = 3;   // projector lines: [3 zeros | nm values | 3 zeros]
+constexpr int kRowPadL = 2, kRowPadR = 3;     // detector rows:   [2 zeros | ns values | 3 zeros]
 
 enum StepMode : int {
   STEP_FIRST = 0,       // out = p + 1/2 k' S(p)
@@ -55,22 +65,31 @@ hipError_t launch_make_kappa(const Dims &d, const T *c, double dt, double dx, T 
 template <typename T>
 hipError_t launch_c_stats(const Dims &d, const T *c, double *partials, int nblocks, double *stats, hipStream_t s);
 
-// g[a][z][j] = X vol (Joseph ray march).
+// g[a][z][j] = X vol (Joseph ray march).  padN [nz][ny][nx + 6] and padT
+// [nz][nx][ny + 6] receive zero-padded copies of vol's rows and of its x-y
+// transpose (rays running along x read the transpose); need_n / need_t say
+// which copies the angle set uses.
 template <typename T>
-hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *vol, T *g,
-                          hipStream_t s);
+hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *vol, T *padN,
+                          T *padT, bool need_n, bool need_t, T *g, hipStream_t s);
 
-// vol = X^T g, optionally multiplied point-wise by kap (when kap != nullptr).
+// vol = X^T g from detector rows in padded layout gpad [rows][ns + 5]
+// (values at offset 2), optionally multiplied point-wise by kap.
+// two_tap: every angle's footprint half-width m dx / ds is <= 1 bin.
 template <typename T>
-hipError_t launch_backproject(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *g, T *vol,
-                              const T *kap, hipStream_t s);
+hipError_t launch_backproject(const Dims &d, int n_angles, int ns, const AngleParams *ap, bool two_tap,
+                              const T *gpad, T *vol, const T *kap, hipStream_t s);
+
+// Copies rows [rows][ns] into the padded row layout (interior only).
+template <typename T>
+hipError_t launch_pad_rows(int rows, int ns, const T *g, T *gpad, hipStream_t s);
 
 // r = mask * (g - G) (G may be null, mask may be null); y = mask * Lambda r (or
-// y = r when taps == nullptr).  y may alias g.  row_partials[row] = sum_j r_j y_j
-// when non-null.
+// y = r when taps == nullptr), written at y[row * y_stride + y_off + j].  y may
+// alias g (same layout).  row_partials[row] = sum_j r_j y_j when non-null.
 template <typename T>
 hipError_t launch_residual_ramp(int rows, int ns, const T *g, const T *G, const uint8_t *mask, const T *taps,
-                                T *y, double *row_partials, hipStream_t s);
+                                T *y, int y_stride, int y_off, double *row_partials, hipStream_t s);
 
 // Reductions and element-wise updates (FP64 partials, fixed order).
 constexpr int kReduceBlocks = 1024;

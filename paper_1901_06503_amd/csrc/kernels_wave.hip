@@ -86,27 +86,39 @@ __device__ __forceinline__ T ld3(const T *__restrict__ p, int x, int y, int z, i
   return (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) ? p[((size_t)z * ny + y) * nx + x] : T(0);
 }
 
-template <typename T, int NDIM, int MODE, int RY>
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p, bool nt)
+{
+  return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+template <typename T, int NDIM, int MODE, int RY, bool NT>
 __global__ void __launch_bounds__(256)
 wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__restrict__ kap, int nx, int ny, int nz,
-                  int zchunk, int tiles_x, int tiles_y, int n_tiles)
+                  int zchunk, int tiles_x, int tiles_y, int n_tiles, int xy_fastest)
 {
   constexpr int BX = 64, TYN = 4, BY = TYN * RY;
   constexpr int LW = BX + 4, LH = BY + 4;
   __shared__ T lds[2][LH * LW];
 
   // XCD-aware tile order: consecutive work-groups are dealt round-robin to
-  // the 8 XCDs; give each XCD a contiguous range of tiles (z-chunk fastest)
-  // so that neighbouring tiles share that XCD's L2.
+  // the 8 XCDs; give each XCD a contiguous range of tiles (x-y tiles or
+  // z-chunks fastest within it) so that neighbouring tiles share that XCD's L2.
   const int b = blockIdx.x;
   const int per_xcd = (n_tiles + 7) / 8;
   const int t = (b % 8) * per_xcd + b / 8;
   if (t >= n_tiles) return;                      // whole group exits together
   const int n_zc = (nz + zchunk - 1) / zchunk;
-  const int zc = t % n_zc;
-  const int txy = t / n_zc;
+  int zc, txy;
+  if (xy_fastest) {
+    const int n_xy = tiles_x * tiles_y;
+    txy = t % n_xy;
+    zc = t / n_xy;
+  } else {
+    zc = t % n_zc;
+    txy = t / n_zc;
+  }
   const int bxi = txy % tiles_x, byi = txy / tiles_x;
-  (void)tiles_y;
 
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int x0 = bxi * BX, y0 = byi * BY;
@@ -155,8 +167,8 @@ wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__res
       const size_t idx = (size_t)z * plane + (size_t)y * nx + x;
       // 3D: plane z+3 enters the window; 2D: the next centre plane z+1
       nxt[r] = ld3(p, x, y, NDIM == 3 ? z + 3 : z + 1, nx, ny, nz);
-      kv[r] = in ? kap[idx] : T(1);
-      pv[r] = (in && (MODE == STEP_LEAP || MODE == STEP_LEAP_DIV)) ? prev[idx] : T(0);
+      kv[r] = in ? ld_stream(kap + idx, NT) : T(1);
+      pv[r] = (in && (MODE == STEP_LEAP || MODE == STEP_LEAP_DIV)) ? ld_stream(prev + idx, NT) : T(0);
     }
     __syncthreads();
 #pragma unroll
@@ -175,7 +187,11 @@ wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__res
       if (MODE == STEP_FIRST || MODE == STEP_FIRST_DIV) v = c0 + T(0.5) * kv[r] * S;
       else v = T(2) * c0 - pv[r] + kv[r] * S;
       if (MODE == STEP_FIRST_DIV || MODE == STEP_LEAP_DIV) v = v / kv[r];
-      if (x < nx && y < ny) out[(size_t)z * plane + (size_t)y * nx + x] = v;
+      if (x < nx && y < ny) {
+        T *o = out + (size_t)z * plane + (size_t)y * nx + x;
+        if (NT) __builtin_nontemporal_store(v, o);
+        else *o = v;
+      }
     }
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -195,45 +211,67 @@ wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__res
 // Tunables of the blocked kernel (set once per process from the environment
 // for sweeps; the defaults are the measured best on MI355X).
 struct BlockedConfig {
-  int ry = 4;        // rows per thread: tile height 4 * ry
+  int ry = 2;        // rows per thread: tile height 4 * ry
   int zchunk = 0;    // planes per work-group; 0 = choose from the grid size
+  int order = 1;     // 1: x-y tiles fastest within an XCD's range; 0: z-chunks fastest
+  int groups = 2048; // target work-group count when zchunk = 0
+  int nt = 0;        // non-temporal loads of p(k-1), k' and stores of p(k+1)
 };
 
-static BlockedConfig blocked_config()
+static BlockedConfig blocked_config(const Dims &d)
 {
-  static BlockedConfig cfg = [] {
+  // default tile height: 8 rows up to 256-wide grids, 16 rows beyond (fewer
+  // halo re-reads once the fields no longer fit in the 256 MB MALL)
+  static BlockedConfig env = [] {
     BlockedConfig c;
+    c.ry = 0;
     if (const char *e = getenv("FFPAT_STENCIL_RY")) c.ry = atoi(e);
     if (const char *e = getenv("FFPAT_STENCIL_ZCHUNK")) c.zchunk = atoi(e);
-    if (c.ry != 2 && c.ry != 4 && c.ry != 8) c.ry = 4;
+    if (const char *e = getenv("FFPAT_STENCIL_ORDER")) c.order = atoi(e) ? 1 : 0;
+    if (const char *e = getenv("FFPAT_STENCIL_GROUPS")) c.groups = atoi(e) > 0 ? atoi(e) : 2048;
+    if (const char *e = getenv("FFPAT_STENCIL_NT")) c.nt = atoi(e) ? 1 : 0;
+    if (c.ry != 0 && c.ry != 1 && c.ry != 2 && c.ry != 4 && c.ry != 8) c.ry = 0;
     if (c.zchunk < 0) c.zchunk = 0;
     return c;
   }();
+  BlockedConfig cfg = env;
+  if (cfg.ry == 0) cfg.ry = d.ny > 256 ? 4 : 2;
   return cfg;
 }
 
 template <typename T, int NDIM, int RY>
 static hipError_t blocked_dispatch(StepMode mode, const Dims &d, const T *p, const T *prev, T *out, const T *kap,
-                                   int zchunk, hipStream_t s)
+                                   const BlockedConfig &cfg, hipStream_t s)
 {
   constexpr int BY = 4 * RY;
   const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + BY - 1) / BY;
+  int zchunk = cfg.zchunk;
+  const int xyf = cfg.order;
   if (zchunk <= 0) {
-    // aim at >= 2048 work-groups (8 per CU), at least 4 planes per group
+    // about cfg.groups work-groups, 4..16 planes per group (measured on MI355X:
+    // longer chunks lose parallelism, shorter ones re-read more z halo)
     const long xy = (long)tiles_x * tiles_y;
-    long want_zc = (2048 + xy - 1) / xy;
-    int zc = (int)((d.nz + want_zc - 1) / want_zc);
-    zchunk = zc < 4 ? 4 : zc;
+    const long zc = (long)d.nz * xy / cfg.groups;
+    zchunk = (int)(zc < 4 ? 4 : (zc > 16 ? 16 : zc));
   }
   if (zchunk > d.nz) zchunk = d.nz;
   const int n_zc = (d.nz + zchunk - 1) / zchunk;
   const int n_tiles = tiles_x * tiles_y * n_zc;
   const int grid = ((n_tiles + 7) / 8) * 8;
-  switch (mode) {
-    case STEP_FIRST: wave_step_blocked<T, NDIM, STEP_FIRST, RY><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles); break;
-    case STEP_LEAP: wave_step_blocked<T, NDIM, STEP_LEAP, RY><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles); break;
-    case STEP_FIRST_DIV: wave_step_blocked<T, NDIM, STEP_FIRST_DIV, RY><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles); break;
-    case STEP_LEAP_DIV: wave_step_blocked<T, NDIM, STEP_LEAP_DIV, RY><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles); break;
+  if (cfg.nt) {
+    switch (mode) {
+      case STEP_FIRST: wave_step_blocked<T, NDIM, STEP_FIRST, RY, true><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles, xyf); break;
+      case STEP_LEAP: wave_step_blocked<T, NDIM, STEP_LEAP, RY, true><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles, xyf); break;
+      case STEP_FIRST_DIV: wave_step_blocked<T, NDIM, STEP_FIRST_DIV, RY, true><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles, xyf); break;
+      case STEP_LEAP_DIV: wave_step_blocked<T, NDIM, STEP_LEAP_DIV, RY, true><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles, xyf); break;
+    }
+  } else {
+    switch (mode) {
+      case STEP_FIRST: wave_step_blocked<T, NDIM, STEP_FIRST, RY, false><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles, xyf); break;
+      case STEP_LEAP: wave_step_blocked<T, NDIM, STEP_LEAP, RY, false><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles, xyf); break;
+      case STEP_FIRST_DIV: wave_step_blocked<T, NDIM, STEP_FIRST_DIV, RY, false><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles, xyf); break;
+      case STEP_LEAP_DIV: wave_step_blocked<T, NDIM, STEP_LEAP_DIV, RY, false><<<grid, 256, 0, s>>>(p, prev, out, kap, d.nx, d.ny, d.nz, zchunk, tiles_x, tiles_y, n_tiles, xyf); break;
+    }
   }
   return hipGetLastError();
 }
@@ -242,11 +280,12 @@ template <typename T, int NDIM>
 static hipError_t blocked_select(StepMode mode, const Dims &d, const T *p, const T *prev, T *out, const T *kap,
                                  hipStream_t s)
 {
-  const BlockedConfig cfg = blocked_config();
+  const BlockedConfig cfg = blocked_config(d);
   switch (cfg.ry) {
-    case 2: return blocked_dispatch<T, NDIM, 2>(mode, d, p, prev, out, kap, cfg.zchunk, s);
-    case 8: return blocked_dispatch<T, NDIM, 8>(mode, d, p, prev, out, kap, cfg.zchunk, s);
-    default: return blocked_dispatch<T, NDIM, 4>(mode, d, p, prev, out, kap, cfg.zchunk, s);
+    case 1: return blocked_dispatch<T, NDIM, 1>(mode, d, p, prev, out, kap, cfg, s);
+    case 4: return blocked_dispatch<T, NDIM, 4>(mode, d, p, prev, out, kap, cfg, s);
+    case 8: return blocked_dispatch<T, NDIM, 8>(mode, d, p, prev, out, kap, cfg, s);
+    default: return blocked_dispatch<T, NDIM, 2>(mode, d, p, prev, out, kap, cfg, s);
   }
 }
 

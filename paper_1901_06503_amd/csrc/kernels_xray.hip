@@ -11,98 +11,260 @@ namespace ffpat {
 
 // ---------------------------------------------------------------------------
 // Projector: one thread per detector bin (a, z, j), coalesced writes along s.
+// Rays march over rows (|cos| >= |sin|) or columns (|sin| > |cos|); for the
+// latter the plane is read from its transposed copy, so in both cases the two
+// taps of a lane sit in one contiguous line and neighbouring bins read
+// neighbouring addresses.  Lines carry 3 zeros on each side: every crossing
+// u of the marched range lies in [-2, nm + 1], so no tap needs a bounds check.
+// Work order: angles fastest, then planes; each XCD owns a contiguous range
+// of planes, so a plane (and its transpose) is fetched into one L2 and reused
+// by every angle.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
-project_kernel(const T *__restrict__ vol, T *__restrict__ g, const AngleParams *__restrict__ ap, int nx, int ny,
-               int nz, int ns)
+pad_planes_kernel(const T *__restrict__ v, T *__restrict__ padN, T *__restrict__ padT, int nx, int ny, int need_n,
+                  int need_t)
 {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int z = blockIdx.y;
-  const int a = blockIdx.z;
-  if (j >= ns) return;
-  const AngleParams P = ap[a];
-  const T *plane = vol + (size_t)z * nx * ny;
-  int nr, nm;
-  size_t sr, sm;
-  if (P.major_x) {  // march over columns x_r, interpolate along y
-    nr = nx; nm = ny; sr = 1; sm = (size_t)nx;
-  } else {          // march over rows y_r, interpolate along x
-    nr = ny; nm = nx; sr = (size_t)nx; sm = 1;
+  __shared__ T tile[32][33];
+  const int z = blockIdx.z;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+  const T *src = v + (size_t)z * nx * ny;
+  const int LPx = nx + kLinePadL + kLinePadR, LPy = ny + kLinePadL + kLinePadR;
+  T *dn = padN + (size_t)z * ny * LPx + kLinePadL;
+  T *dt = padT + (size_t)z * nx * LPy + kLinePadL;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int y = y0 + r, x = x0 + tx;
+    if (x < nx && y < ny) {
+      const T val = src[(size_t)y * nx + x];
+      tile[r][tx] = val;
+      if (need_n) dn[(size_t)y * LPx + x] = val;
+    }
   }
+  if (!need_t) return;
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int x = x0 + r, y = y0 + tx;
+    if (x < nx && y < ny) dt[(size_t)x * LPy + y] = tile[tx][r];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+project_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__restrict__ g,
+               const AngleParams *__restrict__ ap, int nx, int ny, int nz, int ns, int n_angles, int n_work)
+{
+  const int b = blockIdx.x;
+  const int per_xcd = (n_work + 7) / 8;
+  const int t = (b % 8) * per_xcd + b / 8;
+  if (t >= n_work) return;
+  const int a = t % n_angles;
+  const int rest = t / n_angles;
+  const int z = rest % nz;
+  const int jb = rest / nz;
+  const int j = jb * 256 + threadIdx.x;
+  if (j >= ns) return;
+
+  const AngleParams P = ap[a];
+  // padded plane (index 0 = first pad) of the marched orientation; block-uniform
+  int nr, nm;
+  const char *plane;
+  if (P.major_x) {  // march over columns x_r (rows of the transpose), interpolate along y
+    nr = nx; nm = ny;
+    plane = reinterpret_cast<const char *>(padT + (size_t)z * nx * (ny + kLinePadL + kLinePadR));
+  } else {          // march over rows y_r, interpolate along x
+    nr = ny; nm = nx;
+    plane = reinterpret_cast<const char *>(padN + (size_t)z * ny * (nx + kLinePadL + kLinePadR));
+  }
+  const unsigned LPB = (unsigned)((nm + kLinePadL + kLinePadR) * sizeof(T));   // line pitch in bytes
   const double A = P.u0 + (double)j * P.uj;
-  // marched lines whose crossing u lies in (-1, nm), where a tap can be inside
+  // marched lines whose crossing lies in (-1, nm) (where a tap is inside), widened
+  // by one line on each side; |ur| <= 1 keeps the crossings within [-2, nm + 1]
   double lo = 0.0, hi = (double)(nr - 1);
   if (P.ur != 0.0) {
     double r_a = (-1.0 - A) / P.ur, r_b = ((double)nm - A) / P.ur;
-    if (r_a > r_b) { double t = r_a; r_a = r_b; r_b = t; }
+    if (r_a > r_b) { double tt = r_a; r_a = r_b; r_b = tt; }
     lo = fmin(fmax(lo, floor(r_a)), (double)nr);   // clamped before any int conversion
     hi = fmax(fmin(hi, ceil(r_b)), -1.0);
   } else if (!(A > -1.0 && A < (double)nm)) {
     hi = -1.0;
   }
+  const int r0 = (int)lo, r1 = (int)hi;
+  // 32-bit byte offsets from the uniform plane base keep the address math to
+  // one add per tap pair (the second tap is the same offset + sizeof(T))
+  unsigned rowb = (unsigned)r0 * LPB;
   T acc = T(0);
-  for (int r = (int)lo; r <= (int)hi; ++r) {
-    const double u = fma((double)r, P.ur, A);
-    const double fl = floor(u);
-    const int i0 = (int)fl;
-    const T f = (T)(u - fl);
-    const T *line = plane + (size_t)r * sr;
-    const T v0 = (i0 >= 0 && i0 < nm) ? line[(size_t)i0 * sm] : T(0);
-    const T v1 = (i0 + 1 >= 0 && i0 + 1 < nm) ? line[(size_t)(i0 + 1) * sm] : T(0);
-    acc += (T(1) - f) * v0 + f * v1;
+  if (sizeof(T) == 4) {
+    // exact fixed-point stepping: u(r) = U / 2^32, U += ur_fix per line
+    long long U = llrint(fma((double)r0, P.ur, A) * 4294967296.0);
+    const long long UR = P.ur_fix;
+#pragma unroll 8
+    for (int r = r0; r <= r1; ++r) {
+      const unsigned off = rowb + (unsigned)(((int)(U >> 32) + kLinePadL) * (int)sizeof(T));
+      const T f = (T)(unsigned)(U & 0xffffffffLL) * T(2.3283064365386963e-10);
+      const T v0 = *reinterpret_cast<const T *>(plane + off);
+      const T v1 = *reinterpret_cast<const T *>(plane + off + sizeof(T));
+      acc += v0 + f * (v1 - v0);
+      U += UR;
+      rowb += LPB;
+    }
+  } else {
+#pragma unroll 4
+    for (int r = r0; r <= r1; ++r) {
+      const double u = fma((double)r, P.ur, A);
+      const double fl = floor(u);
+      const unsigned off = rowb + (unsigned)(((int)fl + kLinePadL) * (int)sizeof(T));
+      const T f = (T)(u - fl);
+      const T v0 = *reinterpret_cast<const T *>(plane + off);
+      const T v1 = *reinterpret_cast<const T *>(plane + off + sizeof(T));
+      acc += v0 + f * (v1 - v0);
+      rowb += LPB;
+    }
   }
   g[((size_t)a * nz + z) * ns + j] = acc * (T)P.w;
 }
 
 template <typename T>
-hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *vol, T *g,
-                          hipStream_t s)
+hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *vol, T *padN,
+                          T *padT, bool need_n, bool need_t, T *g, hipStream_t s)
 {
+  dim3 pgrid((d.nx + 31) / 32, (d.ny + 31) / 32, d.nz);
+  pad_planes_kernel<T><<<pgrid, 256, 0, s>>>(vol, padN, padT, d.nx, d.ny, need_n ? 1 : 0, need_t ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int jblocks = (ns + 255) / 256;
+  const long n_work = (long)jblocks * d.nz * n_angles;
+  const long grid = (n_work + 7) / 8 * 8;
   const int tb = ns >= 256 ? 256 : ((ns + 63) / 64) * 64;
-  dim3 grid((ns + tb - 1) / tb, d.nz, n_angles);
-  project_kernel<T><<<grid, tb, 0, s>>>(vol, g, ap, d.nx, d.ny, d.nz, ns);
+  project_kernel<T><<<(unsigned)grid, tb, 0, s>>>(padN, padT, g, ap, d.nx, d.ny, d.nz, ns, n_angles, (int)n_work);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Backprojector: one thread per voxel, loop over angles, <= 2 taps per angle
-// when ds = dx (the footprint half-width m dx / ds is at most one bin).
+// Backprojector: one thread per 4 voxels (i, k + 4q) of a 64 x 16 tile in a
+// plane, loop over angles, reading detector rows in the padded layout.
+// With ds >= m dx for every angle (e.g. ds = dx) the footprint covers at most
+// the bins floor(t) and floor(t) + 1: FP32 steps t in 32.32 fixed point and
+// clamps the bin to [-2, ns + 1], where the pads (zeros) absorb voxels that
+// project off the detector; FP64 evaluates t in double.  Otherwise every bin
+// within the half-width is visited.  Tiles of one plane are consecutive on
+// one XCD so the plane's detector rows stay in L2.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool TWO_TAP>
 __global__ void __launch_bounds__(256)
-backproject_kernel(const T *__restrict__ g, T *__restrict__ vol, const AngleParams *__restrict__ ap, int n_angles,
-                   int nx, int ny, int nz, int ns, const T *__restrict__ kap)
+backproject_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const AngleParams *__restrict__ ap, int n_angles,
+                   int nx, int ny, int nz, int ns, const T *__restrict__ kap, int tiles_x, int tiles_y, int n_work)
 {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int k = blockIdx.y * 4 + threadIdx.y;
-  const int z = blockIdx.z;
-  if (i >= nx || k >= ny) return;
-  T acc = T(0);
+  constexpr int RY = 4;
+  const int b = blockIdx.x;
+  const int per_xcd = (n_work + 7) / 8;
+  const int tw = (b % 8) * per_xcd + b / 8;
+  if (tw >= n_work) return;
+  const int bx = tw % tiles_x;
+  const int rest = tw / tiles_x;
+  const int by = rest % tiles_y;
+  const int z = rest / tiles_y;
+  const int i = bx * 64 + (threadIdx.x & 63);
+  const int k0 = by * 16 + (threadIdx.x >> 6);
+  if (i >= nx) return;
+
+  const int RS = ns + kRowPadL + kRowPadR;
+  T acc[RY];
+#pragma unroll
+  for (int q = 0; q < RY; ++q) acc[q] = T(0);
+  // detector row of (a, z) = uniform base; lanes add 32-bit byte offsets
+  const char *gz = reinterpret_cast<const char *>(gpad + (size_t)z * RS);
+  const size_t astride = (size_t)nz * RS * sizeof(T);
+#pragma unroll 2
   for (int a = 0; a < n_angles; ++a) {
     const AngleParams &P = ap[a];
-    const double t = P.b0 + (double)i * P.bi + (double)k * P.bk;
-    const T *row = g + ((size_t)a * nz + z) * ns;
-    const int jlo = (int)fmin(fmax(ceil(t - P.hw), 0.0), (double)ns);
-    const int jhi = (int)fmax(fmin(floor(t + P.hw), (double)(ns - 1)), -1.0);
-    T sum = T(0);
-    for (int j = jlo; j <= jhi; ++j) {
-      const double wt = 1.0 - fabs((double)j - t) * P.inv_hw;
-      if (wt > 0.0) sum += (T)wt * row[j];
+    const char *row = gz + (size_t)a * astride;
+    if (TWO_TAP && sizeof(T) == 4) {
+      const long long T0 = P.b0_fix + (long long)i * P.bi_fix + (long long)k0 * P.bk_fix;
+      const long long BK4 = 4 * P.bk_fix;
+      const T ih = (T)P.inv_hw, wa = (T)P.w;
+#pragma unroll
+      for (int q = 0; q < RY; ++q) {
+        const long long Tq = T0 + (long long)q * BK4;
+        const int j0 = min(max((int)(Tq >> 32), -2), ns + 1);
+        const unsigned off = (unsigned)((j0 + kRowPadL) * (int)sizeof(T));
+        const T f = (T)(unsigned)(Tq & 0xffffffffLL) * T(2.3283064365386963e-10);
+        const T w0 = fmax(T(1) - f * ih, T(0));
+        const T w1 = fmax(T(1) - (T(1) - f) * ih, T(0));
+        const T v0 = *reinterpret_cast<const T *>(row + off);
+        const T v1 = *reinterpret_cast<const T *>(row + off + sizeof(T));
+        acc[q] += wa * (w0 * v0 + w1 * v1);
+      }
+    } else {
+      const T *rowt = reinterpret_cast<const T *>(row) + kRowPadL;
+      const double t0 = P.b0 + (double)i * P.bi + (double)k0 * P.bk;
+#pragma unroll
+      for (int q = 0; q < RY; ++q) {
+        const double t = fma((double)(4 * q), P.bk, t0);
+        if (TWO_TAP) {
+          const double fl = fmin(fmax(floor(t), -2.0), (double)(ns + 1));
+          const unsigned off = (unsigned)(((int)fl + kRowPadL) * (int)sizeof(T));
+          const T f = (T)(t - fl);
+          const T ih = (T)P.inv_hw;
+          // a clamped bin reads two pads, so the weights do not matter there
+          const T w0 = fmax(T(1) - f * ih, T(0));
+          const T w1 = fmax(T(1) - (T(1) - f) * ih, T(0));
+          const T v0 = *reinterpret_cast<const T *>(row + off);
+          const T v1 = *reinterpret_cast<const T *>(row + off + sizeof(T));
+          acc[q] += (T)P.w * (w0 * v0 + w1 * v1);
+        } else {
+          const int jlo = (int)fmin(fmax(ceil(t - P.hw), 0.0), (double)ns);
+          const int jhi = (int)fmax(fmin(floor(t + P.hw), (double)(ns - 1)), -1.0);
+          T sum = T(0);
+          for (int j = jlo; j <= jhi; ++j) {
+            const double wt = 1.0 - fabs((double)j - t) * P.inv_hw;
+            if (wt > 0.0) sum += (T)wt * rowt[j];
+          }
+          acc[q] += sum * (T)P.w;
+        }
+      }
     }
-    acc += sum * (T)P.w;
   }
-  const size_t idx = ((size_t)z * ny + k) * nx + i;
-  vol[idx] = kap ? acc * kap[idx] : acc;
+#pragma unroll
+  for (int q = 0; q < RY; ++q) {
+    const int k = k0 + 4 * q;
+    if (k < ny) {
+      const size_t idx = ((size_t)z * ny + k) * nx + i;
+      vol[idx] = kap ? acc[q] * kap[idx] : acc[q];
+    }
+  }
 }
 
 template <typename T>
-hipError_t launch_backproject(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *g, T *vol,
-                              const T *kap, hipStream_t s)
+hipError_t launch_backproject(const Dims &d, int n_angles, int ns, const AngleParams *ap, bool two_tap,
+                              const T *gpad, T *vol, const T *kap, hipStream_t s)
 {
-  dim3 block(64, 4, 1);
-  dim3 grid((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
-  backproject_kernel<T><<<grid, block, 0, s>>>(g, vol, ap, n_angles, d.nx, d.ny, d.nz, ns, kap);
+  const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + 15) / 16;
+  const long n_work = (long)tiles_x * tiles_y * d.nz;
+  const long grid = (n_work + 7) / 8 * 8;
+  if (two_tap)
+    backproject_kernel<T, true><<<(unsigned)grid, 256, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns, kap,
+                                                                tiles_x, tiles_y, (int)n_work);
+  else
+    backproject_kernel<T, false><<<(unsigned)grid, 256, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns, kap,
+                                                                 tiles_x, tiles_y, (int)n_work);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void pad_rows_kernel(const T *__restrict__ g, T *__restrict__ gpad, int ns, size_t n)
+{
+  const int RS = ns + kRowPadL + kRowPadR;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t row = e / ns, j = e - row * ns;
+    gpad[row * RS + kRowPadL + j] = g[e];
+  }
+}
+
+template <typename T>
+hipError_t launch_pad_rows(int rows, int ns, const T *g, T *gpad, hipStream_t s)
+{
+  pad_rows_kernel<T><<<2048, 256, 0, s>>>(g, gpad, ns, (size_t)rows * ns);
   return hipGetLastError();
 }
 
@@ -114,7 +276,7 @@ hipError_t launch_backproject(const Dims &d, int n_angles, int ns, const AnglePa
 template <typename T>
 __global__ void __launch_bounds__(256)
 residual_ramp_kernel(const T *g, const T *__restrict__ G, const uint8_t *__restrict__ mask,
-                     const T *__restrict__ taps, T *y, int ns, double *row_partials)
+                     const T *__restrict__ taps, T *y, int ns, int y_stride, int y_off, double *row_partials)
 {
   extern __shared__ unsigned char smem_raw[];
   T *r = reinterpret_cast<T *>(smem_raw);
@@ -143,7 +305,7 @@ residual_ramp_kernel(const T *g, const T *__restrict__ G, const uint8_t *__restr
       acc = r[j];
     }
     if (mask && !mask[base + j]) acc = T(0);
-    y[base + j] = acc;
+    y[row * (size_t)y_stride + y_off + j] = acc;
     part += (double)r[j] * (double)acc;
   }
   if (row_partials) {
@@ -159,20 +321,21 @@ residual_ramp_kernel(const T *g, const T *__restrict__ G, const uint8_t *__restr
 
 template <typename T>
 hipError_t launch_residual_ramp(int rows, int ns, const T *g, const T *G, const uint8_t *mask, const T *taps, T *y,
-                                double *row_partials, hipStream_t s)
+                                int y_stride, int y_off, double *row_partials, hipStream_t s)
 {
   const size_t shmem = (size_t)ns * sizeof(T);
-  residual_ramp_kernel<T><<<rows, 256, shmem, s>>>(g, G, mask, taps, y, ns, row_partials);
+  residual_ramp_kernel<T><<<rows, 256, shmem, s>>>(g, G, mask, taps, y, ns, y_stride, y_off, row_partials);
   return hipGetLastError();
 }
 
 #define FFPAT_INST(T)                                                                                         \
-  template hipError_t launch_project<T>(const Dims &, int, int, const AngleParams *, const T *, T *,         \
-                                        hipStream_t);                                                        \
-  template hipError_t launch_backproject<T>(const Dims &, int, int, const AngleParams *, const T *, T *,     \
+  template hipError_t launch_project<T>(const Dims &, int, int, const AngleParams *, const T *, T *, T *, bool, \
+                                        bool, T *, hipStream_t);                                             \
+  template hipError_t launch_backproject<T>(const Dims &, int, int, const AngleParams *, bool, const T *, T *, \
                                             const T *, hipStream_t);                                         \
+  template hipError_t launch_pad_rows<T>(int, int, const T *, T *, hipStream_t);                             \
   template hipError_t launch_residual_ramp<T>(int, int, const T *, const T *, const uint8_t *, const T *, T *, \
-                                              double *, hipStream_t);
+                                              int, int, double *, hipStream_t);
 FFPAT_INST(float)
 FFPAT_INST(double)
 #undef FFPAT_INST

@@ -73,7 +73,10 @@ struct DeviceGuard {
 };
 
 struct Layout {
-  size_t kap, vol[4], dat, taps, ap, partials, scalars, total;
+  size_t kap, vol[4], dat, taps, ap, partials, scalars;
+  size_t padN, padT, padD;              // zero-padded copies for the projector / backprojector
+  size_t padN_bytes, padT_bytes, padD_bytes;
+  size_t total;
   size_t n_partials;
 };
 
@@ -97,11 +100,17 @@ struct ffpat_plan {
   double *obj = nullptr;  // objective history (device), capacity obj_cap
   int obj_cap = 0;
   bool has_step = false;
+  bool two_tap = true;    // every footprint half-width m dx / ds <= 1 bin
+  bool need_n = false;    // some angle marches rows (reads the padded plane)
+  bool need_t = false;    // some angle marches columns (reads the padded transpose)
 
   void *vol(int i) const { return base + lay.vol[i]; }
   void *kap() const { return base + lay.kap; }
   void *dat() const { return base + lay.dat; }
   void *taps() const { return base + lay.taps; }
+  void *padN() const { return base + lay.padN; }
+  void *padT() const { return base + lay.padT; }
+  void *padD() const { return base + lay.padD; }
   AngleParams *ap() const { return reinterpret_cast<AngleParams *>(base + lay.ap); }
   double *partials() const { return reinterpret_cast<double *>(base + lay.partials); }
   double *scalars() const { return reinterpret_cast<double *>(base + lay.scalars); }
@@ -141,6 +150,10 @@ int resolve(const ffpat_geom *g, Resolved *r)
   const size_t nvox = (size_t)g->nx * g->ny * g->nz;
   const size_t ndat = (size_t)g->n_angles * g->nz * ns;
   if (nvox > ((size_t)1 << 33) || ndat > ((size_t)1 << 33)) return fail(FFPAT_EINVAL, "problem too large");
+  // work-group counts of the projector / backprojector grids must fit in int
+  if ((size_t)g->n_angles * g->nz * (size_t)((ns + 255) / 256) > (size_t)INT32_MAX - 8 ||
+      (size_t)((g->nx + 63) / 64) * ((g->ny + 15) / 16) * g->nz > (size_t)INT32_MAX - 8)
+    return fail(FFPAT_EINVAL, "problem too large for one launch");
   r->d = Dims{g->nx, g->ny, g->nz, ndim};
   r->dtype = g->dtype;
   r->n_angles = g->n_angles;
@@ -169,6 +182,12 @@ Layout layout(const Resolved &r)
   L.n_partials = rows > (size_t)3 * kReduceBlocks ? rows : (size_t)3 * kReduceBlocks;
   L.partials = off; off = align_up(off + L.n_partials * sizeof(double));
   L.scalars = off; off = align_up(off + SC_COUNT * sizeof(double));
+  L.padN_bytes = (size_t)r.d.nz * r.d.ny * (r.d.nx + kLinePadL + kLinePadR) * esz;
+  L.padT_bytes = (size_t)r.d.nz * r.d.nx * (r.d.ny + kLinePadL + kLinePadR) * esz;
+  L.padD_bytes = rows * (size_t)(r.ns + kRowPadL + kRowPadR) * esz;
+  L.padN = off; off = align_up(off + L.padN_bytes);
+  L.padT = off; off = align_up(off + L.padT_bytes);
+  L.padD = off; off = align_up(off + L.padD_bytes);
   L.total = off;
   return L;
 }
@@ -200,6 +219,11 @@ AngleParams angle_params(double phi, const Resolved &r)
   P.b0 = cs - cx * dx * ca / ds - cy * dx * sa / ds;
   P.hw = m * dx / ds;
   P.inv_hw = 1.0 / P.hw;
+  const double two32 = 4294967296.0;
+  P.ur_fix = std::llrint(P.ur * two32);
+  P.b0_fix = std::llrint(P.b0 * two32);
+  P.bi_fix = std::llrint(P.bi * two32);
+  P.bk_fix = std::llrint(P.bk * two32);
   return P;
 }
 
@@ -270,24 +294,50 @@ int wave_adjoint_op(ffpat_plan *P, const T *g, T *q, hipStream_t s)
 }
 
 template <typename T>
+hipError_t project(ffpat_plan *P, const T *vol, T *g, hipStream_t s)
+{
+  return launch_project<T>(P->d, P->n_angles, P->ns, P->ap(), vol, static_cast<T *>(P->padN()),
+                           static_cast<T *>(P->padT()), P->need_n, P->need_t, g, s);
+}
+
+template <typename T>
+hipError_t backproject_op(ffpat_plan *P, const T *g, T *vol, hipStream_t s)
+{
+  hipError_t e = launch_pad_rows<T>(P->rows, P->ns, g, static_cast<T *>(P->padD()), s);
+  if (e != hipSuccess) return e;
+  return launch_backproject<T>(P->d, P->n_angles, P->ns, P->ap(), P->two_tap, static_cast<const T *>(P->padD()),
+                               vol, nullptr, s);
+}
+
+template <typename T>
 int op_forward(ffpat_plan *P, const T *h, T *g, hipStream_t s)
 {
   T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1));
   int rc = wave_forward<T>(P, h, V2, V1, s);
   if (rc) return rc;
-  HIP_TRY(launch_project<T>(P->d, P->n_angles, P->ns, P->ap(), V2, g, s));
+  HIP_TRY(project<T>(P, V2, g, s));
   return FFPAT_OK;
+}
+
+// h = A^T y for y already in the padded row buffer.
+template <typename T>
+int op_adjoint_padded(ffpat_plan *P, T *h, hipStream_t s)
+{
+  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1));
+  HIP_TRY(launch_backproject<T>(P->d, P->n_angles, P->ns, P->ap(), P->two_tap, static_cast<const T *>(P->padD()),
+                                V1, static_cast<const T *>(P->kap()), s));
+  return wave_adjoint_from_scaled<T>(P, V1, h, V2, s);
 }
 
 template <typename T>
 int op_adjoint(ffpat_plan *P, const T *g, T *h, hipStream_t s)
 {
-  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1));
-  HIP_TRY(launch_backproject<T>(P->d, P->n_angles, P->ns, P->ap(), g, V1, static_cast<const T *>(P->kap()), s));
-  return wave_adjoint_from_scaled<T>(P, V1, h, V2, s);
+  HIP_TRY(launch_pad_rows<T>(P->rows, P->ns, g, static_cast<T *>(P->padD()), s));
+  return op_adjoint_padded<T>(P, h, s);
 }
 
-// y = chi Lambda chi (A v) or chi (A v - G): the data-space part of one iteration.
+// y = chi Lambda chi (A v - G) (G may be null), written into the padded row
+// buffer that the backprojector reads: the data-space part of one iteration.
 template <typename T>
 int data_residual(ffpat_plan *P, const T *v, const T *G, const uint8_t *mask, bool precond, double *row_partials,
                   hipStream_t s)
@@ -296,7 +346,8 @@ int data_residual(ffpat_plan *P, const T *v, const T *G, const uint8_t *mask, bo
   int rc = op_forward<T>(P, v, D, s);
   if (rc) return rc;
   HIP_TRY(launch_residual_ramp<T>(P->rows, P->ns, D, G, mask, precond ? static_cast<const T *>(P->taps()) : nullptr,
-                                  D, row_partials, s));
+                                  static_cast<T *>(P->padD()), P->ns + kRowPadL + kRowPadR, kRowPadL, row_partials,
+                                  s));
   return FFPAT_OK;
 }
 
@@ -304,13 +355,12 @@ template <typename T>
 int power_iteration(ffpat_plan *P, int n_power, bool precond, const uint8_t *mask, hipStream_t s)
 {
   T *V3 = static_cast<T *>(P->vol(2)), *V4 = static_cast<T *>(P->vol(3));
-  T *D = static_cast<T *>(P->dat());
   double *sc = P->scalars();
   HIP_TRY(launch_fill<T>(V4, P->nvox, 1.0 / std::sqrt((double)P->nvox), s));
   for (int it = 0; it < n_power; ++it) {
     int rc = data_residual<T>(P, V4, nullptr, mask, precond, nullptr, s);
     if (rc) return rc;
-    rc = op_adjoint<T>(P, D, V3, s);
+    rc = op_adjoint_padded<T>(P, V3, s);
     if (rc) return rc;
     HIP_TRY(launch_sumsq<T>(V3, P->nvox, P->partials(), s));
     HIP_TRY(launch_reduce_to(P->partials(), kReduceBlocks, 1.0, sc + SC_SUMSQ, s));
@@ -325,7 +375,6 @@ int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, in
 {
   const bool precond = prm->flags & FFPAT_PRECOND;
   T *V3 = static_cast<T *>(P->vol(2));
-  T *D = static_cast<T *>(P->dat());
   double *sc = P->scalars();
   // R(h_k) for the objective
   HIP_TRY(launch_sumsq<T>(h, P->nvox, P->partials(), s));
@@ -336,7 +385,7 @@ int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, in
   HIP_TRY(launch_reduce_to(P->partials(), P->rows, 1.0, sc + SC_DATA, s));
   HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->obj + k, sc + SC_NONFINITE, s));
   // gradient A^T y, then the prox step
-  rc = op_adjoint<T>(P, D, V3, s);
+  rc = op_adjoint_padded<T>(P, V3, s);
   if (rc) return rc;
   HIP_TRY(launch_prox_l2<T>(h, V3, P->nvox, sc + SC_STEP, prm->lambda, (prm->flags & FFPAT_POSITIVITY) ? 1 : 0,
                             prm->support, s));
@@ -479,7 +528,17 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
   if (e != hipSuccess) return cleanup(hip_fail(e, "make_kappa"));
 
   std::vector<AngleParams> ap((size_t)r.n_angles);
-  for (int a = 0; a < r.n_angles; ++a) ap[(size_t)a] = angle_params(geom->angles[a], r);
+  for (int a = 0; a < r.n_angles; ++a) {
+    ap[(size_t)a] = angle_params(geom->angles[a], r);
+    if (ap[(size_t)a].hw > 1.0) P->two_tap = false;
+    if (ap[(size_t)a].major_x) P->need_t = true;
+    else P->need_n = true;
+  }
+  // the pads of the padded copies stay zero for the life of the plan
+  e = hipMemsetAsync(P->padN(), 0, P->lay.padN_bytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->padT(), 0, P->lay.padT_bytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->padD(), 0, P->lay.padD_bytes, s);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "plan memset"));
   if (is_f64(P)) {
     std::vector<double> t = ramp_taps<double>(r);
     e = hipMemcpyAsync(P->taps(), t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, s);
@@ -571,9 +630,8 @@ int ffpat_project(ffpat_plan *plan, const void *vol_dev, void *g_dev, void *stre
   CHECK_PTR(g_dev, "g_dev");
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = DISPATCH(plan,
-      launch_project<float>(plan->d, plan->n_angles, plan->ns, plan->ap(), (const float *)vol_dev, (float *)g_dev, s),
-      launch_project<double>(plan->d, plan->n_angles, plan->ns, plan->ap(), (const double *)vol_dev, (double *)g_dev, s));
+  hipError_t e = DISPATCH(plan, project<float>(plan, (const float *)vol_dev, (float *)g_dev, s),
+                          project<double>(plan, (const double *)vol_dev, (double *)g_dev, s));
   return e == hipSuccess ? FFPAT_OK : hip_fail(e, "project");
 }
 
@@ -584,9 +642,8 @@ int ffpat_backproject(ffpat_plan *plan, const void *g_dev, void *vol_dev, void *
   CHECK_PTR(g_dev, "g_dev");
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = DISPATCH(plan,
-      launch_backproject<float>(plan->d, plan->n_angles, plan->ns, plan->ap(), (const float *)g_dev, (float *)vol_dev, nullptr, s),
-      launch_backproject<double>(plan->d, plan->n_angles, plan->ns, plan->ap(), (const double *)g_dev, (double *)vol_dev, nullptr, s));
+  hipError_t e = DISPATCH(plan, backproject_op<float>(plan, (const float *)g_dev, (float *)vol_dev, s),
+                          backproject_op<double>(plan, (const double *)g_dev, (double *)vol_dev, s));
   return e == hipSuccess ? FFPAT_OK : hip_fail(e, "backproject");
 }
 
@@ -598,8 +655,8 @@ int ffpat_ramp(ffpat_plan *plan, const void *r_dev, void *y_dev, void *stream)
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = DISPATCH(plan,
-      launch_residual_ramp<float>(plan->rows, plan->ns, (const float *)r_dev, nullptr, nullptr, (const float *)plan->taps(), (float *)y_dev, nullptr, s),
-      launch_residual_ramp<double>(plan->rows, plan->ns, (const double *)r_dev, nullptr, nullptr, (const double *)plan->taps(), (double *)y_dev, nullptr, s));
+      launch_residual_ramp<float>(plan->rows, plan->ns, (const float *)r_dev, nullptr, nullptr, (const float *)plan->taps(), (float *)y_dev, plan->ns, 0, nullptr, s),
+      launch_residual_ramp<double>(plan->rows, plan->ns, (const double *)r_dev, nullptr, nullptr, (const double *)plan->taps(), (double *)y_dev, plan->ns, 0, nullptr, s));
   return e == hipSuccess ? FFPAT_OK : hip_fail(e, "ramp");
 }
 
