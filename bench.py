@@ -146,26 +146,38 @@ def time_wave(torch, plan, reps=3):
     return ms / 1e3 / (reps * plan.nt)
 
 
-def cpu_baseline(case, plan_nt):
-    """Oracle (FP64, OpenMP) on a bounded sample of the same workload, scaled to FB iter/s:
-    8 leapfrog steps, then X and X^T over 8 of the angles, then Lambda on those rows."""
+def cpu_baseline(case, G, step):
+    """The oracle (FP64 C, OpenMP) timed on one full Algorithm-8 iteration of the same
+    workload: same c, same G, same step size, h_0 = 0."""
     import numpy as np
     import oracle
     n = case.n
-    sub = case.angles[:: max(1, len(case.angles) // 8)][:8]
-    T8 = 8 * case.T / plan_nt                       # exactly 8 steps at the workload's dt
-    g8 = oracle.Geometry(nx=n, ny=n, nz=n, dx=case.dx, T=T8, angles=sub)
-    t0 = time.perf_counter(); oracle.wave(g8, case.c, case.h_true); t_wave = time.perf_counter() - t0
-    t0 = time.perf_counter(); d = oracle.project(g8, case.h_true); t_proj = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.backproject(g8, d); t_bp = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.ramp(g8, d); t_ramp = time.perf_counter() - t0
-    ratio = len(case.angles) / len(sub)
-    t_iter = 2 * plan_nt * t_wave / 8 + ratio * (t_proj + t_bp + t_ramp)
+    g = oracle.Geometry(nx=n, ny=n, nz=n, dx=case.dx, T=case.T, angles=case.angles)
+    G_np = G.double().cpu().numpy()
+    t0 = time.perf_counter()
+    oracle.fb(g, case.c, G_np, case.lam, step=step, n_iter=1, flags=oracle.POSITIVITY | oracle.PRECOND)
+    t = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / t_iter, "unit": "FB iter/s", "cores": cores, "kind": "oracle",
-            "sample": (f"{n}^3 FP64: 8 of {plan_nt} leapfrog steps ({t_wave:.1f}s), X/X^T/Lambda on "
-                       f"{len(sub)} of {len(case.angles)} angles ({t_proj + t_bp + t_ramp:.1f}s); "
-                       f"scaled to one FB iteration (2 wave solves + X + X^T + Lambda)")}
+    return {"value": 1.0 / t, "unit": "FB iter/s", "cores": cores, "kind": "oracle",
+            "sample": f"one full FB iteration of the {n}^3 / {len(case.angles)}-angle workload in FP64 "
+                      f"({t:.1f} s: 2 wave solves, X, Lambda, X^T, prox)"}
+
+
+def stored_traffic(recipe, dtype_name):
+    """HBM bytes per stencil launch from the committed counter runs, if the stencil
+    source is unchanged since they were taken (else None)."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1901_06503_amd", "csrc", "kernels_wave.hip")
+    note = os.path.join(ROOT, "profiles", "wave_step_hbm_traffic.md")
+    if not os.path.exists(note):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for line in open(note):
+        m = re.match(r"traffic: recipe=(\S+) dtype=(\S+) bytes_per_launch=([0-9.eE+]+) source_sha256=([0-9a-f]+)", line)
+        if m and m.group(1) == recipe and m.group(2) == dtype_name and m.group(4) == sha:
+            return float(m.group(3))
+    return None
 
 
 def main():
@@ -199,6 +211,7 @@ def main():
     log(f"wave step {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s, {gpt:.1f} Gpt-updates/s")
 
     fp64 = None
+    G_keep = G.cpu() if args.cpu_baseline else None
     if args.fp64_compare and dtype == torch.float32:
         plan.close()
         del G
@@ -213,9 +226,10 @@ def main():
 
     cpu = None
     if args.cpu_baseline:
-        log("cpu baseline (oracle sample)")
-        cpu = cpu_baseline(case, plan.nt)
+        log("cpu baseline (oracle, one FB iteration)")
+        cpu = cpu_baseline(case, G_keep, out.step)
         log(f"cpu baseline {cpu}")
+    traffic = stored_traffic(args.recipe, args.dtype)
 
     line = {
         "metric": METRIC,
@@ -238,7 +252,7 @@ def main():
         "power_iteration_s": t_power,
         "fp64": fp64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "wave_step", "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": t_launch * 1e6},
         "cpu_baseline": cpu,

@@ -218,10 +218,11 @@ struct BlockedConfig {
   int nt = 0;        // non-temporal loads of p(k-1), k' and stores of p(k+1)
 };
 
-static BlockedConfig blocked_config(const Dims &d)
+static BlockedConfig blocked_config(const Dims &d, size_t esz)
 {
-  // default tile height: 8 rows up to 256-wide grids, 16 rows beyond (fewer
-  // halo re-reads once the fields no longer fit in the 256 MB MALL)
+  // default tile height (measured on MI355X): FP32 8 rows up to 256-wide grids,
+  // 16 rows beyond (fewer halo re-reads once the fields no longer fit in the
+  // 256 MB MALL); FP64 16 rows
   static BlockedConfig env = [] {
     BlockedConfig c;
     c.ry = 0;
@@ -235,7 +236,7 @@ static BlockedConfig blocked_config(const Dims &d)
     return c;
   }();
   BlockedConfig cfg = env;
-  if (cfg.ry == 0) cfg.ry = d.ny > 256 ? 4 : 2;
+  if (cfg.ry == 0) cfg.ry = (esz == 8 || d.ny > 256) ? 4 : 2;
   return cfg;
 }
 
@@ -280,7 +281,7 @@ template <typename T, int NDIM>
 static hipError_t blocked_select(StepMode mode, const Dims &d, const T *p, const T *prev, T *out, const T *kap,
                                  hipStream_t s)
 {
-  const BlockedConfig cfg = blocked_config(d);
+  const BlockedConfig cfg = blocked_config(d, sizeof(T));
   switch (cfg.ry) {
     case 1: return blocked_dispatch<T, NDIM, 1>(mode, d, p, prev, out, kap, cfg, s);
     case 4: return blocked_dispatch<T, NDIM, 4>(mode, d, p, prev, out, kap, cfg, s);
