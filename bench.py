@@ -36,11 +36,57 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1, help="time the oracle on a bounded sample (1/0)")
     ap.add_argument("--naive-stencil", action="store_true")
     ap.add_argument("--seed", type=int, default=3001)
-    ap.add_argument("--mode", default="fb", choices=["fb", "wave", "copy"],
+    ap.add_argument("--mode", default="fb", choices=["fb", "wave", "copy", "serve"],
                     help="fb: the benchmark; wave: only W_T applications (for counter runs); "
                          "copy: a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--reps", type=int, default=2, help="applications in --mode wave / copies in --mode copy")
+    ap.add_argument("--jobs", type=int, default=120, help="--mode serve: jobs in the trace")
+    ap.add_argument("--rate", type=float, default=4.0, help="--mode serve: mean arrivals per second (Poisson)")
+    ap.add_argument("--iters", type=int, default=50, help="--mode serve: FB iterations per job")
+    ap.add_argument("--slots", type=int, default=6, help="--mode serve: concurrent jobs")
     return ap.parse_args()
+
+
+def run_serve(args):
+    """Serving workload: Poisson arrivals, grids uniform over {64,128,192,256}^3,
+    angles = grid edge, 50 FB iterations + 20 power steps each, FP32.  Runs the
+    same trace through the serial baseline and the continuous-batching scheduler."""
+    import numpy as np
+    import torch
+    import paper_1901_06503_amd as ff
+    from paper_1901_06503_amd import serving
+    import synth
+    rng = np.random.default_rng(args.seed)
+    sizes = rng.choice([64, 128, 192, 256], size=args.jobs)
+    gaps = rng.exponential(1.0 / args.rate, size=args.jobs)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    jobs = []
+    for i, (n, t) in enumerate(zip(sizes, arrivals)):
+        dx, angles, c, h = synth.torch_case(int(n), int(n), args.seed * 1000 + i)
+        with ff.Plan(c, dx, 0.5, angles) as P:
+            g = P.forward(h)
+            noise = torch.from_numpy(rng.standard_normal(P.data_shape)).to(g.device, g.dtype)
+            G = g + 0.02 * float(g.double().mean()) * noise
+        torch.cuda.synchronize()
+        jobs.append(serving.Job(job_id=i, arrival=float(t), c=c.cpu().pin_memory(), G=G.cpu().pin_memory(), dx=dx,
+                                T=0.5, angles=angles, lam=1e-3, n_iter=args.iters, n_power=20))
+        if (i + 1) % 20 == 0:
+            log(f"trace: {i + 1}/{args.jobs} jobs generated")
+    clone = lambda: [serving.Job(job_id=j.job_id, arrival=j.arrival, c=j.c, G=j.G, dx=j.dx, T=j.T,
+                                 angles=j.angles, lam=j.lam, n_iter=j.n_iter, n_power=j.n_power) for j in jobs]
+    log("serial baseline")
+    base = serving.summary(serving.run_serial(clone()))
+    log(f"serial: {base}")
+    free, total = torch.cuda.mem_get_info()
+    sched = serving.Scheduler(hbm_budget=int(0.5 * free), max_active=args.slots, iters_per_turn=5)
+    log("continuous batching")
+    mixed_jobs = sched.run(clone())
+    mixed = serving.summary(mixed_jobs)
+    log(f"scheduler: {mixed}")
+    print(json.dumps({"mode": "serve", "jobs": args.jobs, "rate_per_s": args.rate, "iters": args.iters,
+                      "slots": args.slots, "serial": base, "continuous_batching": mixed,
+                      "peak_active": sched.peak_active, "peak_bytes": sched.peak_bytes,
+                      "throughput_gain": mixed["jobs_per_s"] / base["jobs_per_s"]}), flush=True)
 
 
 def run_wave_only(args):
@@ -186,6 +232,8 @@ def main():
         return run_wave_only(args)
     if args.mode == "copy":
         return run_copy_only(args)
+    if args.mode == "serve":
+        return run_serve(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the sharded design is described in DESIGN.md)"}))

@@ -81,6 +81,7 @@ typedef struct {
 
 /* Plan flags */
 #define FFPAT_PLAN_NAIVE_STENCIL 1u   /* unblocked stencil kernel (for comparison) */
+#define FFPAT_PLAN_NO_GRAPHS 2u       /* launch every kernel eagerly instead of replaying captured graphs */
 
 /* Reconstruction flags (ffpat_fb_params.flags) */
 #define FFPAT_POSITIVITY 1u   /* R includes the indicator of h >= 0 (prox clamps at 0) */
@@ -153,6 +154,22 @@ int ffpat_ramp(ffpat_plan *plan, const void *r_dev, void *y_dev, void *stream);
  * (FFPAT_EDIVERGED when an objective value or norm is not finite). */
 int ffpat_reconstruct(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params,
                       void *h_dev, double *step_used, void *stream);
+
+/* Asynchronous form of ffpat_reconstruct for serving loops: enqueues the step
+ * selection and params->n_iter iterations on `stream` and returns without any
+ * host synchronisation (params->objective is ignored; the values stay on the
+ * device).  The power iteration and one FB iteration are captured once as HIP
+ * graphs and replayed (unless the plan was created with FFPAT_PLAN_NO_GRAPHS);
+ * a change of G_dev, h_dev, masks, flags or lambda re-captures.  Buffers must
+ * stay alive until the stream has passed the work. */
+int ffpat_fb_enqueue(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev,
+                     void *stream);
+
+/* Completes an ffpat_fb_enqueue: synchronises `stream`, writes the step size
+ * (step_used, may be NULL) and the first n objective values of the last
+ * enqueued run (objective, host, may be NULL when n = 0), and returns
+ * FFPAT_EDIVERGED if any objective value, norm or the step was not finite. */
+int ffpat_fb_report(ffpat_plan *plan, double *step_used, double *objective, int32_t n, void *stream);
 
 #ifdef __cplusplus
 }

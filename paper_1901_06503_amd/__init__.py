@@ -71,7 +71,8 @@ class Plan:
     dtype (float32 or float64) sets the precision of every field.
     """
 
-    def __init__(self, c, dx, T, angles, ns=0, ds=0.0, cfl=0.3, ndim=3, naive_stencil=False, stream=None):
+    def __init__(self, c, dx, T, angles, ns=0, ds=0.0, cfl=0.3, ndim=3, naive_stencil=False, use_graphs=True,
+                 stream=None):
         torch = _torch()
         if not (isinstance(c, torch.Tensor) and c.is_cuda):
             raise TypeError("c must be a device tensor")
@@ -84,7 +85,7 @@ class Plan:
         self.device = c.device
         nz, ny, nx = c.shape
         code = _lib.F64 if c.dtype == torch.float64 else _lib.F32
-        flags = _lib.PLAN_NAIVE_STENCIL if naive_stencil else 0
+        flags = (_lib.PLAN_NAIVE_STENCIL if naive_stencil else 0) | (0 if use_graphs else _lib.PLAN_NO_GRAPHS)
         self._lib = _lib.load()
         g, self._angles = _make_geom(nx, ny, nz, dx, T, angles, ns, ds, cfl, ndim, code, flags)
         handle = ctypes.c_void_p()
@@ -157,14 +158,10 @@ class Plan:
         """y = Lambda r."""
         return self._call(self._lib.ffpat_ramp, r, self.data_shape, out, self.data_shape, stream, "r")
 
-    def reconstruct(self, G, lam, n_iter, step=0.0, n_power=20, positivity=True, precond=True,
-                    support=None, det_mask=None, h0=None, use_plan_step=False, stream=None,
-                    want_objective=True) -> ReconResult:
-        """Algorithm 8: K = n_iter forward-backward iterations from h0 (zeros by default)."""
-        torch = _torch()
+    def _fb_params(self, G, lam, n_iter, step, n_power, positivity, precond, support, det_mask, h,
+                   use_plan_step, objective):
         self._check_tensor(G, self.data_shape, "G")
-        h = torch.zeros(self.shape, dtype=self.dtype, device=self.device) if h0 is None else h0
-        self._check_tensor(h, self.shape, "h0")
+        self._check_tensor(h, self.shape, "h")
         flags = (POSITIVITY if positivity else 0) | (PRECOND if precond else 0)
         if use_plan_step:
             flags |= USE_PLAN_STEP
@@ -176,15 +173,44 @@ class Plan:
         if det_mask is not None:
             self._check_mask(det_mask, self.data_shape, "det_mask")
             msk = det_mask.data_ptr()
+        obj_ptr = objective.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if objective is not None else None
+        return _lib.FbParams(float(lam), float(step), int(n_iter), int(n_power), flags,
+                             ctypes.c_void_p(sup or None), ctypes.c_void_p(msk or None), obj_ptr)
+
+    def reconstruct(self, G, lam, n_iter, step=0.0, n_power=20, positivity=True, precond=True,
+                    support=None, det_mask=None, h0=None, use_plan_step=False, stream=None,
+                    want_objective=True) -> ReconResult:
+        """Algorithm 8: K = n_iter forward-backward iterations from h0 (zeros by default;
+        h0 is updated in place and returned as .h).  Synchronises the stream at the end."""
+        torch = _torch()
+        h = torch.zeros(self.shape, dtype=self.dtype, device=self.device) if h0 is None else h0
         obj = np.zeros(max(int(n_iter), 1), dtype=np.float64)
-        prm = _lib.FbParams(float(lam), float(step), int(n_iter), int(n_power), flags,
-                            ctypes.c_void_p(sup or None), ctypes.c_void_p(msk or None),
-                            obj.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_objective else None)
+        prm = self._fb_params(G, lam, n_iter, step, n_power, positivity, precond, support, det_mask, h,
+                              use_plan_step, obj if want_objective else None)
         s = ctypes.c_double()
         _lib.check(self._lib.ffpat_reconstruct(self._h, ctypes.c_void_p(G.data_ptr()), ctypes.byref(prm),
                                                ctypes.c_void_p(h.data_ptr()), ctypes.byref(s),
                                                ctypes.c_void_p(_stream_handle(stream))))
         return ReconResult(h=h, objective=obj[:int(n_iter)], step=s.value)
+
+    def fb_enqueue(self, G, lam, n_iter, h, step=0.0, n_power=20, positivity=True, precond=True, support=None,
+                   det_mask=None, use_plan_step=False, stream=None):
+        """Enqueues the step selection (unless use_plan_step or step > 0) and n_iter
+        iterations on `stream` without host synchronisation (serving)."""
+        prm = self._fb_params(G, lam, n_iter, step, n_power, positivity, precond, support, det_mask, h,
+                              use_plan_step, None)
+        _lib.check(self._lib.ffpat_fb_enqueue(self._h, ctypes.c_void_p(G.data_ptr()), ctypes.byref(prm),
+                                              ctypes.c_void_p(h.data_ptr()),
+                                              ctypes.c_void_p(_stream_handle(stream))))
+
+    def fb_report(self, n=0, stream=None):
+        """Waits for the stream; returns (step, objective[:n]) of the last enqueued run."""
+        obj = np.zeros(max(int(n), 1), dtype=np.float64)
+        s = ctypes.c_double()
+        _lib.check(self._lib.ffpat_fb_report(self._h, ctypes.byref(s),
+                                             obj.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if n else None,
+                                             int(n), ctypes.c_void_p(_stream_handle(stream))))
+        return s.value, obj[:int(n)]
 
     def _check_mask(self, m, shape, name):
         torch = _torch()

@@ -18,6 +18,7 @@ STATUS_NAMES = {OK: "FFPAT_OK", EINVAL: "FFPAT_EINVAL", ECFL: "FFPAT_ECFL", ENOM
 F32, F64 = 0, 1
 
 PLAN_NAIVE_STENCIL = 1
+PLAN_NO_GRAPHS = 2
 POSITIVITY = 1
 PRECOND = 2
 REG_GRAD = 4
@@ -63,6 +64,9 @@ SIGNATURES = {
     "ffpat_ramp": ([_P, _P, _P, _P], ctypes.c_int),
     "ffpat_reconstruct": ([_P, _P, ctypes.POINTER(FbParams), _P, ctypes.POINTER(ctypes.c_double), _P],
                           ctypes.c_int),
+    "ffpat_fb_enqueue": ([_P, _P, ctypes.POINTER(FbParams), _P, _P], ctypes.c_int),
+    "ffpat_fb_report": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _P],
+                        ctypes.c_int),
 }
 
 _lib = None

@@ -103,10 +103,10 @@ hipError_t launch_dot(const T *x, const T *y, size_t n, double *partials, hipStr
 // out[0] = scale * sum(partials[0..n)) (single block, fixed order).
 hipError_t launch_reduce_to(const double *partials, int n, double scale, double *out, hipStream_t s);
 
-// objective[k] = 0.5 * data + lambda * 0.5 * reg (values read on the device);
-// flags nonfinite in scalars.
-hipError_t launch_objective(const double *data_sum, const double *reg_sum, double lambda, double *obj_k,
-                            double *nonfinite_flag, hipStream_t s);
+// obj[k] = 0.5 * data + lambda * 0.5 * reg with k = *counter (then *counter += 1;
+// values beyond `capacity` are counted but not stored); flags non-finite values.
+hipError_t launch_objective(const double *data_sum, const double *reg_sum, double lambda, double *obj,
+                            double *counter, int capacity, double *nonfinite_flag, hipStream_t s);
 
 // L = sqrt(sumsq); step = 1 / L.
 hipError_t launch_power_finish(const double *sumsq, double *L, double *step, double *nonfinite_flag,

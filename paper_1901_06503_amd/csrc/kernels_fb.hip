@@ -74,22 +74,24 @@ hipError_t launch_reduce_to(const double *partials, int n, double scale, double 
   return hipGetLastError();
 }
 
-__global__ void objective_kernel(const double *data_sum, const double *reg_sum, double lambda, double *obj_k,
-                                 double *nonfinite)
+__global__ void objective_kernel(const double *data_sum, const double *reg_sum, double lambda, double *obj,
+                                 double *counter, int capacity, double *nonfinite)
 {
   if (threadIdx.x == 0) {
     const double d = data_sum[0];
     const double r = reg_sum[0];
     const double J = 0.5 * d + lambda * 0.5 * r;
-    obj_k[0] = J;
+    const int k = (int)counter[0];
+    if (k < capacity) obj[k] = J;
+    counter[0] = (double)(k + 1);
     if (!isfinite(J)) nonfinite[0] = 1.0;
   }
 }
 
-hipError_t launch_objective(const double *data_sum, const double *reg_sum, double lambda, double *obj_k,
-                            double *nonfinite, hipStream_t s)
+hipError_t launch_objective(const double *data_sum, const double *reg_sum, double lambda, double *obj,
+                            double *counter, int capacity, double *nonfinite, hipStream_t s)
 {
-  objective_kernel<<<1, 64, 0, s>>>(data_sum, reg_sum, lambda, obj_k, nonfinite);
+  objective_kernel<<<1, 64, 0, s>>>(data_sum, reg_sum, lambda, obj, counter, capacity, nonfinite);
   return hipGetLastError();
 }
 

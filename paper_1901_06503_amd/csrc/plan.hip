@@ -54,7 +54,7 @@ int hip_fail(hipError_t e, const char *where)
   } while (0)
 
 // Device scalar slots
-enum { SC_STEP = 0, SC_L = 1, SC_REG = 2, SC_DATA = 3, SC_NONFINITE = 4, SC_SUMSQ = 5, SC_COUNT = 8 };
+enum { SC_STEP = 0, SC_L = 1, SC_REG = 2, SC_DATA = 3, SC_NONFINITE = 4, SC_SUMSQ = 5, SC_ITER = 6, SC_COUNT = 8 };
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -69,6 +69,21 @@ struct DeviceGuard {
   ~DeviceGuard()
   {
     if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// A captured graph and the arguments it was recorded with.
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  const void *G = nullptr, *h = nullptr, *support = nullptr, *mask = nullptr;
+  uint32_t flags = 0;
+  double lambda = 0.0;
+  int n_power = 0;
+  bool matches(const void *G_, const void *h_, const void *sup_, const void *m_, uint32_t f_, double lam_,
+               int np_) const
+  {
+    return exec && G == G_ && h == h_ && support == sup_ && mask == m_ && flags == f_ && lambda == lam_ &&
+           n_power == np_;
   }
 };
 
@@ -103,6 +118,9 @@ struct ffpat_plan {
   bool two_tap = true;    // every footprint half-width m dx / ds <= 1 bin
   bool need_n = false;    // some angle marches rows (reads the padded plane)
   bool need_t = false;    // some angle marches columns (reads the padded transpose)
+  bool use_graphs = true; // replay captured graphs for the power iteration and FB iterations
+  hipStream_t cap_stream = nullptr;
+  GraphCache g_iter, g_power;
 
   void *vol(int i) const { return base + lay.vol[i]; }
   void *kap() const { return base + lay.kap; }
@@ -370,8 +388,11 @@ int power_iteration(ffpat_plan *P, int n_power, bool precond, const uint8_t *mas
   return FFPAT_OK;
 }
 
+// One iteration of Algorithm 8.  The objective goes to obj[counter], counter++
+// (device-side), so the same launch sequence serves every iteration and can
+// be captured once as a graph.
 template <typename T>
-int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, int k, hipStream_t s)
+int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, hipStream_t s)
 {
   const bool precond = prm->flags & FFPAT_PRECOND;
   T *V3 = static_cast<T *>(P->vol(2));
@@ -383,7 +404,8 @@ int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, in
   int rc = data_residual<T>(P, h, G, prm->det_mask, precond, P->partials(), s);
   if (rc) return rc;
   HIP_TRY(launch_reduce_to(P->partials(), P->rows, 1.0, sc + SC_DATA, s));
-  HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->obj + k, sc + SC_NONFINITE, s));
+  HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->obj, sc + SC_ITER, P->obj_cap,
+                           sc + SC_NONFINITE, s));
   // gradient A^T y, then the prox step
   rc = op_adjoint_padded<T>(P, V3, s);
   if (rc) return rc;
@@ -392,44 +414,127 @@ int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, in
   return FFPAT_OK;
 }
 
+// Records `body(stream)` into a graph on the plan's capture stream.
+template <typename F>
+int capture_graph(ffpat_plan *P, GraphCache &gc, F &&body)
+{
+  if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+  if (gc.exec) {
+    HIP_TRY(hipGraphExecDestroy(gc.exec));
+    gc.exec = nullptr;
+  }
+  HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = body(P->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
+  if (rc) {
+    if (e == hipSuccess && graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+  gc.exec = exec;
+  return FFPAT_OK;
+}
+
+int ensure_objective_capacity(ffpat_plan *P, int n, hipStream_t s)
+{
+  if (n <= P->obj_cap) return FFPAT_OK;
+  const int cap = n > 1024 ? n : 1024;
+  if (P->obj) {
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipFree(P->obj));
+    P->obj = nullptr;
+    P->obj_cap = 0;
+  }
+  HIP_TRY(hipMalloc(&P->obj, sizeof(double) * (size_t)cap));
+  P->obj_cap = cap;
+  return FFPAT_OK;
+}
+
+// Enqueues the step-size selection and n_iter iterations; no host synchronisation.
 template <typename T>
-int reconstruct(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, double *step_used, hipStream_t s)
+int fb_enqueue(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, hipStream_t s)
 {
   const bool precond = prm->flags & FFPAT_PRECOND;
+  const int n_power = prm->n_power > 0 ? prm->n_power : 20;
   double *sc = P->scalars();
+  int rc = ensure_objective_capacity(P, prm->n_iter, s);
+  if (rc) return rc;
   HIP_TRY(launch_set(sc + SC_NONFINITE, 0.0, s));
+  HIP_TRY(launch_set(sc + SC_ITER, 0.0, s));
   if (prm->flags & FFPAT_USE_PLAN_STEP) {
     if (!P->has_step) return fail(FFPAT_EINVAL, "FFPAT_USE_PLAN_STEP but the plan holds no step yet");
   } else if (prm->step > 0) {
     HIP_TRY(launch_set(sc + SC_STEP, prm->step, s));
+  } else if (P->use_graphs) {
+    const uint32_t key = precond ? FFPAT_PRECOND : 0u;
+    if (!P->g_power.matches(nullptr, nullptr, nullptr, prm->det_mask, key, 0.0, n_power)) {
+      rc = capture_graph(P, P->g_power, [&](hipStream_t cs) {
+        return power_iteration<T>(P, n_power, precond, prm->det_mask, cs);
+      });
+      if (rc) return rc;
+      P->g_power.mask = prm->det_mask;
+      P->g_power.flags = key;
+      P->g_power.n_power = n_power;
+    }
+    HIP_TRY(hipGraphLaunch(P->g_power.exec, s));
   } else {
-    int rc = power_iteration<T>(P, prm->n_power > 0 ? prm->n_power : 20, precond, prm->det_mask, s);
+    rc = power_iteration<T>(P, n_power, precond, prm->det_mask, s);
     if (rc) return rc;
   }
   P->has_step = true;
-  if (prm->n_iter > P->obj_cap) {
-    if (P->obj) {
-      HIP_TRY(hipStreamSynchronize(s));
-      HIP_TRY(hipFree(P->obj));
-      P->obj = nullptr;
-      P->obj_cap = 0;
+  if (prm->n_iter <= 0) return FFPAT_OK;
+  if (P->use_graphs) {
+    const uint32_t key = prm->flags & (FFPAT_PRECOND | FFPAT_POSITIVITY);
+    if (!P->g_iter.matches(G, h, prm->support, prm->det_mask, key, prm->lambda, 0)) {
+      rc = capture_graph(P, P->g_iter, [&](hipStream_t cs) { return fb_iteration<T>(P, G, h, prm, cs); });
+      if (rc) return rc;
+      P->g_iter.G = G;
+      P->g_iter.h = h;
+      P->g_iter.support = prm->support;
+      P->g_iter.mask = prm->det_mask;
+      P->g_iter.flags = key;
+      P->g_iter.lambda = prm->lambda;
     }
-    HIP_TRY(hipMalloc(&P->obj, sizeof(double) * (size_t)prm->n_iter));
-    P->obj_cap = prm->n_iter;
+    for (int k = 0; k < prm->n_iter; ++k) HIP_TRY(hipGraphLaunch(P->g_iter.exec, s));
+  } else {
+    for (int k = 0; k < prm->n_iter; ++k) {
+      rc = fb_iteration<T>(P, G, h, prm, s);
+      if (rc) return rc;
+    }
   }
-  for (int k = 0; k < prm->n_iter; ++k) {
-    int rc = fb_iteration<T>(P, G, h, prm, k, s);
-    if (rc) return rc;
-  }
+  return FFPAT_OK;
+}
+
+// Waits for `s`, then reports the step, up to n objective values and divergence.
+int fb_report(ffpat_plan *P, double *step_used, double *objective, int n, hipStream_t s)
+{
   double host_sc[SC_COUNT];
-  HIP_TRY(hipMemcpyAsync(host_sc, sc, sizeof host_sc, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(host_sc, P->scalars(), sizeof host_sc, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (prm->objective && prm->n_iter > 0)
-    HIP_TRY(hipMemcpy(prm->objective, P->obj, sizeof(double) * (size_t)prm->n_iter, hipMemcpyDeviceToHost));
+  const int done = (int)host_sc[SC_ITER];
+  if (objective && n > 0) {
+    if (n > done || n > P->obj_cap)
+      return fail(FFPAT_EINVAL, "%d objective values requested, %d available", n, done);
+    HIP_TRY(hipMemcpyAsync(objective, P->obj, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   if (step_used) *step_used = host_sc[SC_STEP];
   if (host_sc[SC_NONFINITE] != 0.0 || !std::isfinite(host_sc[SC_STEP]))
     return fail(FFPAT_EDIVERGED, "non-finite objective, norm or step during reconstruction");
   return FFPAT_OK;
+}
+
+template <typename T>
+int reconstruct(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, double *step_used, hipStream_t s)
+{
+  int rc = fb_enqueue<T>(P, G, prm, h, s);
+  if (rc) return rc;
+  return fb_report(P, step_used, prm->objective, prm->objective ? prm->n_iter : 0, s);
 }
 
 bool is_f64(const ffpat_plan *P) { return P->dtype == FFPAT_F64; }
@@ -486,6 +591,7 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
   P->cfl = r.cfl;
   P->flags = r.flags;
   P->stencil = (r.flags & FFPAT_PLAN_NAIVE_STENCIL) ? STENCIL_NAIVE : STENCIL_BLOCKED;
+  P->use_graphs = !(r.flags & FFPAT_PLAN_NO_GRAPHS);
   P->nvox = r.d.nvox();
   P->ndat = (size_t)r.n_angles * r.d.nz * r.ns;
   P->rows = r.n_angles * r.d.nz;
@@ -569,6 +675,9 @@ int ffpat_plan_destroy(ffpat_plan *plan)
   if (!plan) return FFPAT_OK;
   DeviceGuard guard(plan->device);
   hipError_t e = hipDeviceSynchronize();
+  if (plan->g_iter.exec) (void)hipGraphExecDestroy(plan->g_iter.exec);
+  if (plan->g_power.exec) (void)hipGraphExecDestroy(plan->g_power.exec);
+  if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   if (plan->obj) (void)hipFree(plan->obj);
   (void)hipFree(plan->base);
   delete plan;
@@ -660,8 +769,7 @@ int ffpat_ramp(ffpat_plan *plan, const void *r_dev, void *y_dev, void *stream)
   return e == hipSuccess ? FFPAT_OK : hip_fail(e, "ramp");
 }
 
-int ffpat_reconstruct(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev,
-                      double *step_used, void *stream)
+static int check_fb_args(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev)
 {
   CHECK_PLAN(plan);
   CHECK_PTR(params, "params");
@@ -672,10 +780,37 @@ int ffpat_reconstruct(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params
   if (!(params->lambda >= 0) || !std::isfinite(params->lambda)) return fail(FFPAT_EINVAL, "lambda must be finite and >= 0");
   if (!std::isfinite(params->step)) return fail(FFPAT_EINVAL, "step must be finite");
   if (params->flags & FFPAT_REG_GRAD) return fail(FFPAT_EINVAL, "FFPAT_REG_GRAD is not available in this build");
+  return FFPAT_OK;
+}
+
+int ffpat_reconstruct(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev,
+                      double *step_used, void *stream)
+{
+  int rc = check_fb_args(plan, G_dev, params, h_dev);
+  if (rc) return rc;
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   return DISPATCH(plan, reconstruct<float>(plan, (const float *)G_dev, params, (float *)h_dev, step_used, s),
                   reconstruct<double>(plan, (const double *)G_dev, params, (double *)h_dev, step_used, s));
+}
+
+int ffpat_fb_enqueue(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev, void *stream)
+{
+  int rc = check_fb_args(plan, G_dev, params, h_dev);
+  if (rc) return rc;
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return DISPATCH(plan, fb_enqueue<float>(plan, (const float *)G_dev, params, (float *)h_dev, s),
+                  fb_enqueue<double>(plan, (const double *)G_dev, params, (double *)h_dev, s));
+}
+
+int ffpat_fb_report(ffpat_plan *plan, double *step_used, double *objective, int32_t n, void *stream)
+{
+  CHECK_PLAN(plan);
+  if (n < 0) return fail(FFPAT_EINVAL, "n must be >= 0");
+  if (n > 0 && !objective) return fail(FFPAT_EINVAL, "objective is NULL");
+  DeviceGuard guard(plan->device);
+  return fb_report(plan, step_used, objective, n, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

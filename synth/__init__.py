@@ -202,3 +202,41 @@ def gaussian_blob(shape, dx, centre, sigma, amplitude=1.0):
     z, y, x = _coords(shape, dx)
     cx, cy, cz = centre
     return amplitude * np.exp(-((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2) / (2 * sigma * sigma))
+
+
+def torch_case(n, n_angles, seed, device="cuda", dtype=None, n_balls=20, n_bumps=5, amp=0.2, clamp=(0.8, 1.2)):
+    """Device-side generator for large traces (serving): the recipe's balls
+    (smoothed, sigma = 1 voxel) and sound-speed bumps, drawn from a seeded
+    numpy generator and rasterised with torch on the device.  Returns
+    (dx, angles, c, h) with c, h device tensors [n][n][n]."""
+    import torch
+    dtype = dtype or torch.float32
+    rng = np.random.default_rng(seed)
+    dx = grid_spacing(n)
+    ax = torch.as_tensor(axis(n, dx), device=device, dtype=torch.float32)
+    z, y, x = ax[:, None, None], ax[None, :, None], ax[None, None, :]
+    h = torch.zeros((n, n, n), device=device, dtype=torch.float32)
+    centres = _uniform_in_ball(rng, 0.8, n_balls)
+    rad = rng.uniform(0.1, 0.3, size=n_balls)
+    val = rng.uniform(0.5, 1.0, size=n_balls)
+    for (cx, cy, cz), r, v in zip(centres, rad, val):
+        inside = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= r * r
+        h = torch.maximum(h, inside.to(torch.float32) * float(v))
+    t = torch.arange(-4, 5, device=device, dtype=torch.float32)
+    k = torch.exp(-0.5 * t * t)
+    k = k / k.sum()
+    for dim in range(3):
+        pad = [0, 0, 0, 0, 0, 0]
+        pad[2 * (2 - dim)] = pad[2 * (2 - dim) + 1] = 4
+        hp = torch.nn.functional.pad(h, pad)
+        acc = torch.zeros_like(h)
+        for i in range(9):
+            acc += k[i] * hp.narrow(dim, i, n)
+        h = acc
+    c = torch.ones((n, n, n), device=device, dtype=torch.float32)
+    bc = _uniform_in_ball(rng, 1.0, n_bumps)
+    ba = rng.uniform(-1.0, 1.0, size=n_bumps)
+    for (cx, cy, cz), a in zip(bc, ba):
+        c += amp * float(a) * torch.exp(-((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2) / (2 * 0.16))
+    c = torch.clamp(c, clamp[0], clamp[1])
+    return dx, uniform_angles(n_angles), c.to(dtype), h.to(dtype)

@@ -1,0 +1,108 @@
+"""Parity at the workloads' full sizes, in the launch configuration bench.py times.
+
+128^3 / 128 angles: Algorithm 8 for 100 iterations with the 20-step power
+iteration, FP32 (FP64 reductions) and all-FP64, against the oracle's
+iterate at 4096 sampled voxels, its objective history and step size.
+256^3 / 256 angles: forward and adjoint at 4096 sampled outputs, the autograd
+gradient A^T (A h - d) on the central 16^3 crop, and central finite
+differences on 16 random directions (a property that holds at any size).
+Expected values: tests/golden/*_oracle.json, written by
+tests/golden/make_golden.py from the oracle alone.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from conftest import rel_l2, to_dev, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+
+
+def _load(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated")
+    return json.load(open(path))
+
+
+def _golden_mod():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(GOLDEN, "make_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.fixture(scope="module")
+def c256():
+    import synth
+    gold = _load("c256_oracle.json")
+    mg = _golden_mod()
+    case = mg.as_f32_values(synth.make_case("c256", gold["seed"]))
+    data = synth.random_field((len(case.angles), case.n, case.n), gold["data_seed"])
+    data = data.astype(np.float32).astype(np.float64)
+    return gold, case, data
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_c256_forward_adjoint_samples(c256, dtype):
+    import paper_1901_06503_amd as ff
+    gold, case, data = c256
+    print(f"[fullsize] 256^3 forward/adjoint {dtype}", flush=True)
+    with ff.Plan(to_dev(case.c, dtype), case.dx, case.T, case.angles) as P:
+        fwd = P.forward(to_dev(case.h_true, dtype)).double().flatten()
+        fi = torch.tensor(gold["forward_index"], device="cuda")
+        got = fwd[fi].cpu().numpy()
+        adj = P.adjoint(to_dev(data, dtype)).double().flatten()
+        ai = torch.tensor(gold["adjoint_index"], device="cuda")
+        got_a = adj[ai].cpu().numpy()
+        tol = 1e-5 if dtype == torch.float32 else 1e-12
+        assert rel_l2(got, np.array(gold["forward_sample"])) <= tol
+        assert rel_l2(got_a, np.array(gold["adjoint_sample"])) <= tol
+        assert abs(float(fwd.norm()) / gold["forward_norm"] - 1) <= tol
+        assert abs(float(adj.norm()) / gold["adjoint_norm"] - 1) <= tol
+
+
+def test_c256_autograd_gradient_crop_and_fd(c256):
+    import paper_1901_06503_amd as ff
+    from paper_1901_06503_amd.autograd import xw
+    from test_gpu_autograd import _fd_check
+    gold, case, data = c256
+    print("[fullsize] 256^3 autograd", flush=True)
+    with ff.Plan(to_dev(case.c, torch.float32), case.dx, case.T, case.angles) as P:
+        h = to_dev(case.h_true, torch.float32).requires_grad_(True)
+        d = to_dev(data, torch.float32)
+        loss = 0.5 * torch.sum((xw(P, h) - d) ** 2)
+        loss.backward()
+        c0, m = gold["crop_origin"], gold["crop_size"]
+        crop = to_np(h.grad[c0:c0 + m, c0:c0 + m, c0:c0 + m]).ravel()
+        assert rel_l2(crop, np.array(gold["gradient_crop"])) <= 1e-4
+        assert abs(float(h.grad.double().norm()) / gold["gradient_norm"] - 1) <= 1e-5
+        assert _fd_check(P, h.detach(), d, 16, 1e-3, 11) <= 1e-3
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_c128_reconstruction_100_iterations(oracle, dtype):
+    import paper_1901_06503_amd as ff
+    import synth
+    gold = _load("c128_oracle.json")
+    mg = _golden_mod()
+    case = mg.as_f32_values(synth.make_case("c128", gold["seed"]))
+    g = mg.geometry(case)
+    G = mg.simulate(case, g)                   # oracle data simulation (same as the fixture's)
+    print(f"[fullsize] 128^3 reconstruction {dtype}", flush=True)
+    with ff.Plan(to_dev(case.c, dtype), case.dx, case.T, case.angles) as P:
+        res = P.reconstruct(to_dev(G, dtype), gold["lam"], gold["n_iter"], step=0.0, n_power=gold["n_power"])
+        idx = torch.tensor(gold["sample_index"], device="cuda")
+        got = res.h.double().flatten()[idx].cpu().numpy()
+    tol = 1e-4 if dtype == torch.float32 else 1e-10
+    assert res.step == pytest.approx(gold["step"], rel=tol)
+    assert rel_l2(got, np.array(gold["h_sample"])) <= tol
+    assert np.allclose(res.objective, gold["objective"], rtol=tol, atol=0)
+    assert abs(float(res.h.double().norm()) / gold["h_norm"] - 1) <= tol
