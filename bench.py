@@ -43,7 +43,9 @@ def parse():
     ap.add_argument("--jobs", type=int, default=120, help="--mode serve: jobs in the trace")
     ap.add_argument("--rate", type=float, default=4.0, help="--mode serve: mean arrivals per second (Poisson)")
     ap.add_argument("--iters", type=int, default=50, help="--mode serve: FB iterations per job")
-    ap.add_argument("--slots", type=int, default=6, help="--mode serve: concurrent jobs")
+    ap.add_argument("--slots", type=int, default=6, help="--mode serve: admitted (resident) jobs")
+    ap.add_argument("--concurrency", type=int, default=2,
+                    help="--mode serve: jobs advancing at a time (least remaining work first); 0 = all")
     return ap.parse_args()
 
 
@@ -78,14 +80,16 @@ def run_serve(args):
     base = serving.summary(serving.run_serial(clone()))
     log(f"serial: {base}")
     free, total = torch.cuda.mem_get_info()
-    sched = serving.Scheduler(hbm_budget=int(0.5 * free), max_active=args.slots, iters_per_turn=5)
+    sched = serving.Scheduler(hbm_budget=int(0.5 * free), max_active=args.slots, iters_per_turn=5,
+                              concurrency=args.concurrency)
     log("continuous batching")
     mixed_jobs = sched.run(clone())
     mixed = serving.summary(mixed_jobs)
     log(f"scheduler: {mixed}")
     print(json.dumps({"mode": "serve", "jobs": args.jobs, "rate_per_s": args.rate, "iters": args.iters,
-                      "slots": args.slots, "serial": base, "continuous_batching": mixed,
-                      "peak_active": sched.peak_active, "peak_bytes": sched.peak_bytes,
+                      "slots": args.slots, "concurrency": args.concurrency, "serial": base,
+                      "continuous_batching": mixed, "peak_active": sched.peak_active,
+                      "peak_running": sched.peak_running, "peak_bytes": sched.peak_bytes,
                       "throughput_gain": mixed["jobs_per_s"] / base["jobs_per_s"]}), flush=True)
 
 

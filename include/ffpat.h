@@ -88,6 +88,8 @@ typedef struct {
 #define FFPAT_PRECOND    2u   /* data term 1/2 <Lambda r, r> (else 1/2 ||r||^2) */
 #define FFPAT_REG_GRAD   4u   /* R = 1/2 ||D h||^2 (forward differences, zero outside) instead of 1/2 ||h||^2 */
 #define FFPAT_USE_PLAN_STEP 8u /* reuse the step stored in the plan by an earlier call */
+#define FFPAT_TWO_STEP  16u   /* Algorithm 9 (Sec. 4.1): G_dev is the volume g = X^-1 G (see ffpat_fbp),
+                                 the data term is 1/2 ||W_T h - g||^2; det_mask must be NULL */
 
 /* Algorithm 8 parameters (Sec. 3.2). */
 typedef struct {
@@ -95,10 +97,15 @@ typedef struct {
   double step;              /* > 0: constant step s; <= 0: s = 1/L from n_power power-iteration steps */
   int32_t n_iter;           /* K >= 0 iterations */
   int32_t n_power;          /* power-iteration steps (0 selects 20) */
-  uint32_t flags;           /* FFPAT_POSITIVITY | FFPAT_PRECOND | FFPAT_REG_GRAD | FFPAT_USE_PLAN_STEP */
+  uint32_t flags;           /* FFPAT_POSITIVITY | FFPAT_PRECOND | FFPAT_REG_GRAD | FFPAT_USE_PLAN_STEP |
+                               FFPAT_TWO_STEP; REG_GRAD excludes POSITIVITY */
   const uint8_t *support;   /* device [nz][ny][nx] mask chi_V (nonzero = inside), or NULL */
   const uint8_t *det_mask;  /* device [n_angles][nz][ns] mask chi_M (nonzero = measured), or NULL */
   double *objective;        /* host array of n_iter values J_k = 1/2<Lambda r_k, r_k> + lambda R(h_k), or NULL */
+  double cg_tol;            /* FFPAT_REG_GRAD prox: relative residual of the conjugate-gradient solve
+                               (0 selects 1e-12 for FP64 plans, 1e-6 for FP32) */
+  int32_t cg_maxit;         /* FFPAT_REG_GRAD prox: conjugate-gradient iterations per prox (0 selects 200);
+                               iterations after convergence are skipped on the device */
 } ffpat_fb_params;
 
 /* Library version string. */
@@ -146,6 +153,10 @@ int ffpat_backproject(ffpat_plan *plan, const void *g_dev, void *vol_dev, void *
 
 /* y = Lambda r alone (Sec. 3.1).  Data arrays; y may equal r (in place). */
 int ffpat_ramp(ffpat_plan *plan, const void *r_dev, void *y_dev, void *stream);
+
+/* vol = X^-1 G = X^* Lambda G, filtered backprojection per plane (Sec. 3.1):
+ * the first stage of the two-step method (Algorithm 9). */
+int ffpat_fbp(ffpat_plan *plan, const void *G_dev, void *vol_dev, void *stream);
 
 /* Algorithm 8 (Sec. 3.2): h_{k+1} = prox_{s lambda R}(h_k - s A^T chi_M Lambda chi_M (A h_k - G)).
  * G_dev: data; h_dev: in h_0 (zeros reproduce the paper's start), out h_K.

@@ -78,6 +78,9 @@ def _load():
             ("orc_energy", [G, P, P, P], ctypes.c_double),
             ("orc_wave_history", [G, P, P, ctypes.c_int32, P], ctypes.c_int),
             ("orc_plan_info", [G, P, P, P, P], ctypes.c_int),
+            ("orc_fbp", [G, P, P], ctypes.c_int),
+            ("orc_fb_two_step", [G, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_uint32, P, P, P, P], ctypes.c_int),
         ]:
             fn = getattr(lib, name)
             fn.argtypes = args
@@ -319,3 +322,35 @@ def wave_history(geom: Geometry, c, h, nsteps):
     gp, _g = geom._c()
     _check(lib.orc_wave_history(gp, _p(c), _p(h), nsteps, _p(out)))
     return out
+
+
+def fbp(geom: Geometry, G):
+    """X^-1 G = X^T Lambda G (filtered backprojection per plane)."""
+    lib = _load()
+    G = _f64(G, geom.data_shape)
+    out = np.empty(geom.vol_shape)
+    gp, _g = geom._c()
+    _check(lib.orc_fbp(gp, _p(G), _p(out)))
+    return out
+
+
+def fb_two_step(geom: Geometry, c, gvol, lam, step=0.0, n_iter=5, n_power=20, flags=POSITIVITY, support=None,
+                h0=None):
+    """Algorithm 9, second stage: FB on 1/2 ||W h - g||^2 + lambda R.  Returns (h_K, objective, step)."""
+    lib = _load()
+    c = _f64(c, geom.vol_shape); gvol = _f64(gvol, geom.vol_shape)
+    h = np.zeros(geom.vol_shape) if h0 is None else _f64(h0, geom.vol_shape).copy()
+    sup = _u8(support, geom.vol_shape)
+    obj = np.zeros(max(n_iter, 1))
+    s = ctypes.c_double()
+    gp, _g = geom._c()
+    _check(lib.orc_fb_two_step(gp, _p(c), _p(gvol), lam, step, n_iter, n_power, flags, _p(sup), _p(h), _p(obj),
+                               ctypes.addressof(s)))
+    return h, obj[:n_iter], s.value
+
+
+def stripe_mask(geom: Geometry, a: float):
+    """chi_M for M_theta = R minus [-a, a] (the central detector stripe is missing, Sec. 4)."""
+    s = (np.arange(geom.ns) - 0.5 * (geom.ns - 1)) * geom.ds
+    row = (np.abs(s) > a).astype(np.uint8)
+    return np.ascontiguousarray(np.broadcast_to(row, geom.data_shape))

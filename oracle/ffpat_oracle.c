@@ -534,3 +534,81 @@ int orc_wave_history(const orc_geom *g, const double *c, const double *h, int32_
   free(kappa); free(lap);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Filtered backprojection X^-1 = X^* Lambda (Sec. 3.1), plane by plane.     */
+/* ------------------------------------------------------------------------ */
+int orc_fbp(const orc_geom *g, const double *G, double *vol)
+{
+  double *y = malloc(ndat(g) * sizeof(double));
+  if (!y) return -3;
+  orc_ramp(g, G, y);
+  orc_backproject(g, y, vol);
+  free(y);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 9 (Sec. 4.1): the second stage of the two-step method,         */
+/* forward-backward splitting on 1/2 ||W_T h - g||^2 + lambda R(h) with g a  */
+/* volume (the first stage is g = X^-1 G).  Same prox and step rules as      */
+/* orc_fb; the power iteration runs on W_T^T W_T.                           */
+/* ------------------------------------------------------------------------ */
+int orc_fb_two_step(const orc_geom *g, const double *c, const double *gvol, double lambda, double step,
+                    int32_t n_iter, int32_t n_power, uint32_t flags, const uint8_t *support, double *h,
+                    double *objective, double *step_used)
+{
+  size_t n = nvox(g);
+  int rc = 0;
+  double *r = malloc(n * sizeof(double)), *grad = malloc(n * sizeof(double));
+  double *f = malloc(n * sizeof(double)), *tmp = malloc(n * sizeof(double));
+  if (!r || !grad || !f || !tmp) { free(r); free(grad); free(f); free(tmp); return -3; }
+  double s = step;
+  if (s <= 0.0) {
+    /* power iteration on W^T W from the normalised all-ones vector */
+    for (size_t i = 0; i < n; ++i) f[i] = 1.0 / sqrt((double)n);
+    double L = 0.0;
+    for (int32_t it = 0; it < (n_power > 0 ? n_power : 20); ++it) {
+      rc = orc_wave(g, c, f, r);
+      if (!rc) rc = orc_wave_T(g, c, r, grad);
+      if (rc) break;
+      L = sqrt(orc_dot(grad, grad, n));
+      for (size_t i = 0; i < n; ++i) f[i] = grad[i] / L;
+    }
+    s = 1.0 / L;
+  }
+  if (step_used) *step_used = s;
+  for (int32_t k = 0; k < n_iter && rc == 0; ++k) {
+    rc = orc_wave(g, c, h, r);
+    if (rc) break;
+    for (size_t i = 0; i < n; ++i) r[i] -= gvol[i];
+    if (objective) {
+      double reg;
+      if (flags & ORC_REG_GRAD) {
+        orc_neg_lap7(g, h, tmp);
+        reg = 0.5 * orc_dot(h, tmp, n);
+      } else {
+        reg = 0.5 * orc_dot(h, h, n);
+      }
+      objective[k] = 0.5 * orc_dot(r, r, n) + lambda * reg;
+    }
+    rc = orc_wave_T(g, c, r, grad);
+    if (rc) break;
+    for (size_t i = 0; i < n; ++i) f[i] = h[i] - s * grad[i];
+    if (flags & ORC_REG_GRAD) {
+      int it = orc_prox_grad(g, s * lambda, f, h, 1e-13, 10000);
+      if (it < 0) { rc = it; break; }
+      if (support) for (size_t i = 0; i < n; ++i) if (!support[i]) h[i] = 0.0;
+    } else {
+      for (size_t i = 0; i < n; ++i) {
+        double v = f[i];
+        if ((flags & ORC_POSITIVITY) && v < 0.0) v = 0.0;
+        v = v / (1.0 + s * lambda);
+        if (support && !support[i]) v = 0.0;
+        h[i] = v;
+      }
+    }
+  }
+  free(r); free(grad); free(f); free(tmp);
+  return rc;
+}

@@ -18,10 +18,10 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _lib
-from ._lib import FfpatError, POSITIVITY, PRECOND, REG_GRAD, USE_PLAN_STEP
+from ._lib import FfpatError, POSITIVITY, PRECOND, REG_GRAD, TWO_STEP, USE_PLAN_STEP
 
 __all__ = ["Plan", "FfpatError", "ReconResult", "workspace_bytes", "version", "POSITIVITY", "PRECOND",
-           "REG_GRAD", "USE_PLAN_STEP"]
+           "REG_GRAD", "TWO_STEP", "USE_PLAN_STEP"]
 
 
 def version() -> str:
@@ -98,6 +98,7 @@ class Plan:
         self.ns = int(ns) if ns else int(nx)
         self.data_shape = (self.n_angles, nz, self.ns)
         self.dx, self.T = float(dx), float(T)
+        self.ds = float(ds) if ds else float(dx)
         nt = ctypes.c_int32(); dt = ctypes.c_double(); cm = ctypes.c_double()
         _lib.check(self._lib.ffpat_plan_info(self._h, ctypes.byref(nt), ctypes.byref(dt), ctypes.byref(cm)))
         self.nt, self.dt, self.cmax = nt.value, dt.value, cm.value
@@ -158,11 +159,33 @@ class Plan:
         """y = Lambda r."""
         return self._call(self._lib.ffpat_ramp, r, self.data_shape, out, self.data_shape, stream, "r")
 
+    def fbp(self, G, out=None, stream=None):
+        """vol = X^-1 G = X^T Lambda G (filtered backprojection per plane)."""
+        return self._call(self._lib.ffpat_fbp, G, self.data_shape, out, self.shape, stream, "G")
+
+    def landweber(self, G, n_iter, step=0.0, n_power=20, det_mask=None, h0=None, stream=None) -> ReconResult:
+        """Algorithm 7, preconditioned Landweber: Algorithm 8 with R = 0 (no prox)."""
+        return self.reconstruct(G, 0.0, n_iter, step=step, n_power=n_power, positivity=False, precond=True,
+                                det_mask=det_mask, h0=h0, stream=stream)
+
+    def stripe_mask(self, a):
+        """chi_M for M_theta = R minus [-a, a]: 1 where the detector coordinate |s| > a."""
+        torch = _torch()
+        s = (torch.arange(self.ns, dtype=torch.float64) - 0.5 * (self.ns - 1)) * self.ds
+        row = (s.abs() > a).to(torch.uint8)
+        return row.expand(self.data_shape).contiguous().to(self.device)
+
     def _fb_params(self, G, lam, n_iter, step, n_power, positivity, precond, support, det_mask, h,
-                   use_plan_step, objective):
-        self._check_tensor(G, self.data_shape, "G")
+                   use_plan_step, objective, reg="l2", two_step=False, cg_tol=0.0, cg_maxit=0):
+        self._check_tensor(G, self.shape if two_step else self.data_shape, "G")
         self._check_tensor(h, self.shape, "h")
+        if reg not in ("l2", "grad"):
+            raise ValueError("reg must be 'l2' (1/2||h||^2) or 'grad' (1/2||D h||^2)")
         flags = (POSITIVITY if positivity else 0) | (PRECOND if precond else 0)
+        if reg == "grad":
+            flags |= REG_GRAD
+        if two_step:
+            flags |= TWO_STEP
         if use_plan_step:
             flags |= USE_PLAN_STEP
         sup = 0
@@ -175,18 +198,21 @@ class Plan:
             msk = det_mask.data_ptr()
         obj_ptr = objective.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if objective is not None else None
         return _lib.FbParams(float(lam), float(step), int(n_iter), int(n_power), flags,
-                             ctypes.c_void_p(sup or None), ctypes.c_void_p(msk or None), obj_ptr)
+                             ctypes.c_void_p(sup or None), ctypes.c_void_p(msk or None), obj_ptr,
+                             float(cg_tol), int(cg_maxit))
 
     def reconstruct(self, G, lam, n_iter, step=0.0, n_power=20, positivity=True, precond=True,
                     support=None, det_mask=None, h0=None, use_plan_step=False, stream=None,
-                    want_objective=True) -> ReconResult:
-        """Algorithm 8: K = n_iter forward-backward iterations from h0 (zeros by default;
-        h0 is updated in place and returned as .h).  Synchronises the stream at the end."""
+                    want_objective=True, reg="l2", two_step=False, cg_tol=0.0, cg_maxit=0) -> ReconResult:
+        """Algorithm 8 (or Algorithm 9 with two_step=True and G = fbp(data)): K = n_iter
+        forward-backward iterations from h0 (zeros by default; h0 is updated in place and
+        returned as .h).  reg='grad' selects R = 1/2||D h||^2 (prox by conjugate gradients;
+        positivity must be False).  Synchronises the stream at the end."""
         torch = _torch()
         h = torch.zeros(self.shape, dtype=self.dtype, device=self.device) if h0 is None else h0
         obj = np.zeros(max(int(n_iter), 1), dtype=np.float64)
         prm = self._fb_params(G, lam, n_iter, step, n_power, positivity, precond, support, det_mask, h,
-                              use_plan_step, obj if want_objective else None)
+                              use_plan_step, obj if want_objective else None, reg, two_step, cg_tol, cg_maxit)
         s = ctypes.c_double()
         _lib.check(self._lib.ffpat_reconstruct(self._h, ctypes.c_void_p(G.data_ptr()), ctypes.byref(prm),
                                                ctypes.c_void_p(h.data_ptr()), ctypes.byref(s),
@@ -194,11 +220,12 @@ class Plan:
         return ReconResult(h=h, objective=obj[:int(n_iter)], step=s.value)
 
     def fb_enqueue(self, G, lam, n_iter, h, step=0.0, n_power=20, positivity=True, precond=True, support=None,
-                   det_mask=None, use_plan_step=False, stream=None):
+                   det_mask=None, use_plan_step=False, stream=None, reg="l2", two_step=False, cg_tol=0.0,
+                   cg_maxit=0):
         """Enqueues the step selection (unless use_plan_step or step > 0) and n_iter
         iterations on `stream` without host synchronisation (serving)."""
         prm = self._fb_params(G, lam, n_iter, step, n_power, positivity, precond, support, det_mask, h,
-                              use_plan_step, None)
+                              use_plan_step, None, reg, two_step, cg_tol, cg_maxit)
         _lib.check(self._lib.ffpat_fb_enqueue(self._h, ctypes.c_void_p(G.data_ptr()), ctypes.byref(prm),
                                               ctypes.c_void_p(h.data_ptr()),
                                               ctypes.c_void_p(_stream_handle(stream))))

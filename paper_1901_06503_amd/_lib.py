@@ -23,6 +23,7 @@ POSITIVITY = 1
 PRECOND = 2
 REG_GRAD = 4
 USE_PLAN_STEP = 8
+TWO_STEP = 16
 
 
 class FfpatError(RuntimeError):
@@ -43,7 +44,8 @@ class FbParams(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("step", ctypes.c_double), ("n_iter", ctypes.c_int32),
                 ("n_power", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("support", ctypes.c_void_p), ("det_mask", ctypes.c_void_p),
-                ("objective", ctypes.POINTER(ctypes.c_double))]
+                ("objective", ctypes.POINTER(ctypes.c_double)), ("cg_tol", ctypes.c_double),
+                ("cg_maxit", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -62,6 +64,7 @@ SIGNATURES = {
     "ffpat_project": ([_P, _P, _P, _P], ctypes.c_int),
     "ffpat_backproject": ([_P, _P, _P, _P], ctypes.c_int),
     "ffpat_ramp": ([_P, _P, _P, _P], ctypes.c_int),
+    "ffpat_fbp": ([_P, _P, _P, _P], ctypes.c_int),
     "ffpat_reconstruct": ([_P, _P, ctypes.POINTER(FbParams), _P, ctypes.POINTER(ctypes.c_double), _P],
                           ctypes.c_int),
     "ffpat_fb_enqueue": ([_P, _P, ctypes.POINTER(FbParams), _P, _P], ctypes.c_int),

@@ -12,7 +12,7 @@ namespace ffpat {
 struct Dims {
   int nx, ny, nz;
   int ndim;  // 3, or 2 for the z-invariant mode (no z coupling in the Laplacian)
-  size_t nvox() const { return (size_t)nx * ny * nz; }
+  __host__ __device__ size_t nvox() const { return (size_t)nx * ny * nz; }
 };
 
 // Per-angle parameters, computed on the host in double precision.
@@ -139,4 +139,40 @@ template <typename T>
 hipError_t launch_mul(const T *x, const T *k, T *y, size_t n, hipStream_t s);
 // dst[0] = v (a kernel, so that the write can sit inside a captured graph).
 hipError_t launch_set(double *dst, double v, hipStream_t s);
+}  // namespace ffpat
+
+namespace ffpat {
+// ---- gradient regulariser R = 1/2 ||D h||^2 (D: forward differences / dx, zero
+// outside the grid), D^T D = N = -(7-point Laplacian) (5-point in 2D mode).
+// partials[b] = sum over block b of h . (N h)
+template <typename T>
+hipError_t launch_neglap_dot(const Dims &d, double dx, const T *h, double *partials, hipStream_t s);
+
+// Conjugate gradients for (I + tau N) x = f, tau = step[0] * lambda, with FP64
+// scalars cg[] on the device: cg[0] rr, cg[1] ff, cg[2] pq, cg[3] rr_new,
+// cg[4] alpha, cg[5] beta, cg[6] done flag, cg[7] iterations.
+// Every kernel returns at once when cg[6] is set.
+template <typename T>
+hipError_t launch_cg_init(const Dims &d, double dx, const T *f, const T *x, T *r, T *p, const double *step,
+                          double lambda, double *partials_rr, double *partials_ff, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_apply(const Dims &d, double dx, const T *p, T *q, const double *step, double lambda,
+                           const double *cg, double *partials, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_update(const Dims &d, T *x, T *r, const T *p, const T *q, const double *cg,
+                            double *partials, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_direction(const Dims &d, T *p, const T *r, const double *cg, hipStream_t s);
+// scalar steps: after init (done if rr <= tol^2 ff), alpha = rr / pq, then beta / convergence
+hipError_t launch_cg_check_init(double *cg, double tol, hipStream_t s);
+hipError_t launch_cg_alpha(double *cg, hipStream_t s);
+hipError_t launch_cg_beta(double *cg, double tol, hipStream_t s);
+
+// h = 0 where support == 0
+template <typename T>
+hipError_t launch_apply_support(T *h, const uint8_t *support, size_t n, hipStream_t s);
+// f = h - step * grad (in place into grad allowed)
+// r = w - g (written over w), partials = sum r^2 per block
+template <typename T>
+hipError_t launch_vol_residual(T *w, const T *g, size_t n, double *partials, hipStream_t s);
 }  // namespace ffpat

@@ -232,3 +232,259 @@ FFPAT_INST(double)
 #undef FFPAT_INST
 
 }  // namespace ffpat
+
+// ===========================================================================
+// Gradient regulariser and its prox (conjugate gradients, device scalars).
+// ===========================================================================
+namespace ffpat {
+
+// (N u) at (x, y, z): 7-point (5-point in 2D) negative Laplacian / dx^2, zero outside.
+template <typename T>
+__device__ __forceinline__ T neglap_at(const T *__restrict__ u, int x, int y, int z, int nx, int ny, int nz, int ndim,
+                                       T inv_dx2)
+{
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  const size_t i = (size_t)z * sz + (size_t)y * sy + x;
+  const T c = u[i];
+  T acc = T(2 * ndim) * c;
+  if (x > 0) acc -= u[i - 1];
+  if (x + 1 < nx) acc -= u[i + 1];
+  if (y > 0) acc -= u[i - sy];
+  if (y + 1 < ny) acc -= u[i + sy];
+  if (ndim == 3) {
+    if (z > 0) acc -= u[i - sz];
+    if (z + 1 < nz) acc -= u[i + sz];
+  }
+  return acc * inv_dx2;
+}
+
+__device__ inline double block_sum_256b(double v, double *red)
+{
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// grid-stride over voxels with (x, y, z) decoded from the linear index
+#define FFPAT_VOXEL_LOOP(d, i, x, y, z)                                                                 \
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (d).nvox();                    \
+       i += (size_t)gridDim.x * blockDim.x)                                                          \
+    if (int x = (int)(i % (size_t)(d).nx), y = (int)((i / (size_t)(d).nx) % (size_t)(d).ny),         \
+        z = (int)(i / ((size_t)(d).nx * (d).ny)); true)
+
+template <typename T>
+__global__ void __launch_bounds__(256) neglap_dot_kernel(Dims d, T inv_dx2, const T *__restrict__ h, double *partials)
+{
+  __shared__ double red[256];
+  double acc = 0.0;
+  FFPAT_VOXEL_LOOP(d, i, x, y, z) acc += (double)h[i] * (double)neglap_at(h, x, y, z, d.nx, d.ny, d.nz, d.ndim, inv_dx2);
+  const double t = block_sum_256b(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <typename T>
+hipError_t launch_neglap_dot(const Dims &d, double dx, const T *h, double *partials, hipStream_t s)
+{
+  neglap_dot_kernel<T><<<kReduceBlocks, kReduceThreads, 0, s>>>(d, (T)(1.0 / (dx * dx)), h, partials);
+  return hipGetLastError();
+}
+
+// r = f - (x + tau N x), p = r; partial sums of r.r and f.f
+template <typename T>
+__global__ void __launch_bounds__(256)
+cg_init_kernel(Dims d, T inv_dx2, const T *__restrict__ f, const T *__restrict__ xv, T *__restrict__ r,
+               T *__restrict__ p, const double *step, double lambda, double *prr, double *pff)
+{
+  __shared__ double red[256];
+  const T tau = (T)(step[0] * lambda);
+  double rr = 0.0, ff = 0.0;
+  FFPAT_VOXEL_LOOP(d, i, x, y, z) {
+    const T ri = f[i] - (xv[i] + tau * neglap_at(xv, x, y, z, d.nx, d.ny, d.nz, d.ndim, inv_dx2));
+    r[i] = ri;
+    p[i] = ri;
+    rr += (double)ri * (double)ri;
+    ff += (double)f[i] * (double)f[i];
+  }
+  const double a = block_sum_256b(rr, red);
+  if (threadIdx.x == 0) prr[blockIdx.x] = a;
+  __syncthreads();
+  const double b = block_sum_256b(ff, red);
+  if (threadIdx.x == 0) pff[blockIdx.x] = b;
+}
+
+template <typename T>
+hipError_t launch_cg_init(const Dims &d, double dx, const T *f, const T *x, T *r, T *p, const double *step,
+                          double lambda, double *partials_rr, double *partials_ff, hipStream_t s)
+{
+  cg_init_kernel<T><<<kReduceBlocks, kReduceThreads, 0, s>>>(d, (T)(1.0 / (dx * dx)), f, x, r, p, step, lambda,
+                                                              partials_rr, partials_ff);
+  return hipGetLastError();
+}
+
+// q = p + tau N p; partial sums of p.q
+template <typename T>
+__global__ void __launch_bounds__(256)
+cg_apply_kernel(Dims d, T inv_dx2, const T *__restrict__ p, T *__restrict__ q, const double *step, double lambda,
+                const double *cg, double *partials)
+{
+  __shared__ double red[256];
+  if (cg[6] != 0.0) return;
+  const T tau = (T)(step[0] * lambda);
+  double acc = 0.0;
+  FFPAT_VOXEL_LOOP(d, i, x, y, z) {
+    const T qi = p[i] + tau * neglap_at(p, x, y, z, d.nx, d.ny, d.nz, d.ndim, inv_dx2);
+    q[i] = qi;
+    acc += (double)p[i] * (double)qi;
+  }
+  const double t = block_sum_256b(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <typename T>
+hipError_t launch_cg_apply(const Dims &d, double dx, const T *p, T *q, const double *step, double lambda,
+                           const double *cg, double *partials, hipStream_t s)
+{
+  cg_apply_kernel<T><<<kReduceBlocks, kReduceThreads, 0, s>>>(d, (T)(1.0 / (dx * dx)), p, q, step, lambda, cg,
+                                                               partials);
+  return hipGetLastError();
+}
+
+// x += alpha p; r -= alpha q; partial sums of r.r
+template <typename T>
+__global__ void __launch_bounds__(256)
+cg_update_kernel(size_t n, T *__restrict__ xv, T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ q,
+                 const double *cg, double *partials)
+{
+  __shared__ double red[256];
+  if (cg[6] != 0.0) return;
+  const T alpha = (T)cg[4];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    xv[i] += alpha * p[i];
+    const T ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    acc += (double)ri * (double)ri;
+  }
+  const double t = block_sum_256b(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <typename T>
+hipError_t launch_cg_update(const Dims &d, T *x, T *r, const T *p, const T *q, const double *cg, double *partials,
+                            hipStream_t s)
+{
+  cg_update_kernel<T><<<kReduceBlocks, kReduceThreads, 0, s>>>(d.nvox(), x, r, p, q, cg, partials);
+  return hipGetLastError();
+}
+
+// p = r + beta p (cg[5] is beta of the step just finished; skipped once converged)
+template <typename T>
+__global__ void cg_direction_kernel(size_t n, T *__restrict__ p, const T *__restrict__ r, const double *cg)
+{
+  if (cg[6] != 0.0) return;
+  const T beta = (T)cg[5];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = r[i] + beta * p[i];
+}
+
+template <typename T>
+hipError_t launch_cg_direction(const Dims &d, T *p, const T *r, const double *cg, hipStream_t s)
+{
+  cg_direction_kernel<T><<<2048, 256, 0, s>>>(d.nvox(), p, r, cg);
+  return hipGetLastError();
+}
+
+__global__ void cg_check_init_kernel(double *cg, double tol)
+{
+  if (threadIdx.x == 0) {
+    cg[7] = 0.0;
+    cg[6] = (cg[0] <= tol * tol * cg[1]) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void cg_alpha_kernel(double *cg)
+{
+  if (threadIdx.x == 0 && cg[6] == 0.0) cg[4] = cg[2] != 0.0 ? cg[0] / cg[2] : 0.0;
+}
+
+__global__ void cg_beta_kernel(double *cg, double tol)
+{
+  if (threadIdx.x == 0 && cg[6] == 0.0) {
+    cg[5] = cg[0] != 0.0 ? cg[3] / cg[0] : 0.0;
+    cg[0] = cg[3];
+    cg[7] += 1.0;
+    if (cg[3] <= tol * tol * cg[1] || !isfinite(cg[3])) cg[6] = 1.0;
+  }
+}
+
+hipError_t launch_cg_check_init(double *cg, double tol, hipStream_t s)
+{
+  cg_check_init_kernel<<<1, 64, 0, s>>>(cg, tol);
+  return hipGetLastError();
+}
+hipError_t launch_cg_alpha(double *cg, hipStream_t s)
+{
+  cg_alpha_kernel<<<1, 64, 0, s>>>(cg);
+  return hipGetLastError();
+}
+hipError_t launch_cg_beta(double *cg, double tol, hipStream_t s)
+{
+  cg_beta_kernel<<<1, 64, 0, s>>>(cg, tol);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void apply_support_kernel(T *h, const uint8_t *__restrict__ support, size_t n)
+{
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    if (!support[i]) h[i] = T(0);
+}
+
+template <typename T>
+hipError_t launch_apply_support(T *h, const uint8_t *support, size_t n, hipStream_t s)
+{
+  apply_support_kernel<T><<<2048, 256, 0, s>>>(h, support, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) vol_residual_kernel(T *w, const T *__restrict__ g, size_t n, double *partials)
+{
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const T r = w[i] - g[i];
+    w[i] = r;
+    acc += (double)r * (double)r;
+  }
+  const double t = block_sum_256b(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <typename T>
+hipError_t launch_vol_residual(T *w, const T *g, size_t n, double *partials, hipStream_t s)
+{
+  vol_residual_kernel<T><<<kReduceBlocks, kReduceThreads, 0, s>>>(w, g, n, partials);
+  return hipGetLastError();
+}
+
+#define FFPAT_INST2(T)                                                                                          \
+  template hipError_t launch_neglap_dot<T>(const Dims &, double, const T *, double *, hipStream_t);              \
+  template hipError_t launch_cg_init<T>(const Dims &, double, const T *, const T *, T *, T *, const double *,     \
+                                        double, double *, double *, hipStream_t);                              \
+  template hipError_t launch_cg_apply<T>(const Dims &, double, const T *, T *, const double *, double,          \
+                                         const double *, double *, hipStream_t);                               \
+  template hipError_t launch_cg_update<T>(const Dims &, T *, T *, const T *, const T *, const double *, double *, \
+                                          hipStream_t);                                                        \
+  template hipError_t launch_cg_direction<T>(const Dims &, T *, const T *, const double *, hipStream_t);        \
+  template hipError_t launch_apply_support<T>(T *, const uint8_t *, size_t, hipStream_t);                       \
+  template hipError_t launch_vol_residual<T>(T *, const T *, size_t, double *, hipStream_t);
+FFPAT_INST2(float)
+FFPAT_INST2(double)
+#undef FFPAT_INST2
+
+}  // namespace ffpat

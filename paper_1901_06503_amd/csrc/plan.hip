@@ -54,7 +54,8 @@ int hip_fail(hipError_t e, const char *where)
   } while (0)
 
 // Device scalar slots
-enum { SC_STEP = 0, SC_L = 1, SC_REG = 2, SC_DATA = 3, SC_NONFINITE = 4, SC_SUMSQ = 5, SC_ITER = 6, SC_COUNT = 8 };
+enum { SC_STEP = 0, SC_L = 1, SC_REG = 2, SC_DATA = 3, SC_NONFINITE = 4, SC_SUMSQ = 5, SC_ITER = 6, SC_CG = 8,
+       SC_COUNT = 16 };   // SC_CG .. SC_CG + 7: conjugate-gradient scalars
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -77,13 +78,19 @@ struct GraphCache {
   hipGraphExec_t exec = nullptr;
   const void *G = nullptr, *h = nullptr, *support = nullptr, *mask = nullptr;
   uint32_t flags = 0;
-  double lambda = 0.0;
-  int n_power = 0;
+  double lambda = 0.0, cg_tol = 0.0;
+  int n_power = 0, cg_maxit = 0;
   bool matches(const void *G_, const void *h_, const void *sup_, const void *m_, uint32_t f_, double lam_,
-               int np_) const
+               int np_, double tol_, int maxit_) const
   {
     return exec && G == G_ && h == h_ && support == sup_ && mask == m_ && flags == f_ && lambda == lam_ &&
-           n_power == np_;
+           n_power == np_ && cg_tol == tol_ && cg_maxit == maxit_;
+  }
+  void set(const void *G_, const void *h_, const void *sup_, const void *m_, uint32_t f_, double lam_, int np_,
+           double tol_, int maxit_)
+  {
+    G = G_; h = h_; support = sup_; mask = m_; flags = f_; lambda = lam_; n_power = np_; cg_tol = tol_;
+    cg_maxit = maxit_;
   }
 };
 
@@ -369,16 +376,45 @@ int data_residual(ffpat_plan *P, const T *v, const T *G, const uint8_t *mask, bo
   return FFPAT_OK;
 }
 
+// Conjugate-gradient iteration controls (defaults when the caller passes 0).
+struct CgControl {
+  double tol;
+  int maxit;
+};
+
 template <typename T>
-int power_iteration(ffpat_plan *P, int n_power, bool precond, const uint8_t *mask, hipStream_t s)
+CgControl cg_control(const ffpat_fb_params *prm)
+{
+  CgControl c;
+  c.tol = prm->cg_tol > 0 ? prm->cg_tol : (sizeof(T) == 8 ? 1e-12 : 1e-6);
+  c.maxit = prm->cg_maxit > 0 ? prm->cg_maxit : 200;
+  return c;
+}
+
+// w = A^T chi Lambda chi A v (one-step) or W^T W v (two-step) into V3; scratch V1, V2.
+template <typename T>
+int normal_operator(ffpat_plan *P, const T *v, bool two_step, bool precond, const uint8_t *mask, hipStream_t s)
+{
+  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1)), *V3 = static_cast<T *>(P->vol(2));
+  if (two_step) {
+    int rc = wave_forward<T>(P, v, V2, V1, s);
+    if (rc) return rc;
+    HIP_TRY(launch_mul<T>(V2, static_cast<const T *>(P->kap()), V1, P->nvox, s));
+    return wave_adjoint_from_scaled<T>(P, V1, V3, V2, s);
+  }
+  int rc = data_residual<T>(P, v, nullptr, mask, precond, nullptr, s);
+  if (rc) return rc;
+  return op_adjoint_padded<T>(P, V3, s);
+}
+
+template <typename T>
+int power_iteration(ffpat_plan *P, int n_power, bool two_step, bool precond, const uint8_t *mask, hipStream_t s)
 {
   T *V3 = static_cast<T *>(P->vol(2)), *V4 = static_cast<T *>(P->vol(3));
   double *sc = P->scalars();
   HIP_TRY(launch_fill<T>(V4, P->nvox, 1.0 / std::sqrt((double)P->nvox), s));
   for (int it = 0; it < n_power; ++it) {
-    int rc = data_residual<T>(P, V4, nullptr, mask, precond, nullptr, s);
-    if (rc) return rc;
-    rc = op_adjoint_padded<T>(P, V3, s);
+    int rc = normal_operator<T>(P, V4, two_step, precond, mask, s);
     if (rc) return rc;
     HIP_TRY(launch_sumsq<T>(V3, P->nvox, P->partials(), s));
     HIP_TRY(launch_reduce_to(P->partials(), kReduceBlocks, 1.0, sc + SC_SUMSQ, s));
@@ -388,30 +424,79 @@ int power_iteration(ffpat_plan *P, int n_power, bool precond, const uint8_t *mas
   return FFPAT_OK;
 }
 
-// One iteration of Algorithm 8.  The objective goes to obj[counter], counter++
-// (device-side), so the same launch sequence serves every iteration and can
-// be captured once as a graph.
+// h <- prox_{s lambda R}(h - s grad), grad in V3.  l2 (+ positivity): closed form;
+// gradient regulariser: (I + s lambda N) h = f by conjugate gradients started from
+// h_k, with f in V1 and r, p, q in V2, V4, V3.  Support mask applied last.
+template <typename T>
+int prox_step(ffpat_plan *P, T *h, const ffpat_fb_params *prm, hipStream_t s)
+{
+  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1)), *V3 = static_cast<T *>(P->vol(2)),
+    *V4 = static_cast<T *>(P->vol(3));
+  double *sc = P->scalars();
+  if (!(prm->flags & FFPAT_REG_GRAD)) {
+    HIP_TRY(launch_prox_l2<T>(h, V3, P->nvox, sc + SC_STEP, prm->lambda, (prm->flags & FFPAT_POSITIVITY) ? 1 : 0,
+                              prm->support, s));
+    return FFPAT_OK;
+  }
+  const CgControl cc = cg_control<T>(prm);
+  double *cg = sc + SC_CG;
+  double *pa = P->partials(), *pb = P->partials() + kReduceBlocks;
+  HIP_TRY(launch_grad_step<T>(h, V3, V1, P->nvox, sc + SC_STEP, s));                 // f = h - s grad
+  HIP_TRY(launch_cg_init<T>(P->d, P->dx, V1, h, V2, V4, sc + SC_STEP, prm->lambda, pa, pb, s));
+  HIP_TRY(launch_reduce_to(pa, kReduceBlocks, 1.0, cg + 0, s));
+  HIP_TRY(launch_reduce_to(pb, kReduceBlocks, 1.0, cg + 1, s));
+  HIP_TRY(launch_cg_check_init(cg, cc.tol, s));
+  for (int it = 0; it < cc.maxit; ++it) {
+    HIP_TRY(launch_cg_apply<T>(P->d, P->dx, V4, V3, sc + SC_STEP, prm->lambda, cg, pa, s));
+    HIP_TRY(launch_reduce_to(pa, kReduceBlocks, 1.0, cg + 2, s));
+    HIP_TRY(launch_cg_alpha(cg, s));
+    HIP_TRY(launch_cg_update<T>(P->d, h, V2, V4, V3, cg, pa, s));
+    HIP_TRY(launch_reduce_to(pa, kReduceBlocks, 1.0, cg + 3, s));
+    HIP_TRY(launch_cg_beta(cg, cc.tol, s));
+    HIP_TRY(launch_cg_direction<T>(P->d, V4, V2, cg, s));
+  }
+  if (prm->support) HIP_TRY(launch_apply_support<T>(h, prm->support, P->nvox, s));
+  return FFPAT_OK;
+}
+
+// One iteration of Algorithm 8 (or of Algorithm 9 with FFPAT_TWO_STEP, where G
+// is the volume g = X^-1 G and the operator is W_T).  The objective goes to
+// obj[counter], counter++ (device-side), so the same launch sequence serves
+// every iteration and can be captured once as a graph.
 template <typename T>
 int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, hipStream_t s)
 {
   const bool precond = prm->flags & FFPAT_PRECOND;
-  T *V3 = static_cast<T *>(P->vol(2));
+  const bool two_step = prm->flags & FFPAT_TWO_STEP;
+  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1)), *V3 = static_cast<T *>(P->vol(2));
   double *sc = P->scalars();
-  // R(h_k) for the objective
-  HIP_TRY(launch_sumsq<T>(h, P->nvox, P->partials(), s));
+  // R(h_k) for the objective: ||h||^2 or h . N h
+  if (prm->flags & FFPAT_REG_GRAD) HIP_TRY(launch_neglap_dot<T>(P->d, P->dx, h, P->partials(), s));
+  else HIP_TRY(launch_sumsq<T>(h, P->nvox, P->partials(), s));
   HIP_TRY(launch_reduce_to(P->partials(), kReduceBlocks, 1.0, sc + SC_REG, s));
-  // r = chi (A h - G), y = chi Lambda r, data term
-  int rc = data_residual<T>(P, h, G, prm->det_mask, precond, P->partials(), s);
-  if (rc) return rc;
-  HIP_TRY(launch_reduce_to(P->partials(), P->rows, 1.0, sc + SC_DATA, s));
-  HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->obj, sc + SC_ITER, P->obj_cap,
-                           sc + SC_NONFINITE, s));
-  // gradient A^T y, then the prox step
-  rc = op_adjoint_padded<T>(P, V3, s);
-  if (rc) return rc;
-  HIP_TRY(launch_prox_l2<T>(h, V3, P->nvox, sc + SC_STEP, prm->lambda, (prm->flags & FFPAT_POSITIVITY) ? 1 : 0,
-                            prm->support, s));
-  return FFPAT_OK;
+  int rc;
+  if (two_step) {
+    // r = W h - g, data term ||r||^2, gradient W^T r
+    rc = wave_forward<T>(P, h, V2, V1, s);
+    if (rc) return rc;
+    HIP_TRY(launch_vol_residual<T>(V2, G, P->nvox, P->partials(), s));
+    HIP_TRY(launch_reduce_to(P->partials(), kReduceBlocks, 1.0, sc + SC_DATA, s));
+    HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->obj, sc + SC_ITER, P->obj_cap,
+                             sc + SC_NONFINITE, s));
+    HIP_TRY(launch_mul<T>(V2, static_cast<const T *>(P->kap()), V1, P->nvox, s));
+    rc = wave_adjoint_from_scaled<T>(P, V1, V3, V2, s);
+    if (rc) return rc;
+  } else {
+    // r = chi (A h - G), y = chi Lambda r, data term, gradient A^T y
+    rc = data_residual<T>(P, h, G, prm->det_mask, precond, P->partials(), s);
+    if (rc) return rc;
+    HIP_TRY(launch_reduce_to(P->partials(), P->rows, 1.0, sc + SC_DATA, s));
+    HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->obj, sc + SC_ITER, P->obj_cap,
+                             sc + SC_NONFINITE, s));
+    rc = op_adjoint_padded<T>(P, V3, s);
+    if (rc) return rc;
+  }
+  return prox_step<T>(P, h, prm, s);
 }
 
 // Records `body(stream)` into a graph on the plan's capture stream.
@@ -460,6 +545,7 @@ template <typename T>
 int fb_enqueue(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, hipStream_t s)
 {
   const bool precond = prm->flags & FFPAT_PRECOND;
+  const bool two_step = prm->flags & FFPAT_TWO_STEP;
   const int n_power = prm->n_power > 0 ? prm->n_power : 20;
   double *sc = P->scalars();
   int rc = ensure_objective_capacity(P, prm->n_iter, s);
@@ -471,34 +557,28 @@ int fb_enqueue(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, hipS
   } else if (prm->step > 0) {
     HIP_TRY(launch_set(sc + SC_STEP, prm->step, s));
   } else if (P->use_graphs) {
-    const uint32_t key = precond ? FFPAT_PRECOND : 0u;
-    if (!P->g_power.matches(nullptr, nullptr, nullptr, prm->det_mask, key, 0.0, n_power)) {
+    const uint32_t key = prm->flags & (FFPAT_PRECOND | FFPAT_TWO_STEP);
+    if (!P->g_power.matches(nullptr, nullptr, nullptr, prm->det_mask, key, 0.0, n_power, 0.0, 0)) {
       rc = capture_graph(P, P->g_power, [&](hipStream_t cs) {
-        return power_iteration<T>(P, n_power, precond, prm->det_mask, cs);
+        return power_iteration<T>(P, n_power, two_step, precond, prm->det_mask, cs);
       });
       if (rc) return rc;
-      P->g_power.mask = prm->det_mask;
-      P->g_power.flags = key;
-      P->g_power.n_power = n_power;
+      P->g_power.set(nullptr, nullptr, nullptr, prm->det_mask, key, 0.0, n_power, 0.0, 0);
     }
     HIP_TRY(hipGraphLaunch(P->g_power.exec, s));
   } else {
-    rc = power_iteration<T>(P, n_power, precond, prm->det_mask, s);
+    rc = power_iteration<T>(P, n_power, two_step, precond, prm->det_mask, s);
     if (rc) return rc;
   }
   P->has_step = true;
   if (prm->n_iter <= 0) return FFPAT_OK;
   if (P->use_graphs) {
-    const uint32_t key = prm->flags & (FFPAT_PRECOND | FFPAT_POSITIVITY);
-    if (!P->g_iter.matches(G, h, prm->support, prm->det_mask, key, prm->lambda, 0)) {
+    const uint32_t key = prm->flags & (FFPAT_PRECOND | FFPAT_POSITIVITY | FFPAT_REG_GRAD | FFPAT_TWO_STEP);
+    const CgControl cc = cg_control<T>(prm);
+    if (!P->g_iter.matches(G, h, prm->support, prm->det_mask, key, prm->lambda, 0, cc.tol, cc.maxit)) {
       rc = capture_graph(P, P->g_iter, [&](hipStream_t cs) { return fb_iteration<T>(P, G, h, prm, cs); });
       if (rc) return rc;
-      P->g_iter.G = G;
-      P->g_iter.h = h;
-      P->g_iter.support = prm->support;
-      P->g_iter.mask = prm->det_mask;
-      P->g_iter.flags = key;
-      P->g_iter.lambda = prm->lambda;
+      P->g_iter.set(G, h, prm->support, prm->det_mask, key, prm->lambda, 0, cc.tol, cc.maxit);
     }
     for (int k = 0; k < prm->n_iter; ++k) HIP_TRY(hipGraphLaunch(P->g_iter.exec, s));
   } else {
@@ -535,6 +615,16 @@ int reconstruct(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, dou
   int rc = fb_enqueue<T>(P, G, prm, h, s);
   if (rc) return rc;
   return fb_report(P, step_used, prm->objective, prm->objective ? prm->n_iter : 0, s);
+}
+
+template <typename T>
+int fbp_op(ffpat_plan *P, const T *G, T *vol, hipStream_t s)
+{
+  HIP_TRY(launch_residual_ramp<T>(P->rows, P->ns, G, nullptr, nullptr, static_cast<const T *>(P->taps()),
+                                  static_cast<T *>(P->padD()), P->ns + kRowPadL + kRowPadR, kRowPadL, nullptr, s));
+  HIP_TRY(launch_backproject<T>(P->d, P->n_angles, P->ns, P->ap(), P->two_tap, static_cast<const T *>(P->padD()),
+                                vol, nullptr, s));
+  return FFPAT_OK;
 }
 
 bool is_f64(const ffpat_plan *P) { return P->dtype == FFPAT_F64; }
@@ -769,6 +859,17 @@ int ffpat_ramp(ffpat_plan *plan, const void *r_dev, void *y_dev, void *stream)
   return e == hipSuccess ? FFPAT_OK : hip_fail(e, "ramp");
 }
 
+int ffpat_fbp(ffpat_plan *plan, const void *G_dev, void *vol_dev, void *stream)
+{
+  CHECK_PLAN(plan);
+  CHECK_PTR(G_dev, "G_dev");
+  CHECK_PTR(vol_dev, "vol_dev");
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return DISPATCH(plan, fbp_op<float>(plan, (const float *)G_dev, (float *)vol_dev, s),
+                  fbp_op<double>(plan, (const double *)G_dev, (double *)vol_dev, s));
+}
+
 static int check_fb_args(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev)
 {
   CHECK_PLAN(plan);
@@ -779,7 +880,12 @@ static int check_fb_args(ffpat_plan *plan, const void *G_dev, const ffpat_fb_par
   if (params->n_power < 0) return fail(FFPAT_EINVAL, "n_power must be >= 0");
   if (!(params->lambda >= 0) || !std::isfinite(params->lambda)) return fail(FFPAT_EINVAL, "lambda must be finite and >= 0");
   if (!std::isfinite(params->step)) return fail(FFPAT_EINVAL, "step must be finite");
-  if (params->flags & FFPAT_REG_GRAD) return fail(FFPAT_EINVAL, "FFPAT_REG_GRAD is not available in this build");
+  if (params->cg_maxit < 0 || params->cg_maxit > 100000) return fail(FFPAT_EINVAL, "cg_maxit must be in [0, 100000]");
+  if (!(params->cg_tol >= 0) || !std::isfinite(params->cg_tol)) return fail(FFPAT_EINVAL, "cg_tol must be >= 0");
+  if ((params->flags & FFPAT_TWO_STEP) && params->det_mask)
+    return fail(FFPAT_EINVAL, "FFPAT_TWO_STEP works on volumes: det_mask must be NULL");
+  if ((params->flags & FFPAT_REG_GRAD) && (params->flags & FFPAT_POSITIVITY))
+    return fail(FFPAT_EINVAL, "FFPAT_REG_GRAD and FFPAT_POSITIVITY cannot be combined (no closed-form prox)");
   return FFPAT_OK;
 }
 

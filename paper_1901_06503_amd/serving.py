@@ -58,7 +58,14 @@ class _Active:
         self.job, self.plan, self.stream, self.h, self.G = job, plan, stream, h, G
         self.done_iters = 0
         self.event = None
+        self.busy = False
         self.bytes = 0
+        self.last_chunk = 0
+
+
+def _remaining_work(a) -> float:
+    """Remaining point updates of an active job (two wave solves per FB iteration)."""
+    return 2.0 * a.plan.nt * a.job.c.numel() * (a.job.n_iter - a.done_iters)
 
 
 class Scheduler:
@@ -68,13 +75,18 @@ class Scheduler:
     max_active: slots.  iters_per_turn: FB iterations enqueued per job per turn.
     """
 
-    def __init__(self, hbm_budget: int, max_active: int = 8, iters_per_turn: int = 5, device="cuda"):
+    def __init__(self, hbm_budget: int, max_active: int = 8, iters_per_turn: int = 5, concurrency: int = 0,
+                 device="cuda"):
         self.hbm_budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.iters_per_turn = max(1, int(iters_per_turn))
+        # how many admitted jobs advance at a time: 0 = all (round robin); k > 0 = the k
+        # jobs with the least remaining work (the others stay resident and wait)
+        self.concurrency = int(concurrency)
         self.device = device
         self.peak_bytes = 0
         self.peak_active = 0
+        self.peak_running = 0
 
     def _admit(self, job, now):
         import torch
@@ -90,6 +102,7 @@ class Scheduler:
         a = _Active(job, plan, stream, h, G)
         a.event = torch.cuda.Event()
         a.event.record(stream)
+        a.busy = True
         job.t_admit = now
         job.status = "running"
         return a
@@ -103,10 +116,11 @@ class Scheduler:
         a.last_chunk = k
         a.event = torch.cuda.Event()
         a.event.record(a.stream)
+        a.busy = True
 
     def _collect(self, a):
         """Objective values of the chunk that just finished (stream already idle)."""
-        step, obj = a.plan.fb_report(getattr(a, "last_chunk", 0), stream=a.stream)
+        step, obj = a.plan.fb_report(a.last_chunk, stream=a.stream)
         a.job.step = step
         a.job.objective.extend(obj.tolist())
 
@@ -137,25 +151,39 @@ class Scheduler:
                 self.peak_bytes = max(self.peak_bytes, used)
                 self.peak_active = max(self.peak_active, len(active))
                 progressed = True
-            # progress: every job whose previous work has completed gets its next chunk
+            # retire finished jobs; collect the objective of completed chunks
             for a in list(active):
-                if not a.event.query():
-                    continue
-                progressed = True
-                try:
-                    if a.done_iters > 0:
-                        self._collect(a)
-                    if a.done_iters < a.job.n_iter:
+                if a.busy and a.event.query():
+                    a.busy = False
+                    progressed = True
+                    try:
+                        if a.done_iters > 0:
+                            self._collect(a)
+                        if a.done_iters < a.job.n_iter:
+                            continue
+                        a.job.status = "done"
+                    except FfpatError as e:
+                        a.job.status = f"failed: {e}"
+                    a.job.h = a.h
+                    a.job.t_done = time.perf_counter() - t0
+                    a.plan.close()
+                    used -= a.bytes
+                    active.remove(a)
+            # advance: all idle jobs, or the `concurrency` jobs with the least remaining work
+            order = sorted(active, key=_remaining_work) if self.concurrency > 0 else active
+            chosen = order[:self.concurrency] if self.concurrency > 0 else order
+            for a in chosen:
+                if not a.busy:
+                    try:
                         self._advance(a)
-                        continue
-                    a.job.status = "done"
-                except FfpatError as e:
-                    a.job.status = f"failed: {e}"
-                a.job.h = a.h
-                a.job.t_done = time.perf_counter() - t0
-                a.plan.close()
-                used -= a.bytes
-                active.remove(a)
+                        progressed = True
+                    except FfpatError as e:
+                        a.job.status = f"failed: {e}"
+                        a.job.t_done = time.perf_counter() - t0
+                        a.plan.close()
+                        used -= a.bytes
+                        active.remove(a)
+            self.peak_running = max(self.peak_running, sum(1 for a in active if a.busy))
             if not progressed:
                 time.sleep(0.0002)
         return jobs

@@ -100,16 +100,17 @@ def test_results_in_the_mix_equal_results_alone():
     from paper_1901_06503_amd.serving import Scheduler, run_serial, summary
     jobs = _trace([24, 40, 32, 48, 24, 40, 32, 24], 70)
     alone = run_serial(_clone(jobs))
-    sched = Scheduler(hbm_budget=8 << 30, max_active=4, iters_per_turn=3)
-    mixed = sched.run(_clone(jobs))
-    assert sched.peak_active > 1                           # work really overlapped
-    for a, b in zip(sorted(alone, key=lambda j: j.job_id), sorted(mixed, key=lambda j: j.job_id)):
-        assert a.status == b.status == "done"
-        assert a.step == b.step
-        assert torch.equal(a.h, b.h)
-        assert np.array_equal(np.array(a.objective), np.array(b.objective))
-    s = summary(mixed)
-    assert s["jobs"] == len(jobs) and math.isfinite(s["latency_p99_s"])
+    for concurrency in (0, 2):
+        sched = Scheduler(hbm_budget=8 << 30, max_active=4, iters_per_turn=3, concurrency=concurrency)
+        mixed = sched.run(_clone(jobs))
+        assert sched.peak_running > 1                      # work really overlapped on the device
+        for a, b in zip(sorted(alone, key=lambda j: j.job_id), sorted(mixed, key=lambda j: j.job_id)):
+            assert a.status == b.status == "done"
+            assert a.step == b.step
+            assert torch.equal(a.h, b.h)
+            assert np.array_equal(np.array(a.objective), np.array(b.objective))
+        s = summary(mixed)
+        assert s["jobs"] == len(jobs) and math.isfinite(s["latency_p99_s"])
 
 
 def test_admission_respects_the_hbm_budget():

@@ -166,3 +166,58 @@ def test_fb_gradient_regulariser_converges_to_normal_equations(oracle, problem):
     ref = np.linalg.solve(H + lam * D, A.T @ Lam @ G.ravel())
     h, _, _ = oracle.fb(g, c, G, lam, step=1.0 / lam_max, n_iter=2000, flags=oracle.PRECOND | oracle.REG_GRAD)
     assert rel_l2(h.ravel(), ref) <= 1e-8
+
+
+# ---------------------------------------------------------------- two-step method (Algorithm 9)
+def test_fbp_inverts_the_xray_transform_on_smooth_objects(oracle):
+    """X^-1 = X^* Lambda (Sec. 3.1): fbp(X v) ~ v."""
+    n = 64
+    dx = synth.grid_spacing(n)
+    g = oracle.Geometry(nx=n, ny=n, nz=2, dx=dx, T=0.1, angles=synth.uniform_angles(96))
+    vol = synth.gaussian_blob(g.vol_shape, dx, (-0.15, 0.2, 0.0), 4 * dx)
+    rec = oracle.fbp(g, oracle.project(g, vol))
+    inner = np.hypot(*np.meshgrid(synth.axis(n, dx), synth.axis(n, dx))) < 1.0
+    for z in range(2):
+        assert rel_l2(rec[z][inner], vol[z][inner]) < 0.05
+
+
+@pytest.fixture(scope="module")
+def wave_problem(oracle):
+    g = tiny(oracle, n=(5, 5, 4))
+    rng = np.random.default_rng(31)
+    c = rng.uniform(0.85, 1.15, size=g.vol_shape)
+    W = dense(lambda f: oracle.wave(g, c, f), g.vol_shape)
+    gv = rng.normal(size=g.vol_shape)
+    return g, c, W, gv
+
+
+def test_two_step_fb_converges_to_normal_equations(oracle, wave_problem):
+    g, c, W, gv = wave_problem
+    H = W.T @ W
+    lam_max = np.linalg.eigvalsh(0.5 * (H + H.T)).max()
+    lam = 0.3 * lam_max
+    ref = np.linalg.solve(H + lam * np.eye(H.shape[0]), W.T @ gv.ravel())
+    h, obj, s = oracle.fb_two_step(g, c, gv, lam, step=1.0 / lam_max, n_iter=300, flags=0)
+    assert rel_l2(h.ravel(), ref) <= 1e-10
+    assert np.all(np.diff(obj) <= 1e-12 * abs(obj[0]))
+    _, _, s_pow = oracle.fb_two_step(g, c, gv, lam, step=0.0, n_iter=0, n_power=3000, flags=0)
+    assert 1.0 / s_pow == pytest.approx(lam_max, rel=1e-10)
+
+
+def test_two_step_fb_gradient_regulariser(oracle, wave_problem):
+    g, c, W, gv = wave_problem
+    H = W.T @ W
+    D = dense(lambda f: oracle.neg_lap7(g, f), g.vol_shape)
+    lam_max = np.linalg.eigvalsh(0.5 * (H + H.T)).max()
+    lam = 0.02 * lam_max * g.dx ** 2
+    ref = np.linalg.solve(H + lam * D, W.T @ gv.ravel())
+    h, _, _ = oracle.fb_two_step(g, c, gv, lam, step=1.0 / lam_max, n_iter=1500, flags=oracle.REG_GRAD)
+    assert rel_l2(h.ravel(), ref) <= 1e-8
+
+
+def test_stripe_mask(oracle):
+    g = oracle.Geometry(nx=11, ny=11, nz=2, dx=0.2, T=0.1, angles=synth.uniform_angles(3))
+    m = oracle.stripe_mask(g, 0.5)
+    assert m.shape == g.data_shape
+    s = (np.arange(11) - 5) * 0.2
+    assert np.array_equal(m[1, 1], (np.abs(s) > 0.5).astype(np.uint8))
