@@ -35,18 +35,110 @@ def parse():
     ap.add_argument("--fp64-compare", type=int, default=1, help="also time FB iterations in FP64 (1/0)")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="time the oracle on a bounded sample (1/0)")
     ap.add_argument("--naive-stencil", action="store_true")
+    ap.add_argument("--stencil", default="auto", choices=["auto", "single", "pairs"],
+                    help="--mode wave: leapfrog steps per stencil pass (auto: the plan's choice)")
     ap.add_argument("--seed", type=int, default=3001)
-    ap.add_argument("--mode", default="fb", choices=["fb", "wave", "copy", "serve"],
+    ap.add_argument("--mode", default="fb", choices=["fb", "wave", "copy", "serve", "precision", "paper2d"],
                     help="fb: the benchmark; wave: only W_T applications (for counter runs); "
                          "copy: a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--reps", type=int, default=2, help="applications in --mode wave / copies in --mode copy")
     ap.add_argument("--jobs", type=int, default=120, help="--mode serve: jobs in the trace")
     ap.add_argument("--rate", type=float, default=4.0, help="--mode serve: mean arrivals per second (Poisson)")
-    ap.add_argument("--iters", type=int, default=50, help="--mode serve: FB iterations per job")
+    ap.add_argument("--iters", type=int, default=None,
+                    help="--mode serve: FB iterations per job (50); --mode precision: iterations (200)")
     ap.add_argument("--slots", type=int, default=6, help="--mode serve: admitted (resident) jobs")
     ap.add_argument("--concurrency", type=int, default=2,
-                    help="--mode serve: jobs advancing at a time (least remaining work first); 0 = all")
+                    help="--mode serve: jobs advancing at a time (the oldest + the least remaining work); 0 = all")
     return ap.parse_args()
+
+
+def run_precision(args):
+    """384^3 / 360 angles / T = 0.6: Algorithm 8 for --iters iterations (default 200) in
+    FP32 fields with FP64 reductions and in all-FP64, on the same data; reports the
+    relative L2 difference of the two reconstructions and each one's error against
+    the phantom, and the FB iteration rate of both."""
+    import numpy as np
+    import torch
+    import paper_1901_06503_amd as ff
+    import synth
+    case = synth.make_case("c384", args.seed)
+    case.c = case.c.astype(np.float32).astype(np.float64)         # identical c (and n_t) in both plans
+    case.h_true = case.h_true.astype(np.float32).astype(np.float64)
+    n_iter = args.iters if args.iters is not None else case.n_iter
+    dev = torch.device("cuda:0")
+    out = {"mode": "precision", "grid": case.n, "angles": len(case.angles), "T": case.T, "iters": n_iter}
+    recon = {}
+    with ff.Plan(torch.from_numpy(case.c).to(dev), case.dx, case.T, case.angles) as P64:
+        clean = P64.forward(torch.from_numpy(case.h_true).to(dev))
+        G64 = clean + case.noise_level * float(clean.mean()) * torch.from_numpy(case.noise).to(dev)
+        out["nt"] = P64.nt
+    for name, dtype in (("f32", torch.float32), ("f64", torch.float64)):
+        with ff.Plan(torch.from_numpy(case.c).to(dev, dtype), case.dx, case.T, case.angles) as P:
+            G = G64.to(dtype)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = P.reconstruct(G, case.lam, n_iter, step=0.0, n_power=case.n_power)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            recon[name] = res.h.double()
+            out[name] = {"seconds": t, "fb_iter_per_s_incl_power": n_iter / t, "step": res.step,
+                         "objective_first": float(res.objective[0]), "objective_last": float(res.objective[-1])}
+            log(f"{name}: {t:.1f}s for {n_iter} iterations + {case.n_power} power steps")
+    h_true = torch.from_numpy(case.h_true).to(dev)
+    d = float((recon["f32"] - recon["f64"]).norm() / recon["f64"].norm())
+    out["rel_l2_f32_vs_f64"] = d
+    for name in ("f32", "f64"):
+        out[name]["rel_l2_vs_phantom"] = float((recon[name] - h_true).norm() / h_true.norm())
+    print(json.dumps(out), flush=True)
+
+
+def run_paper2d(args):
+    """The paper's 2D experiment geometry (Sec. 4.1/4.2) on synthetic inputs: one-step
+    (Algorithm 8) vs two-step (Algorithm 9) vs one-step with the mean constant speed,
+    R = 1/2 ||grad h||^2, 60 iterations, 20% noise, stripe [-1, 1] missing, for a sweep
+    of lambda (the paper's lambda = 0.5 and s = 0.2 belong to its own, unstated,
+    discrete normalisation; the step here comes from the power iteration)."""
+    import numpy as np
+    import torch
+    import paper_1901_06503_amd as ff
+    import synth
+    k = synth.paper2d_case(args.seed)
+    dev = torch.device("cuda:0")
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32)
+    n_iter = args.iters or 60
+    lams = [0.5, 5e-2, 5e-3, 5e-4, 5e-5]
+    out = {"mode": "paper2d", "grid": k["h"].shape[-1], "angles": len(k["angles"]), "T": k["T"], "iters": n_iter,
+           "regulariser": "1/2 ||grad h||^2", "noise": "20% of mean(XWh)", "missing_stripe": k["stripe"],
+           "runs": []}
+    h_true = f32(k["h"])
+    support = torch.from_numpy(k["support"]).to(dev)
+    rel = lambda h: float((h - h_true).norm() / h_true.norm())
+    cmean = float(np.mean(k["c"]))
+    with ff.Plan(f32(k["c"]), k["dx"], k["T"], k["angles"], ndim=2) as P, \
+            ff.Plan(torch.full_like(f32(k["c"]), cmean), k["dx"], k["T"], k["angles"], ndim=2) as Pc:
+        out["nt"] = P.nt
+        mask = P.stripe_mask(k["stripe"])
+        clean = P.forward(h_true)
+        noise = f32(k["noise"]) * 0.2 * float(clean.double().mean())
+        out["data_error"] = float(noise.norm() / clean.norm())
+        G = (clean + noise) * mask
+        g = P.fbp(G)
+        for lam in lams:
+            t0 = time.perf_counter()
+            one = P.reconstruct(G, lam, n_iter, reg="grad", positivity=False, det_mask=mask, support=support,
+                                cg_maxit=400)
+            t_one = time.perf_counter() - t0
+            two = P.reconstruct(g, lam, n_iter, reg="grad", positivity=False, two_step=True, support=support,
+                                cg_maxit=400)
+            const = Pc.reconstruct(G, lam, n_iter, reg="grad", positivity=False, det_mask=mask,
+                                   support=support, cg_maxit=400)
+            run = {"lambda": lam, "one_step_rel_error": rel(one.h), "two_step_rel_error": rel(two.h),
+                   "constant_speed_rel_error": rel(const.h), "one_step_seconds": t_one, "step": one.step}
+            out["runs"].append(run)
+            log(f"paper2d {run}")
+    best = min(out["runs"], key=lambda r: r["one_step_rel_error"])
+    out["best_lambda"] = best["lambda"]
+    print(json.dumps(out), flush=True)
 
 
 def run_serve(args):
@@ -71,7 +163,7 @@ def run_serve(args):
             G = g + 0.02 * float(g.double().mean()) * noise
         torch.cuda.synchronize()
         jobs.append(serving.Job(job_id=i, arrival=float(t), c=c.cpu().pin_memory(), G=G.cpu().pin_memory(), dx=dx,
-                                T=0.5, angles=angles, lam=1e-3, n_iter=args.iters, n_power=20))
+                                T=0.5, angles=angles, lam=1e-3, n_iter=args.iters or 50, n_power=20))
         if (i + 1) % 20 == 0:
             log(f"trace: {i + 1}/{args.jobs} jobs generated")
     clone = lambda: [serving.Job(job_id=j.job_id, arrival=j.arrival, c=j.c, G=j.G, dx=j.dx, T=j.T,
@@ -86,7 +178,7 @@ def run_serve(args):
     mixed_jobs = sched.run(clone())
     mixed = serving.summary(mixed_jobs)
     log(f"scheduler: {mixed}")
-    print(json.dumps({"mode": "serve", "jobs": args.jobs, "rate_per_s": args.rate, "iters": args.iters,
+    print(json.dumps({"mode": "serve", "jobs": args.jobs, "rate_per_s": args.rate, "iters": args.iters or 50,
                       "slots": args.slots, "concurrency": args.concurrency, "serial": base,
                       "continuous_batching": mixed, "peak_active": sched.peak_active,
                       "peak_running": sched.peak_running, "peak_bytes": sched.peak_bytes,
@@ -105,7 +197,8 @@ def run_wave_only(args):
     dx = synth.grid_spacing(n)
     c = synth.sound_speed((n, n, n), dx, np.random.default_rng(args.seed), r["bumps"], r["amp"], r["clamp"])
     plan = ff.Plan(torch.from_numpy(c).to("cuda", dtype), dx, r["T"], synth.uniform_angles(r["n_angles"]),
-                   naive_stencil=args.naive_stencil)
+                   naive_stencil=args.naive_stencil,
+                   two_step_stencil={"auto": None, "single": False, "pairs": True}[args.stencil])
     h = torch.randn((n, n, n), dtype=dtype, device="cuda")
     out = torch.empty_like(h)
     plan.wave(h, out=out)
@@ -118,10 +211,10 @@ def run_wave_only(args):
     e1.record(stream)
     e1.synchronize()
     us = 1e3 * e0.elapsed_time(e1) / (args.reps * plan.nt)
-    nbytes = 4 * (4 if dtype == torch.float32 else 8) * n ** 3
     env = {k: v for k, v in os.environ.items() if k.startswith("FFPAT_")}
-    print(json.dumps({"mode": "wave", "n": n, "nt": plan.nt, "reps": args.reps, "us_per_launch": us,
-                      "GBps": nbytes / us / 1e3, "bytes_per_launch": nbytes, "env": env}), flush=True)
+    print(json.dumps({"mode": "wave", "n": n, "dtype": args.dtype, "nt": plan.nt, "reps": args.reps,
+                      "steps_per_pass": plan.steps_per_pass, "us_per_step": us,
+                      "gpt_updates_per_s": n ** 3 / us / 1e3, "env": env}), flush=True)
 
 
 def run_copy_only(args):
@@ -179,8 +272,8 @@ def time_fb(torch, plan, G, lam, steps, warmup):
 
 
 def time_wave(torch, plan, reps=3):
-    """Average duration of one leapfrog-step launch, from HIP events around
-    back-to-back W_T applications on the stream the kernels run on."""
+    """Seconds per W_T application, from HIP events around back-to-back
+    applications on the stream the kernels are launched on."""
     x = torch.randn(plan.shape, dtype=plan.dtype, device="cuda")
     y = torch.empty_like(x)
     plan.wave(x, out=y)
@@ -192,8 +285,33 @@ def time_wave(torch, plan, reps=3):
         plan.wave(x, out=y, stream=stream)
     e1.record(stream)
     e1.synchronize()
-    ms = e0.elapsed_time(e1)
-    return ms / 1e3 / (reps * plan.nt)
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def stencil_roofline(torch, ff, plan, case, dtype):
+    """The dominant kernel of the path (the leapfrog stencil) and its average launch
+    duration, measured live.  A W_T solve is n_t leapfrog steps: with one step per
+    pass, n_t launches of wave_step_blocked (algorithmic bytes per launch: read
+    p(k), p(k-1), k', write p(k+1) = 4 words per voxel); with two steps per pass,
+    one first-step launch, P = (n_t - 1) // 2 launches of wave_step2_blocked (read
+    p(k-1), p(k), k', write p(k+1), p(k+2) = 5 words per voxel) and S = (n_t - 1) % 2
+    single-step launches.  The pair kernel's duration is then
+    (t(W_T) - (1 + S) t_single) / P, with t_single measured on a plan that runs one
+    step per pass."""
+    esz = 4 if dtype == torch.float32 else 8
+    nvox = case.n ** 3
+    t_w = time_wave(torch, plan)
+    out = {"t_wave": t_w, "steps_per_pass": plan.steps_per_pass}
+    if plan.steps_per_pass == 1:
+        out.update(kernel="wave_step_blocked", t_launch=t_w / plan.nt, bytes_per_launch=4 * esz * nvox)
+        return out
+    c = torch.from_numpy(case.c).to("cuda", dtype)
+    with ff.Plan(c, case.dx, case.T, case.angles, two_step_stencil=False) as ps:
+        t_single = time_wave(torch, ps) / ps.nt
+    pairs, singles = divmod(plan.nt - 1, 2)
+    out.update(kernel="wave_step2_blocked", t_launch=(t_w - (1 + singles) * t_single) / pairs,
+               bytes_per_launch=5 * esz * nvox, t_single_launch=t_single)
+    return out
 
 
 def cpu_baseline(case, G, step):
@@ -213,9 +331,9 @@ def cpu_baseline(case, G, step):
                       f"({t:.1f} s: 2 wave solves, X, Lambda, X^T, prox)"}
 
 
-def stored_traffic(recipe, dtype_name):
-    """HBM bytes per stencil launch from the committed counter runs, if the stencil
-    source is unchanged since they were taken (else None)."""
+def stored_traffic(kernel, recipe, dtype_name):
+    """HBM bytes per launch of `kernel` from the committed counter runs, if the
+    stencil source is unchanged since they were taken (else None)."""
     import hashlib
     import re
     src = os.path.join(ROOT, "paper_1901_06503_amd", "csrc", "kernels_wave.hip")
@@ -224,9 +342,10 @@ def stored_traffic(recipe, dtype_name):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     for line in open(note):
-        m = re.match(r"traffic: recipe=(\S+) dtype=(\S+) bytes_per_launch=([0-9.eE+]+) source_sha256=([0-9a-f]+)", line)
-        if m and m.group(1) == recipe and m.group(2) == dtype_name and m.group(4) == sha:
-            return float(m.group(3))
+        m = re.match(r"traffic: kernel=(\S+) recipe=(\S+) dtype=(\S+) bytes_per_launch=([0-9.eE+]+) "
+                     r"source_sha256=([0-9a-f]+)", line)
+        if m and m.group(1) == kernel and m.group(2) == recipe and m.group(3) == dtype_name and m.group(5) == sha:
+            return float(m.group(4))
     return None
 
 
@@ -238,6 +357,10 @@ def main():
         return run_copy_only(args)
     if args.mode == "serve":
         return run_serve(args)
+    if args.mode == "precision":
+        return run_precision(args)
+    if args.mode == "paper2d":
+        return run_paper2d(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the sharded design is described in DESIGN.md)"}))
@@ -255,12 +378,12 @@ def main():
     ms = 1e3 * t / args.steps
     log(f"FB {args.steps} iterations: {t:.3f}s ({ms:.2f} ms/iter), power iteration {t_power:.3f}s")
 
-    t_launch = time_wave(torch, plan)
-    esz = 4 if dtype == torch.float32 else 8
-    bytes_per_launch = 4 * esz * N ** 3              # read p(k), p(k-1), k'; write p(k+1)
+    roof = stencil_roofline(torch, ff, plan, case, dtype)
+    t_launch, bytes_per_launch = roof["t_launch"], roof["bytes_per_launch"]
     achieved = bytes_per_launch / t_launch / 1e9
-    gpt = N ** 3 / t_launch / 1e9
-    log(f"wave step {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s, {gpt:.1f} Gpt-updates/s")
+    gpt = N ** 3 * plan.nt / roof["t_wave"] / 1e9
+    log(f"{roof['kernel']} {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s; "
+        f"W_T {roof['t_wave'] * 1e3:.2f} ms, {gpt:.1f} Gpt-updates/s")
 
     fp64 = None
     G_keep = G.cpu() if args.cpu_baseline else None
@@ -272,7 +395,8 @@ def main():
         k64 = max(2, args.steps // 4)
         t64, _, _ = time_fb(torch, plan64, G64, case.lam, k64, 1)
         fp64 = {"fb_iter_per_s": k64 / t64, "ms_per_iter": 1e3 * t64 / k64, "steps": k64,
-                "wave_gpt_updates_per_s": N ** 3 / time_wave(torch, plan64) / 1e9}
+                "wave_gpt_updates_per_s": N ** 3 * plan64.nt / time_wave(torch, plan64) / 1e9,
+                "steps_per_pass": plan64.steps_per_pass}
         plan64.close()
         log(f"FP64: {fp64}")
 
@@ -281,7 +405,7 @@ def main():
         log("cpu baseline (oracle, one FB iteration)")
         cpu = cpu_baseline(case, G_keep, out.step)
         log(f"cpu baseline {cpu}")
-    traffic = stored_traffic(args.recipe, args.dtype)
+    traffic = stored_traffic(roof["kernel"], args.recipe, args.dtype)
 
     line = {
         "metric": METRIC,
@@ -299,13 +423,13 @@ def main():
         "config": {"workload": f"{N}^3 grid, {nang} angles, T={case.T}, Algorithm 8 with positivity + "
                                f"lambda={case.lam} l2 prox, FP32 fields + FP64 reductions",
                    "grid": N, "angles": nang, "nt": plan.nt, "power_steps": 20,
-                   "stencil": "naive" if args.naive_stencil else "blocked"},
+                   "stencil": "naive" if args.naive_stencil else roof["kernel"]},
         "wave_gpt_updates_per_s": gpt,
         "power_iteration_s": t_power,
         "fp64": fp64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "wave_step", "bytes_per_launch": bytes_per_launch,
+                     "kernel": roof["kernel"], "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": t_launch * 1e6},
         "cpu_baseline": cpu,
         "objective_last": float(out.objective[-1]) if len(out.objective) else None,

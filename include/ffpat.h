@@ -82,6 +82,11 @@ typedef struct {
 /* Plan flags */
 #define FFPAT_PLAN_NAIVE_STENCIL 1u   /* unblocked stencil kernel (for comparison) */
 #define FFPAT_PLAN_NO_GRAPHS 2u       /* launch every kernel eagerly instead of replaying captured graphs */
+#define FFPAT_PLAN_SINGLE_STEP 4u     /* one leapfrog step per stencil pass (no temporal blocking) */
+#define FFPAT_PLAN_TWO_STEP 8u        /* two leapfrog steps per stencil pass wherever the chain allows.
+                                         With neither of these two flags the plan chooses: two steps per
+                                         pass for FP64 fields and for grids above 256^3 voxels, where that
+                                         kernel is measured faster, one step otherwise.  Both: EINVAL. */
 
 /* Reconstruction flags (ffpat_fb_params.flags) */
 #define FFPAT_POSITIVITY 1u   /* R includes the indicator of h >= 0 (prox clamps at 0) */
@@ -126,6 +131,12 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
 
 /* Time grid of the plan: n_t, dt, c_max.  Any pointer may be NULL. */
 int ffpat_plan_info(const ffpat_plan *plan, int32_t *nt, double *dt, double *cmax);
+
+/* Leapfrog steps per stencil pass that the plan's wave solves use (eq. leapfrog):
+ * 2 when the temporally blocked kernel runs (see FFPAT_PLAN_TWO_STEP), else 1.
+ * A W_T solve is one first-step pass, then pairs, then a single pass when the
+ * remaining n_t - 1 steps are odd. */
+int ffpat_plan_steps_per_pass(const ffpat_plan *plan, int32_t *steps);
 
 /* Releases the plan and its device memory (synchronises the device first). */
 int ffpat_plan_destroy(ffpat_plan *plan);

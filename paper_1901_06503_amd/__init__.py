@@ -72,7 +72,7 @@ class Plan:
     """
 
     def __init__(self, c, dx, T, angles, ns=0, ds=0.0, cfl=0.3, ndim=3, naive_stencil=False, use_graphs=True,
-                 stream=None):
+                 two_step_stencil=None, stream=None):
         torch = _torch()
         if not (isinstance(c, torch.Tensor) and c.is_cuda):
             raise TypeError("c must be a device tensor")
@@ -85,7 +85,8 @@ class Plan:
         self.device = c.device
         nz, ny, nx = c.shape
         code = _lib.F64 if c.dtype == torch.float64 else _lib.F32
-        flags = (_lib.PLAN_NAIVE_STENCIL if naive_stencil else 0) | (0 if use_graphs else _lib.PLAN_NO_GRAPHS)
+        flags = ((_lib.PLAN_NAIVE_STENCIL if naive_stencil else 0) | (0 if use_graphs else _lib.PLAN_NO_GRAPHS)
+                 | {None: 0, True: _lib.PLAN_TWO_STEP, False: _lib.PLAN_SINGLE_STEP}[two_step_stencil])
         self._lib = _lib.load()
         g, self._angles = _make_geom(nx, ny, nz, dx, T, angles, ns, ds, cfl, ndim, code, flags)
         handle = ctypes.c_void_p()
@@ -102,6 +103,9 @@ class Plan:
         nt = ctypes.c_int32(); dt = ctypes.c_double(); cm = ctypes.c_double()
         _lib.check(self._lib.ffpat_plan_info(self._h, ctypes.byref(nt), ctypes.byref(dt), ctypes.byref(cm)))
         self.nt, self.dt, self.cmax = nt.value, dt.value, cm.value
+        sp = ctypes.c_int32()
+        _lib.check(self._lib.ffpat_plan_steps_per_pass(self._h, ctypes.byref(sp)))
+        self.steps_per_pass = sp.value          # 2: temporally blocked stencil kernel
 
     # ------------------------------------------------------------------ helpers
     def _check_tensor(self, t, shape, name):

@@ -19,6 +19,8 @@ F32, F64 = 0, 1
 
 PLAN_NAIVE_STENCIL = 1
 PLAN_NO_GRAPHS = 2
+PLAN_SINGLE_STEP = 4
+PLAN_TWO_STEP = 8
 POSITIVITY = 1
 PRECOND = 2
 REG_GRAD = 4
@@ -56,6 +58,7 @@ SIGNATURES = {
     "ffpat_plan_create": ([ctypes.POINTER(Geom), _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "ffpat_plan_info": ([_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                          ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "ffpat_plan_steps_per_pass": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "ffpat_plan_destroy": ([_P], ctypes.c_int),
     "ffpat_forward": ([_P, _P, _P, _P], ctypes.c_int),
     "ffpat_adjoint": ([_P, _P, _P, _P], ctypes.c_int),

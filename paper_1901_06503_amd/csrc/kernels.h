@@ -58,6 +58,15 @@ template <typename T>
 hipError_t launch_wave_step(StencilKind kind, StepMode mode, const Dims &d, const T *p, const T *prev,
                             T *out, const T *kap, hipStream_t s);
 
+// Two leapfrog steps in one pass: q = p(k+1), o = p(k+2) from pm1 = p(k-1), pk = p(k).
+// All four buffers must be distinct.
+template <typename T>
+hipError_t launch_wave_pair(const Dims &d, const T *pm1, const T *pk, T *q, T *o, const T *kap, hipStream_t s);
+// Whether the plan layer should use launch_wave_pair (FFPAT_STENCIL_TB=0 disables it).
+// Whether the two-step kernel is the faster choice for this grid and element size
+// (FFPAT_STENCIL_TB=0/1 in the environment overrides the rule).
+bool wave_pairs_preferred(const Dims &d, size_t esz);
+
 // k' = (c dt)^2 / (12 dx^2) from c, and c range / finiteness into stats[0..2]
 // (min, max, count of non-finite or non-positive values) via block partials.
 template <typename T>

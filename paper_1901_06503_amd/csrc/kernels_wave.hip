@@ -208,6 +208,220 @@ wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__res
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two leapfrog steps per pass (temporal blocking):
+//   q = p(k+1) = 2 p(k) - p(k-1) + k' S(p(k))   on the tile plus a 2-point halo
+//   o = p(k+2) = 2 q    - p(k)   + k' S(q)      on the tile
+// One pass reads p(k-1), p(k), k' and writes p(k+1), p(k+2): 20 B per two point
+// updates in FP32 instead of 32 B, the halo re-reads served by L2.
+// A work-group owns a 64 x BY tile and a z-chunk.  It marches the stage-1 plane
+// zs from zbeg - 2 to zend + 1; stage 2 follows two planes behind (z = zs - 2).
+// Every thread owns up to PPT points of the extended tile (64 + 4) x (BY + 4)
+// and keeps, per point, p(k) at zs-2..zs+2, q at zs-4..zs and k' at zs-2..zs in
+// registers (loads of the next plane are issued one plane ahead).  LDS holds
+// p(k) of plane zs with a 4-point halo (stage-1 x-y neighbours) and a ring of
+// three q planes with a 2-point halo (stage-2 x-y neighbours).  q is zero
+// outside the grid (the zero values outside).
+// Inputs and outputs are four distinct buffers (neighbouring groups read the
+// inputs in their halos while this group writes).
+// ---------------------------------------------------------------------------
+template <typename T, int NDIM, int RY, int NTH>
+__global__ void __launch_bounds__(NTH)
+wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__restrict__ q_out,
+                   T *__restrict__ o_out, const T *__restrict__ kap, int nx, int ny, int nz, int zchunk, int tiles_x,
+                   int tiles_y, int n_tiles, int xy_fastest)
+{
+  constexpr int BX = 64, BY = 4 * RY;
+  constexpr int EX = BX + 4, EY = BY + 4;   // extended tile: stage-1 output region
+  constexpr int KX = BX + 8, KY = BY + 8;   // p(k) plane in LDS: stage-1 input region
+  constexpr int NE = EX * EY;
+  constexpr int PPT = (NE + NTH - 1) / NTH;
+  constexpr int NRING = KX * KY - NE;        // outer 2-point ring of the p(k) plane
+  __shared__ T lk[KY * KX];
+  __shared__ T lq[3][EY * EX];
+
+  const int b = blockIdx.x;
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int t = (b % 8) * per_xcd + b / 8;
+  if (t >= n_tiles) return;                 // whole group exits together
+  const int n_zc = (nz + zchunk - 1) / zchunk;
+  int zc, txy;
+  if (xy_fastest) {
+    const int n_xy = tiles_x * tiles_y;
+    txy = t % n_xy;
+    zc = t / n_xy;
+  } else {
+    zc = t % n_zc;
+    txy = t / n_zc;
+  }
+  const int x0 = (txy % tiles_x) * BX, y0 = (txy / tiles_x) * BY;
+  const int zbeg = zc * zchunk;
+  const int zend = min(nz, zbeg + zchunk);
+  const size_t plane = (size_t)nx * ny;
+
+  // Per point: its place in the extended tile, flags, and its offset within a
+  // plane, clamped into the grid so that every load below is in bounds (a point
+  // outside reads a neighbour's value and its flag zeroes it).  The plane base
+  // is uniform, so each load is one scalar base plus one 32-bit offset.
+  int ex[PPT], ey[PPT];
+  unsigned off[PPT];
+  bool ev[PPT], ing[PPT], inter[PPT];
+  T w[PPT][5], r1[PPT][5], kr[PPT][3];
+#pragma unroll
+  for (int m = 0; m < PPT; ++m) {
+    const int e = threadIdx.x + NTH * m;
+    ev[m] = e < NE;
+    ey[m] = ev[m] ? e / EX : 0;
+    ex[m] = ev[m] ? e - ey[m] * EX : 0;
+    const int gx = x0 - 2 + ex[m], gy = y0 - 2 + ey[m];
+    ing[m] = ev[m] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    inter[m] = ing[m] && ex[m] >= 2 && ex[m] < EX - 2 && ey[m] >= 2 && ey[m] < EY - 2;
+    off[m] = (unsigned)(min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int zq = zbeg - 4 + q;
+      w[m][q] = T(0);
+      if ((NDIM == 3 || q == 2) && zq >= 0 && zq < nz) {
+        const T v = pk[(size_t)zq * plane + off[m]];
+        w[m][q] = ing[m] ? v : T(0);
+      }
+    }
+    w[m][4] = T(0);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r1[m][q] = T(0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) kr[m][q] = T(1);
+  }
+
+  // ring elements of the p(k) plane owned by this thread (fixed positions)
+  constexpr int RPT = (NRING + NTH - 1) / NTH;
+  int rl[RPT];
+  unsigned roff[RPT];
+  bool rin[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int e = threadIdx.x + NTH * j;
+    const bool rv = e < NRING;
+    int lr = 0, lc = 0;
+    if (rv) {
+      // rows 0, 1, KY-2, KY-1 (full width), then columns 0, 1, KX-2, KX-1 of rows 2..KY-3
+      if (e < 4 * KX) {
+        const int hr = e / KX;
+        lr = hr < 2 ? hr : KY - 4 + hr;
+        lc = e - hr * KX;
+      } else {
+        const int e2 = e - 4 * KX;
+        const int hc = e2 / (KY - 4);
+        lc = hc < 2 ? hc : KX - 4 + hc;
+        lr = 2 + (e2 - hc * (KY - 4));
+      }
+    }
+    rl[j] = rv ? lr * KX + lc : -1;
+    const int gx = x0 - 4 + lc, gy = y0 - 4 + lr;
+    rin[j] = rv && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    roff[j] = (unsigned)(min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1));
+  }
+  // software pipeline: the loads of plane zs + 1 are issued during plane zs
+  T nw[PPT], npv[PPT], nkv[PPT], nring[RPT];
+  // The loads are unconditional (plane index clamped too) and their values are
+  // masked only where they are used, one plane later, so that they stay in
+  // flight across the barrier and the arithmetic of the current plane.
+  auto fetch = [&](int zf) {
+    const int zw = min(max(NDIM == 3 ? zf + 2 : zf, 0), nz - 1);
+    const int zc = min(max(zf, 0), nz - 1);
+    const T *bw = pk + (size_t)zw * plane, *bp = pm1 + (size_t)zc * plane, *bk = kap + (size_t)zc * plane;
+    const T *br = pk + (size_t)zc * plane;
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+      nw[m] = bw[off[m]];
+      npv[m] = bp[off[m]];
+      nkv[m] = bk[off[m]];
+    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) nring[j] = br[roff[j]];
+  };
+  fetch(zbeg - 2);
+
+  for (int zs = zbeg - 2; zs < zend + 2; ++zs) {
+    const int z = zs - 2;
+    const bool zs_in = zs >= 0 && zs < nz;
+    // stage-1 inputs of plane zs (fetched one plane ahead); p(k) and q are zero outside the grid
+    const int zw = NDIM == 3 ? zs + 2 : zs;
+    const bool zw_in = zw >= 0 && zw < nz;
+    T pv[PPT], kv[PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+      const T v = (ing[m] && zw_in) ? nw[m] : T(0);
+      if (NDIM == 3) w[m][4] = v;
+      else w[m][2] = v;
+      pv[m] = npv[m];   // used only where the point and plane zs are inside the grid
+      kv[m] = nkv[m];
+      if (ev[m]) lk[(ey[m] + 2) * KX + ex[m] + 2] = w[m][2];
+    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+      if (rl[j] >= 0) lk[rl[j]] = (rin[j] && zs_in) ? nring[j] : T(0);
+    fetch(zs + 1);   // clamped: past the last plane it re-reads valid memory, unused
+    __syncthreads();
+    // stage 1: q(zs) on the extended tile
+    T *Lq = lq[(zs + 3) % 3];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+      if (!ev[m]) continue;
+      const T *c = &lk[(ey[m] + 2) * KX + ex[m] + 2];
+      T s1 = (c[-1] + c[1]) + (c[-KX] + c[KX]);
+      T s2 = (c[-2] + c[2]) + (c[-2 * KX] + c[2 * KX]);
+      if (NDIM == 3) {
+        s1 += w[m][1] + w[m][3];
+        s2 += w[m][0] + w[m][4];
+      }
+      const T c0 = w[m][2];
+      const T S = T(16) * s1 - s2 - T(NDIM == 3 ? 90 : 60) * c0;
+      const T q = (ing[m] && zs_in) ? T(2) * c0 - pv[m] + kv[m] * S : T(0);
+      Lq[ey[m] * EX + ex[m]] = q;
+      r1[m][4] = q;
+      kr[m][2] = kv[m];
+      if (inter[m] && zs >= zbeg && zs < zend) q_out[(size_t)zs * plane + off[m]] = q;
+    }
+    __syncthreads();
+    // stage 2: o(z) on the tile, z = zs - 2
+    if (z >= zbeg) {
+      const T *Q = lq[(z + 3) % 3];
+#pragma unroll
+      for (int m = 0; m < PPT; ++m) {
+        if (!inter[m]) continue;
+        const T *c = &Q[ey[m] * EX + ex[m]];
+        T s1 = (c[-1] + c[1]) + (c[-EX] + c[EX]);
+        T s2 = (c[-2] + c[2]) + (c[-2 * EX] + c[2 * EX]);
+        if (NDIM == 3) {
+          s1 += r1[m][1] + r1[m][3];
+          s2 += r1[m][0] + r1[m][4];
+        }
+        const T c0 = r1[m][2];
+        const T S = T(16) * s1 - s2 - T(NDIM == 3 ? 90 : 60) * c0;
+        // p(k) at z: w[m][0] in 3D (the ring is at zs-2..zs+2); in 2D the ring holds only zs
+        const T pkz = NDIM == 3 ? w[m][0] : pk[(size_t)z * plane + off[m]];
+        o_out[(size_t)z * plane + off[m]] = T(2) * c0 - pkz + kr[m][0] * S;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+      if (NDIM == 3) {
+        w[m][0] = w[m][1];
+        w[m][1] = w[m][2];
+        w[m][2] = w[m][3];
+        w[m][3] = w[m][4];
+      }
+      r1[m][0] = r1[m][1];
+      r1[m][1] = r1[m][2];
+      r1[m][2] = r1[m][3];
+      r1[m][3] = r1[m][4];
+      kr[m][0] = kr[m][1];
+      kr[m][1] = kr[m][2];
+    }
+  }
+}
+
 // Tunables of the blocked kernel (set once per process from the environment
 // for sweeps; the defaults are the measured best on MI355X).
 struct BlockedConfig {
@@ -216,6 +430,9 @@ struct BlockedConfig {
   int order = 1;     // 1: x-y tiles fastest within an XCD's range; 0: z-chunks fastest
   int groups = 2048; // target work-group count when zchunk = 0
   int nt = 0;        // non-temporal loads of p(k-1), k' and stores of p(k+1)
+  int ry2 = 0;       // two-step kernel: tile height / 4 (0: default 4)
+  int zchunk2 = 0;   // two-step kernel: planes per work-group (0: from the grid size)
+  int threads2 = 512; // two-step kernel: work-group size (256, 512 or 1024)
 };
 
 static BlockedConfig blocked_config(const Dims &d, size_t esz)
@@ -231,6 +448,12 @@ static BlockedConfig blocked_config(const Dims &d, size_t esz)
     if (const char *e = getenv("FFPAT_STENCIL_ORDER")) c.order = atoi(e) ? 1 : 0;
     if (const char *e = getenv("FFPAT_STENCIL_GROUPS")) c.groups = atoi(e) > 0 ? atoi(e) : 2048;
     if (const char *e = getenv("FFPAT_STENCIL_NT")) c.nt = atoi(e) ? 1 : 0;
+    if (const char *e = getenv("FFPAT_STENCIL2_RY")) c.ry2 = atoi(e);
+    if (const char *e = getenv("FFPAT_STENCIL2_ZCHUNK")) c.zchunk2 = atoi(e);
+    if (const char *e = getenv("FFPAT_STENCIL2_THREADS")) {
+      const int v = atoi(e);
+      c.threads2 = v == 1024 ? 1024 : (v == 256 ? 256 : 512);
+    }
     if (c.ry != 0 && c.ry != 1 && c.ry != 2 && c.ry != 4 && c.ry != 8) c.ry = 0;
     if (c.zchunk < 0) c.zchunk = 0;
     return c;
@@ -288,6 +511,66 @@ static hipError_t blocked_select(StepMode mode, const Dims &d, const T *p, const
     case 8: return blocked_dispatch<T, NDIM, 8>(mode, d, p, prev, out, kap, cfg, s);
     default: return blocked_dispatch<T, NDIM, 2>(mode, d, p, prev, out, kap, cfg, s);
   }
+}
+
+template <typename T, int NDIM, int RY, int NTH>
+static hipError_t pair_dispatch(const Dims &d, const T *pm1, const T *pk, T *q_out, T *o_out, const T *kap,
+                                const BlockedConfig &cfg, hipStream_t s)
+{
+  constexpr int BY = 4 * RY;
+  const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + BY - 1) / BY;
+  int zchunk = cfg.zchunk2;
+  if (zchunk <= 0) {
+    const long xy = (long)tiles_x * tiles_y;
+    // FP32: about 512 work-groups (two fit on a compute unit), 8 to 32 planes each;
+    // FP64: about 256 (one fits), 8 to 64 planes each
+    const bool f64 = sizeof(T) == 8;
+    const long zc = (long)d.nz * xy / (f64 ? 256 : 512);
+    const long zmax = f64 ? 64 : 32;
+    zchunk = (int)(zc < 8 ? 8 : (zc > zmax ? zmax : zc));
+  }
+  if (zchunk > d.nz) zchunk = d.nz;
+  const int n_zc = (d.nz + zchunk - 1) / zchunk;
+  const int n_tiles = tiles_x * tiles_y * n_zc;
+  const int grid = ((n_tiles + 7) / 8) * 8;
+  wave_step2_blocked<T, NDIM, RY, NTH><<<grid, NTH, 0, s>>>(pm1, pk, q_out, o_out, kap, d.nx, d.ny, d.nz, zchunk,
+                                                             tiles_x, tiles_y, n_tiles, cfg.order);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_wave_pair(const Dims &d, const T *pm1, const T *pk, T *q_out, T *o_out, const T *kap,
+                            hipStream_t s)
+{
+  BlockedConfig cfg = blocked_config(d, sizeof(T));
+  const int ry = cfg.ry2 > 0 ? cfg.ry2 : 4;
+  if (d.ndim == 2) {
+    if (ry == 4) return pair_dispatch<T, 2, 4, 256>(d, pm1, pk, q_out, o_out, kap, cfg, s);
+    return pair_dispatch<T, 2, 2, 256>(d, pm1, pk, q_out, o_out, kap, cfg, s);
+  }
+  if (cfg.threads2 == 1024) {
+    if (ry == 8) return pair_dispatch<T, 3, 8, 1024>(d, pm1, pk, q_out, o_out, kap, cfg, s);
+    return pair_dispatch<T, 3, 4, 1024>(d, pm1, pk, q_out, o_out, kap, cfg, s);
+  }
+  if (cfg.threads2 == 512) {
+    if (ry == 8) return pair_dispatch<T, 3, 8, 512>(d, pm1, pk, q_out, o_out, kap, cfg, s);
+    if (ry == 4) return pair_dispatch<T, 3, 4, 512>(d, pm1, pk, q_out, o_out, kap, cfg, s);
+    return pair_dispatch<T, 3, 2, 512>(d, pm1, pk, q_out, o_out, kap, cfg, s);
+  }
+  if (ry == 4) return pair_dispatch<T, 3, 4, 256>(d, pm1, pk, q_out, o_out, kap, cfg, s);
+  return pair_dispatch<T, 3, 2, 256>(d, pm1, pk, q_out, o_out, kap, cfg, s);
+}
+
+bool wave_pairs_preferred(const Dims &d, size_t esz)
+{
+  static const int env = [] {
+    const char *e = getenv("FFPAT_STENCIL_TB");
+    return e ? (atoi(e) != 0 ? 1 : 0) : -1;
+  }();
+  if (env >= 0) return env == 1;
+  // measured on MI355X: FP64 at 128^3..384^3 runs 11-22% faster per step with two
+  // steps per pass; FP32 ties up to 256^3 and gains from 384^3 on
+  return esz == 8 || d.nvox() > (size_t)256 * 256 * 256;
 }
 
 template <typename T>
@@ -393,6 +676,7 @@ hipError_t launch_c_stats(const Dims &d, const T *c, double *partials, int nbloc
 }
 
 #define FFPAT_INST(T)                                                                                        \
+  template hipError_t launch_wave_pair<T>(const Dims &, const T *, const T *, T *, T *, const T *, hipStream_t); \
   template hipError_t launch_wave_step<T>(StencilKind, StepMode, const Dims &, const T *, const T *, T *,  \
                                           const T *, hipStream_t);                                          \
   template hipError_t launch_make_kappa<T>(const Dims &, const T *, double, double, T *, hipStream_t);     \

@@ -95,7 +95,7 @@ struct GraphCache {
 };
 
 struct Layout {
-  size_t kap, vol[4], dat, taps, ap, partials, scalars;
+  size_t kap, vol[6], dat, taps, ap, partials, scalars;
   size_t padN, padT, padD;              // zero-padded copies for the projector / backprojector
   size_t padN_bytes, padT_bytes, padD_bytes;
   size_t total;
@@ -126,6 +126,7 @@ struct ffpat_plan {
   bool need_n = false;    // some angle marches rows (reads the padded plane)
   bool need_t = false;    // some angle marches columns (reads the padded transpose)
   bool use_graphs = true; // replay captured graphs for the power iteration and FB iterations
+  bool use_pairs = true;  // two leapfrog steps per pass where possible
   hipStream_t cap_stream = nullptr;
   GraphCache g_iter, g_power;
 
@@ -187,6 +188,8 @@ int resolve(const ffpat_geom *g, Resolved *r)
   r->ds = ds;
   r->T = g->T;
   r->cfl = cfl;
+  if ((g->flags & FFPAT_PLAN_SINGLE_STEP) && (g->flags & FFPAT_PLAN_TWO_STEP))
+    return fail(FFPAT_EINVAL, "FFPAT_PLAN_SINGLE_STEP and FFPAT_PLAN_TWO_STEP exclude each other");
   r->flags = g->flags;
   return FFPAT_OK;
 }
@@ -200,7 +203,7 @@ Layout layout(const Resolved &r)
   const size_t rows = (size_t)r.n_angles * r.d.nz;
   size_t off = 0;
   L.kap = off; off = align_up(off + nvox * esz);
-  for (int i = 0; i < 4; ++i) { L.vol[i] = off; off = align_up(off + nvox * esz); }
+  for (int i = 0; i < 6; ++i) { L.vol[i] = off; off = align_up(off + nvox * esz); }
   L.dat = off; off = align_up(off + ndat * esz);
   L.taps = off; off = align_up(off + (size_t)r.ns * esz);
   L.ap = off; off = align_up(off + (size_t)r.n_angles * sizeof(AngleParams));
@@ -269,53 +272,89 @@ std::vector<T> ramp_taps(const Resolved &r)
 }
 
 // ------------------------------------------------------------------ operators
+// Scratch volumes handed to a wave solve (buffers not holding live data).
 template <typename T>
-int wave_forward(ffpat_plan *P, const T *in, T *out, T *ws, hipStream_t s)
+struct Pool {
+  T *b[6];
+  int n = 0;
+  Pool(std::initializer_list<void *> v)
+  {
+    for (void *x : v) b[n++] = static_cast<T *>(x);
+  }
+  T *take() { return n > 0 ? b[--n] : nullptr; }
+  void give(T *x) { b[n++] = x; }
+};
+
+// Leapfrog levels after the first step: pm1 = p(k-1), pk = p(k) (pk always a
+// scratch buffer; pm1 may be read-only input), `steps` LEAP updates, the last
+// one written to `out` (dividing by k' when div_last).  Pairs of steps run in
+// the two-step kernel when the plan allows and enough scratch is free.
+template <typename T>
+int leapfrog_chain(ffpat_plan *P, const T *pm1, bool pm1_owned, T *pk, int steps, T *out, bool div_last,
+                   Pool<T> pool, hipStream_t s)
 {
   const T *kap = static_cast<const T *>(P->kap());
-  const int nt = P->nt;
-  T *X1 = (nt % 2 == 1) ? out : ws;
-  T *X2 = (nt % 2 == 1) ? ws : out;
-  HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, in, nullptr, X1, kap, s));
-  const T *pm1 = in;
-  T *pk = X1;
-  for (int k = 1; k < nt; ++k) {
-    T *dst = (k == 1) ? X2 : const_cast<T *>(pm1);
-    HIP_TRY(launch_wave_step<T>(P->stencil, STEP_LEAP, P->d, pk, pm1, dst, kap, s));
-    pm1 = pk;
-    pk = dst;
+  while (steps > 0) {
+    const bool pair = P->use_pairs && steps >= 2 && !(div_last && steps == 2) && pool.n >= (steps == 2 ? 1 : 2);
+    if (pair) {
+      T *a = pool.take();
+      T *b = (steps == 2) ? out : pool.take();
+      HIP_TRY(launch_wave_pair<T>(P->d, pm1, pk, a, b, kap, s));
+      if (pm1_owned) pool.give(const_cast<T *>(pm1));
+      pool.give(pk);
+      pm1 = a;
+      pm1_owned = true;
+      pk = b;
+      steps -= 2;
+    } else {
+      T *dst = (steps == 1) ? out : (pm1_owned ? const_cast<T *>(pm1) : pool.take());
+      if (!dst) return fail(FFPAT_EINVAL, "internal: no scratch volume for the leapfrog");
+      const StepMode mode = (steps == 1 && div_last) ? STEP_LEAP_DIV : STEP_LEAP;
+      HIP_TRY(launch_wave_step<T>(P->stencil, mode, P->d, pk, pm1, dst, kap, s));
+      if (pm1_owned && dst != pm1) pool.give(const_cast<T *>(pm1));
+      pm1 = pk;
+      pm1_owned = true;
+      pk = dst;
+      steps -= 1;
+    }
   }
   return FFPAT_OK;
 }
 
-// out = K^-1 W_T K g given b = k' g already in `b` (overwritten), ws scratch.
+// out = W_T in (in read-only; pool: scratch volumes distinct from in and out)
 template <typename T>
-int wave_adjoint_from_scaled(ffpat_plan *P, T *b, T *out, T *ws, hipStream_t s)
+int wave_forward(ffpat_plan *P, const T *in, T *out, Pool<T> pool, hipStream_t s)
 {
   const T *kap = static_cast<const T *>(P->kap());
-  const int nt = P->nt;
-  if (nt == 1) {
+  if (P->nt == 1) {
+    HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, in, nullptr, out, kap, s));
+    return FFPAT_OK;
+  }
+  T *p1 = pool.take();
+  HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, in, nullptr, p1, kap, s));
+  return leapfrog_chain<T>(P, in, false, p1, P->nt - 1, out, false, pool, s);
+}
+
+// out = K^-1 W_T K g given b = k' g already in `b` (overwritten).
+template <typename T>
+int wave_adjoint_from_scaled(ffpat_plan *P, T *b, T *out, Pool<T> pool, hipStream_t s)
+{
+  const T *kap = static_cast<const T *>(P->kap());
+  if (P->nt == 1) {
     HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST_DIV, P->d, b, nullptr, out, kap, s));
     return FFPAT_OK;
   }
-  HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, b, nullptr, ws, kap, s));
-  T *pm1 = b, *pk = ws;
-  for (int k = 1; k < nt; ++k) {
-    const bool last = (k == nt - 1);
-    T *dst = last ? out : pm1;
-    HIP_TRY(launch_wave_step<T>(P->stencil, last ? STEP_LEAP_DIV : STEP_LEAP, P->d, pk, pm1, dst, kap, s));
-    pm1 = pk;
-    pk = dst;
-  }
-  return FFPAT_OK;
+  T *p1 = pool.take();
+  HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, b, nullptr, p1, kap, s));
+  return leapfrog_chain<T>(P, b, true, p1, P->nt - 1, out, true, pool, s);
 }
 
 template <typename T>
 int wave_adjoint_op(ffpat_plan *P, const T *g, T *q, hipStream_t s)
 {
-  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1));
+  T *V1 = static_cast<T *>(P->vol(0));
   HIP_TRY(launch_mul<T>(g, static_cast<const T *>(P->kap()), V1, P->nvox, s));
-  return wave_adjoint_from_scaled<T>(P, V1, q, V2, s);
+  return wave_adjoint_from_scaled<T>(P, V1, q, Pool<T>{P->vol(1), P->vol(2), P->vol(4)}, s);
 }
 
 template <typename T>
@@ -337,8 +376,8 @@ hipError_t backproject_op(ffpat_plan *P, const T *g, T *vol, hipStream_t s)
 template <typename T>
 int op_forward(ffpat_plan *P, const T *h, T *g, hipStream_t s)
 {
-  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1));
-  int rc = wave_forward<T>(P, h, V2, V1, s);
+  T *V2 = static_cast<T *>(P->vol(1));
+  int rc = wave_forward<T>(P, h, V2, Pool<T>{P->vol(0), P->vol(2), P->vol(4), P->vol(5)}, s);
   if (rc) return rc;
   HIP_TRY(project<T>(P, V2, g, s));
   return FFPAT_OK;
@@ -348,10 +387,10 @@ int op_forward(ffpat_plan *P, const T *h, T *g, hipStream_t s)
 template <typename T>
 int op_adjoint_padded(ffpat_plan *P, T *h, hipStream_t s)
 {
-  T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1));
+  T *V1 = static_cast<T *>(P->vol(0));
   HIP_TRY(launch_backproject<T>(P->d, P->n_angles, P->ns, P->ap(), P->two_tap, static_cast<const T *>(P->padD()),
                                 V1, static_cast<const T *>(P->kap()), s));
-  return wave_adjoint_from_scaled<T>(P, V1, h, V2, s);
+  return wave_adjoint_from_scaled<T>(P, V1, h, Pool<T>{P->vol(1), P->vol(4), P->vol(5)}, s);
 }
 
 template <typename T>
@@ -397,10 +436,10 @@ int normal_operator(ffpat_plan *P, const T *v, bool two_step, bool precond, cons
 {
   T *V1 = static_cast<T *>(P->vol(0)), *V2 = static_cast<T *>(P->vol(1)), *V3 = static_cast<T *>(P->vol(2));
   if (two_step) {
-    int rc = wave_forward<T>(P, v, V2, V1, s);
+    int rc = wave_forward<T>(P, v, V2, Pool<T>{P->vol(0), P->vol(2), P->vol(4), P->vol(5)}, s);
     if (rc) return rc;
     HIP_TRY(launch_mul<T>(V2, static_cast<const T *>(P->kap()), V1, P->nvox, s));
-    return wave_adjoint_from_scaled<T>(P, V1, V3, V2, s);
+    return wave_adjoint_from_scaled<T>(P, V1, V3, Pool<T>{P->vol(1), P->vol(4), P->vol(5)}, s);
   }
   int rc = data_residual<T>(P, v, nullptr, mask, precond, nullptr, s);
   if (rc) return rc;
@@ -477,14 +516,14 @@ int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, hi
   int rc;
   if (two_step) {
     // r = W h - g, data term ||r||^2, gradient W^T r
-    rc = wave_forward<T>(P, h, V2, V1, s);
+    rc = wave_forward<T>(P, h, V2, Pool<T>{P->vol(0), P->vol(2), P->vol(4), P->vol(5)}, s);
     if (rc) return rc;
     HIP_TRY(launch_vol_residual<T>(V2, G, P->nvox, P->partials(), s));
     HIP_TRY(launch_reduce_to(P->partials(), kReduceBlocks, 1.0, sc + SC_DATA, s));
     HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->obj, sc + SC_ITER, P->obj_cap,
                              sc + SC_NONFINITE, s));
     HIP_TRY(launch_mul<T>(V2, static_cast<const T *>(P->kap()), V1, P->nvox, s));
-    rc = wave_adjoint_from_scaled<T>(P, V1, V3, V2, s);
+    rc = wave_adjoint_from_scaled<T>(P, V1, V3, Pool<T>{P->vol(1), P->vol(4), P->vol(5)}, s);
     if (rc) return rc;
   } else {
     // r = chi (A h - G), y = chi Lambda r, data term, gradient A^T y
@@ -682,6 +721,9 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
   P->flags = r.flags;
   P->stencil = (r.flags & FFPAT_PLAN_NAIVE_STENCIL) ? STENCIL_NAIVE : STENCIL_BLOCKED;
   P->use_graphs = !(r.flags & FFPAT_PLAN_NO_GRAPHS);
+  P->use_pairs = P->stencil == STENCIL_BLOCKED &&
+                 ((r.flags & FFPAT_PLAN_TWO_STEP) ||
+                  (!(r.flags & FFPAT_PLAN_SINGLE_STEP) && wave_pairs_preferred(r.d, r.dtype == FFPAT_F64 ? 8 : 4)));
   P->nvox = r.d.nvox();
   P->ndat = (size_t)r.n_angles * r.d.nz * r.ns;
   P->rows = r.n_angles * r.d.nz;
@@ -760,6 +802,14 @@ int ffpat_plan_info(const ffpat_plan *plan, int32_t *nt, double *dt, double *cma
   return FFPAT_OK;
 }
 
+int ffpat_plan_steps_per_pass(const ffpat_plan *plan, int32_t *steps)
+{
+  CHECK_PLAN(plan);
+  if (!steps) return fail(FFPAT_EINVAL, "steps is NULL");
+  *steps = plan->use_pairs ? 2 : 1;
+  return FFPAT_OK;
+}
+
 int ffpat_plan_destroy(ffpat_plan *plan)
 {
   if (!plan) return FFPAT_OK;
@@ -807,8 +857,11 @@ int ffpat_wave(ffpat_plan *plan, const void *h_dev, void *p_dev, void *stream)
   if (h_dev == p_dev) return fail(FFPAT_EINVAL, "h_dev and p_dev must not overlap");
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return DISPATCH(plan, wave_forward<float>(plan, (const float *)h_dev, (float *)p_dev, (float *)plan->vol(0), s),
-                  wave_forward<double>(plan, (const double *)h_dev, (double *)p_dev, (double *)plan->vol(0), s));
+  return DISPATCH(plan,
+                  wave_forward<float>(plan, (const float *)h_dev, (float *)p_dev,
+                                      Pool<float>{plan->vol(0), plan->vol(1), plan->vol(2), plan->vol(4)}, s),
+                  wave_forward<double>(plan, (const double *)h_dev, (double *)p_dev,
+                                       Pool<double>{plan->vol(0), plan->vol(1), plan->vol(2), plan->vol(4)}, s));
 }
 
 int ffpat_wave_adjoint(ffpat_plan *plan, const void *g_dev, void *q_dev, void *stream)

@@ -80,8 +80,9 @@ class Scheduler:
         self.hbm_budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.iters_per_turn = max(1, int(iters_per_turn))
-        # how many admitted jobs advance at a time: 0 = all (round robin); k > 0 = the k
-        # jobs with the least remaining work (the others stay resident and wait)
+        # how many admitted jobs advance at a time: 0 = all (round robin); k > 0 = the
+        # oldest job plus the k - 1 with the least remaining work (the others stay
+        # resident and wait)
         self.concurrency = int(concurrency)
         self.device = device
         self.peak_bytes = 0
@@ -169,9 +170,14 @@ class Scheduler:
                     a.plan.close()
                     used -= a.bytes
                     active.remove(a)
-            # advance: all idle jobs, or the `concurrency` jobs with the least remaining work
-            order = sorted(active, key=_remaining_work) if self.concurrency > 0 else active
-            chosen = order[:self.concurrency] if self.concurrency > 0 else order
+            # advance: all idle jobs, or `concurrency` jobs: the oldest one (no job waits
+            # for ever) plus those with the least remaining work (short jobs overtake)
+            if self.concurrency > 0 and active:
+                oldest = min(active, key=lambda a: a.job.arrival)
+                rest = sorted((a for a in active if a is not oldest), key=_remaining_work)
+                chosen = [oldest] + rest[:self.concurrency - 1]
+            else:
+                chosen = active
             for a in chosen:
                 if not a.busy:
                     try:

@@ -50,8 +50,9 @@ def _coords(shape, dx):
     return z, y, x
 
 
-def gaussian_smooth(vol: np.ndarray, sigma_vox: float = 1.0) -> np.ndarray:
-    """Separable Gaussian blur (sigma in voxels, truncated at 4 sigma, zero padded, unit-sum kernel)."""
+def gaussian_smooth(vol: np.ndarray, sigma_vox: float = 1.0, axes=(0, 1, 2)) -> np.ndarray:
+    """Separable Gaussian blur over `axes` (sigma in voxels, truncated at 4 sigma, zero padded,
+    unit-sum kernel)."""
     if sigma_vox <= 0:
         return vol.copy()
     r = int(math.ceil(4 * sigma_vox))
@@ -59,7 +60,7 @@ def gaussian_smooth(vol: np.ndarray, sigma_vox: float = 1.0) -> np.ndarray:
     k = np.exp(-0.5 * (t / sigma_vox) ** 2)
     k /= k.sum()
     out = vol.astype(np.float64, copy=True)
-    for ax in range(3):
+    for ax in axes:
         pad = [(0, 0)] * 3
         pad[ax] = (r, r)
         padded = np.pad(out, pad)
@@ -171,15 +172,18 @@ RECIPES = {
 }
 
 
-def make_case(recipe: str, seed: int, n: int | None = None, n_angles: int | None = None) -> Case:
-    """Builds a seeded case from a recipe; n/n_angles override the grid and angle count."""
+def make_case(recipe: str, seed: int, n: int | None = None, n_angles: int | None = None,
+              dx: float | None = None) -> Case:
+    """Builds a seeded case from a recipe; n / n_angles override the grid and angle
+    count, dx the spacing (with n < the recipe's grid and the recipe's dx this is
+    the central n^3 window of the recipe's domain: a standalone sub-problem)."""
     r = dict(RECIPES[recipe])
     if n is not None:
         r["n"] = n
     if n_angles is not None:
         r["n_angles"] = n_angles
     N = r["n"]
-    dx = grid_spacing(N)
+    dx = grid_spacing(N) if dx is None else dx
     rng = np.random.default_rng(seed)
     shape = (N, N, N)
     h = balls(shape, dx, rng, r["balls"])
@@ -240,3 +244,33 @@ def torch_case(n, n_angles, seed, device="cuda", dtype=None, n_balls=20, n_bumps
         c += amp * float(a) * torch.exp(-((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2) / (2 * 0.16))
     c = torch.clamp(c, clamp[0], clamp[1])
     return dx, uniform_angles(n_angles), c.to(dtype), h.to(dtype)
+
+
+def paper2d_case(seed, n=601, half_width=3.0, n_angles=1000, n_disks=12, c_bumps=4, c_amp=0.3):
+    """Inputs in the geometry of the paper's 2D experiment (Sec. 4.1): wave grid n x n
+    on [-3, 3]^2, source supported in [-1, 1]^2, 1000 angles in [0, pi).  The paper's
+    phantom and trapping speed are not available: smoothed disks inside the unit disk
+    and smooth Gaussian sound-speed bumps stand in for them.  Arrays are [1][n][n]."""
+    rng = np.random.default_rng(seed)
+    dx = 2.0 * half_width / (n - 1)
+    ax = axis(n, dx)
+    y, x = ax[:, None], ax[None, :]
+    h = np.zeros((n, n))
+    for _ in range(n_disks):
+        while True:
+            cx, cy = rng.uniform(-0.75, 0.75, size=2)
+            if cx * cx + cy * cy <= 0.75 ** 2:
+                break
+        r = rng.uniform(0.05, 0.2)
+        v = rng.uniform(0.5, 1.0)
+        h = np.maximum(h, np.where((x - cx) ** 2 + (y - cy) ** 2 <= r * r, v, 0.0))
+    h = gaussian_smooth(h[None], 1.0, axes=(1, 2))[0]
+    c = np.ones((n, n))
+    for _ in range(c_bumps):
+        cx, cy = rng.uniform(-1.0, 1.0, size=2)
+        c += c_amp * rng.uniform(-1.0, 1.0) * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2 * 0.3 ** 2))
+    c = np.clip(c, 0.7, 1.3)
+    support = ((np.abs(x) <= 1.0) & (np.abs(y) <= 1.0)).astype(np.uint8)
+    noise = rng.standard_normal((n_angles, 1, n))
+    return dict(dx=dx, T=2.0, angles=uniform_angles(n_angles), h=h[None], c=c[None], support=support[None],
+                noise=noise, stripe=1.0)

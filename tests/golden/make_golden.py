@@ -3,6 +3,7 @@ oracle and the seeded input generators (no HIP code).
 
   python tests/golden/make_golden.py c128   # 128^3 reconstruction, 100 iterations
   python tests/golden/make_golden.py c256   # 256^3 forward / adjoint / gradient samples
+  python tests/golden/make_golden.py c384crop  # 64^3 window of the 384^3 workload, 200 iterations
 
 Each fixture is a small JSON text file: the recipe, seeds, sample indices and
 the oracle's values there.
@@ -88,9 +89,27 @@ def make_c256(seed=3001):
             "oracle_seconds": time.time() - t0}
 
 
+def make_c384crop(seed=4001):
+    """The central 64^3 window of the 384^3 workload as a standalone problem (same
+    dx = 3/383, T = 0.6, 360 angles, 10 bumps clamped to [0.75, 1.25]); 200 FB
+    iterations after a 20-step power iteration."""
+    case = as_f32_values(synth.make_case("c384", seed, n=64, dx=synth.grid_spacing(384)))
+    g = geometry(case)
+    t0 = time.time()
+    G = simulate(case, g)
+    h, obj, step = oracle.fb(g, case.c, G, case.lam, step=0.0, n_iter=case.n_iter, n_power=case.n_power,
+                             flags=oracle.POSITIVITY | oracle.PRECOND)
+    err = float(np.linalg.norm(h - case.h_true) / np.linalg.norm(case.h_true))
+    idx = sample_indices(g.vol_shape, seed + 1, count=8192)
+    return {"recipe": "c384", "window": 64, "seed": seed, "sample_seed": seed + 1, "n_iter": case.n_iter,
+            "n_power": case.n_power, "lam": case.lam, "step": step, "objective": obj.tolist(),
+            "h_norm": float(np.linalg.norm(h)), "sample_index": idx.tolist(), "h_sample": h.ravel()[idx].tolist(),
+            "relative_error_vs_phantom": err, "oracle_seconds": time.time() - t0}
+
+
 if __name__ == "__main__":
     which = sys.argv[1]
-    out = {"c128": make_c128, "c256": make_c256}[which]()
+    out = {"c128": make_c128, "c256": make_c256, "c384crop": make_c384crop}[which]()
     path = os.path.join(HERE, f"{which}_oracle.json")
     with open(path, "w") as f:
         json.dump(out, f)

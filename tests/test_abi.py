@@ -50,11 +50,11 @@ def test_version(lib):
 
 
 def _geom(nx=32, ny=30, nz=20, dx=0.05, T=0.5, cfl=0.3, n_angles=16, ns=0, ds=0.0, dtype=0, ndim=3,
-          angles=None):
+          angles=None, flags=0):
     from paper_1901_06503_amd import _lib
     ang = np.linspace(0, math.pi, n_angles, endpoint=False) if angles is None else np.asarray(angles, float)
     g = _lib.Geom(nx, ny, nz, ndim, dx, T, cfl, n_angles, ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                  ns, ds, dtype, 0)
+                  ns, ds, dtype, flags)
     return g, ang
 
 
@@ -64,7 +64,7 @@ def test_workspace_bytes_accounts_for_all_buffers(lib):
     assert lib.ffpat_workspace_bytes(ctypes.byref(g), ctypes.byref(out)) == 0
     nvox, ndat = 64 ** 3, 64 ** 3
     padded = 2 * 64 * 64 * (64 + 6) + 64 * 64 * (64 + 5)   # line copies (plane, transpose) + detector rows
-    need = (5 * nvox + ndat + padded) * 4
+    need = (7 * nvox + ndat + padded) * 4                  # k' + six volumes
     assert need <= out.value < need + 2 * 1024 * 1024
     g64, _b = _geom(nx=64, ny=64, nz=64, n_angles=64, dtype=1)
     out64 = ctypes.c_size_t()
@@ -78,6 +78,7 @@ def test_workspace_bytes_accounts_for_all_buffers(lib):
     (dict(nx=0), -1), (dict(dx=0.0), -1), (dict(dx=float("nan")), -1), (dict(T=-1.0), -1),
     (dict(n_angles=0), -1), (dict(ns=-3), -1), (dict(ds=-1.0), -1), (dict(dtype=7), -6), (dict(ndim=4), -1),
     (dict(angles=[0.0, float("inf")], n_angles=2), -1),
+    (dict(flags=4), 0), (dict(flags=8), 0), (dict(flags=4 | 8), -1),
 ])
 def test_geometry_validation(lib, kw, status):
     g, _a = _geom(**kw)

@@ -106,3 +106,28 @@ def test_c128_reconstruction_100_iterations(oracle, dtype):
     assert rel_l2(got, np.array(gold["h_sample"])) <= tol
     assert np.allclose(res.objective, gold["objective"], rtol=tol, atol=0)
     assert abs(float(res.h.double().norm()) / gold["h_norm"] - 1) <= tol
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_c384_window_reconstruction_200_iterations(oracle, dtype):
+    """Precision study: the central 64^3 window of the 384^3 workload (dx = 3/383,
+    T = 0.6, 360 angles) as a standalone problem, 200 iterations, against the oracle;
+    FP32 fields with FP64 reductions and all-FP64."""
+    import paper_1901_06503_amd as ff
+    import synth
+    gold = _load("c384crop_oracle.json")
+    mg = _golden_mod()
+    case = mg.as_f32_values(synth.make_case("c384", gold["seed"], n=64, dx=synth.grid_spacing(384)))
+    g = mg.geometry(case)
+    G = mg.simulate(case, g)
+    print(f"[fullsize] 384^3 window, 200 iterations, {dtype}", flush=True)
+    with ff.Plan(to_dev(case.c, dtype), case.dx, case.T, case.angles) as P:
+        res = P.reconstruct(to_dev(G, dtype), gold["lam"], gold["n_iter"], step=0.0, n_power=gold["n_power"])
+        idx = torch.tensor(gold["sample_index"], device="cuda")
+        got = res.h.double().flatten()[idx].cpu().numpy()
+        norm = float(res.h.double().norm())
+    tol = 1e-4 if dtype == torch.float32 else 1e-10
+    assert res.step == pytest.approx(gold["step"], rel=tol)
+    assert rel_l2(got, np.array(gold["h_sample"])) <= tol
+    assert np.allclose(res.objective, gold["objective"], rtol=tol, atol=0)
+    assert abs(norm / gold["h_norm"] - 1) <= tol

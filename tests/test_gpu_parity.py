@@ -46,14 +46,20 @@ def oracle_geom(oracle, k, ndim=3):
                            ns=k["ns"], ds=k["ds"], ndim=ndim)
 
 
-def gpu_plan(k, dtype, naive=False, ndim=3):
+def gpu_plan(k, dtype, naive=False, ndim=3, variant="pairs"):
+    """variant: 'pairs' (two leapfrog steps per pass, forced), 'single' (one step per
+    pass, forced), 'naive' (unblocked kernel)."""
     import paper_1901_06503_amd as ff
+    if naive:
+        variant = "naive"
     return ff.Plan(to_dev(k["c"], dtype), k["dx"], k["T"], k["angles"], ns=k["ns"], ds=k["ds"], cfl=k["cfl"],
-                   ndim=ndim, naive_stencil=naive)
+                   ndim=ndim, naive_stencil=variant == "naive", two_step_stencil=variant == "pairs")
+
+VARIANTS = ["pairs", "single", "naive"]
 
 
-def _case_tag(shape, dtype, naive):
-    print(f"[parity] shape={shape} dtype={dtype} naive={naive}", flush=True)
+def _case_tag(shape, dtype, variant):
+    print(f"[parity] shape={shape} dtype={dtype} variant={variant}", flush=True)
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])
@@ -67,15 +73,15 @@ def test_plan_time_grid_matches_oracle(oracle, shape, dtype):
         assert P.cmax == cmax
 
 
-@pytest.mark.parametrize("naive", [False, True])
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("dtype", [F64, F32])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_wave_and_transpose(oracle, shape, dtype, naive):
-    _case_tag(shape, dtype, naive)
+def test_wave_and_transpose(oracle, shape, dtype, variant):
+    _case_tag(shape, dtype, variant)
     k = make_case(shape, 2)
     g = oracle_geom(oracle, k)
     c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
-    with gpu_plan(k, dtype, naive) as P:
+    with gpu_plan(k, dtype, variant=variant) as P:
         p = to_np(P.wave(to_dev(h, dtype)))
         assert rel_l2(p, oracle.wave(g, c, h)) <= TOL_WAVE[dtype]
         q = to_np(P.wave_adjoint(to_dev(h, dtype)))
@@ -162,13 +168,31 @@ def test_edge_two_steps_and_tiny_grid(oracle, dtype):
         assert rel_l2(to_np(P.wave_adjoint(to_dev(h, dtype))), oracle.wave_T(g, c, h)) <= TOL_WAVE[dtype]
 
 
-@pytest.mark.parametrize("naive", [False, True])
+@pytest.mark.parametrize("variant", ["pairs", "single"])
+@pytest.mark.parametrize("nt", [1, 2, 3, 4, 5, 6, 7])
+def test_every_step_count(oracle, nt, variant):
+    """n_t = 1..7 covers first step only, pairs, odd leftovers and the dividing last step."""
+    k = make_case((13, 19, 70), 13, n_angles=5)
+    cmax = float(rounded(k["c"], F64).max())
+    k["T"] = (nt - 0.5) * k["cfl"] * k["dx"] / cmax
+    g = oracle_geom(oracle, k)
+    c, h = k["c"], k["h"]
+    d = k["rng"].standard_normal(g.data_shape)
+    with gpu_plan(k, F64, variant=variant) as P:
+        assert P.nt == nt
+        assert rel_l2(to_np(P.wave(to_dev(h, F64))), oracle.wave(g, c, h)) <= 1e-12
+        assert rel_l2(to_np(P.wave_adjoint(to_dev(h, F64))), oracle.wave_T(g, c, h)) <= 1e-12
+        assert rel_l2(to_np(P.forward(to_dev(h, F64))), oracle.forward(g, c, h)) <= 1e-12
+        assert rel_l2(to_np(P.adjoint(to_dev(d, F64))), oracle.adjoint(g, c, d)) <= 1e-12
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("dtype", [F64, F32])
-def test_two_dimensional_mode(oracle, dtype, naive):
+def test_two_dimensional_mode(oracle, dtype, variant):
     k = make_case((11, 50, 66), 9, n_angles=11)
     g = oracle_geom(oracle, k, ndim=2)
     c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
-    with gpu_plan(k, dtype, naive=naive, ndim=2) as P:
+    with gpu_plan(k, dtype, ndim=2, variant=variant) as P:
         assert rel_l2(to_np(P.wave(to_dev(h, dtype))), oracle.wave(g, c, h)) <= TOL_WAVE[dtype]
         assert rel_l2(to_np(P.forward(to_dev(h, dtype))), oracle.forward(g, c, h)) <= TOL_WAVE[dtype]
 
