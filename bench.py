@@ -47,8 +47,14 @@ def parse():
     ap.add_argument("--iters", type=int, default=None,
                     help="--mode serve: FB iterations per job (50); --mode precision: iterations (200)")
     ap.add_argument("--slots", type=int, default=6, help="--mode serve: admitted (resident) jobs")
+    ap.add_argument("--policy", default="shortest", choices=["fill", "shortest", "all"],
+                    help="--mode serve: scheduler policy (shortest: the oldest job + the least remaining work; "
+                         "fill: arrival order, small grids share the device)")
+    ap.add_argument("--fill-voxels", type=int, default=192 ** 3,
+                    help="--mode serve, policy fill: grid points the running jobs may hold together")
     ap.add_argument("--concurrency", type=int, default=2,
-                    help="--mode serve: jobs advancing at a time (the oldest + the least remaining work); 0 = all")
+                    help="--mode serve, policy shortest: jobs advancing at a time")
+    ap.add_argument("--serial", type=int, default=1, help="--mode serve: also run the serial baseline (1/0)")
     return ap.parse_args()
 
 
@@ -56,7 +62,10 @@ def run_precision(args):
     """384^3 / 360 angles / T = 0.6: Algorithm 8 for --iters iterations (default 200) in
     FP32 fields with FP64 reductions and in all-FP64, on the same data; reports the
     relative L2 difference of the two reconstructions and each one's error against
-    the phantom, and the FB iteration rate of both."""
+    the phantom, and the FB iteration rate of both.  Also the operator HBM fraction of
+    the forward operator A = X W_T: (w N^3 n_t + w N^3 + w N_phi N^2) / t_A / 8 TB/s with
+    w = 4 words of the field type per leapfrog point update (16 B FP32, 32 B FP64) and
+    one word per voxel and per bin for the projection, t_A from HIP events."""
     import numpy as np
     import torch
     import paper_1901_06503_amd as ff
@@ -82,7 +91,24 @@ def run_precision(args):
             t = time.perf_counter() - t0
             recon[name] = res.h.double()
             out[name] = {"seconds": t, "fb_iter_per_s_incl_power": n_iter / t, "step": res.step,
-                         "objective_first": float(res.objective[0]), "objective_last": float(res.objective[-1])}
+                         "objective_first": float(res.objective[0]), "objective_last": float(res.objective[-1]),
+                         "steps_per_pass": P.steps_per_pass}
+            x = res.h.clone()
+            g = P.forward(x)
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(3):
+                P.forward(x, out=g, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            t_a = e0.elapsed_time(e1) / 1e3 / 3
+            esz = 4 if dtype == torch.float32 else 8
+            n3, nang = case.n ** 3, len(case.angles)
+            alg = esz * (4 * n3 * P.nt + n3 + nang * case.n ** 2)
+            out[name].update(forward_ms=1e3 * t_a, forward_gpt_updates_per_s=n3 * P.nt / t_a / 1e9,
+                             operator_hbm_frac=alg / t_a / (HBM_PEAK_GBS * 1e9))
             log(f"{name}: {t:.1f}s for {n_iter} iterations + {case.n_power} power steps")
     h_true = torch.from_numpy(case.h_true).to(dev)
     d = float((recon["f32"] - recon["f64"]).norm() / recon["f64"].norm())
@@ -168,21 +194,25 @@ def run_serve(args):
             log(f"trace: {i + 1}/{args.jobs} jobs generated")
     clone = lambda: [serving.Job(job_id=j.job_id, arrival=j.arrival, c=j.c, G=j.G, dx=j.dx, T=j.T,
                                  angles=j.angles, lam=j.lam, n_iter=j.n_iter, n_power=j.n_power) for j in jobs]
-    log("serial baseline")
-    base = serving.summary(serving.run_serial(clone()))
-    log(f"serial: {base}")
+    base = None
+    if args.serial:
+        log("serial baseline")
+        base = serving.summary(serving.run_serial(clone()))
+        log(f"serial: {base}")
     free, total = torch.cuda.mem_get_info()
     sched = serving.Scheduler(hbm_budget=int(0.5 * free), max_active=args.slots, iters_per_turn=5,
-                              concurrency=args.concurrency)
+                              concurrency=args.concurrency, policy=args.policy, fill_voxels=args.fill_voxels)
     log("continuous batching")
     mixed_jobs = sched.run(clone())
     mixed = serving.summary(mixed_jobs)
     log(f"scheduler: {mixed}")
     print(json.dumps({"mode": "serve", "jobs": args.jobs, "rate_per_s": args.rate, "iters": args.iters or 50,
-                      "slots": args.slots, "concurrency": args.concurrency, "serial": base,
+                      "slots": args.slots, "policy": args.policy, "fill_voxels": args.fill_voxels,
+                      "concurrency": args.concurrency, "serial": base,
                       "continuous_batching": mixed, "peak_active": sched.peak_active,
                       "peak_running": sched.peak_running, "peak_bytes": sched.peak_bytes,
-                      "throughput_gain": mixed["jobs_per_s"] / base["jobs_per_s"]}), flush=True)
+                      "throughput_gain": mixed["jobs_per_s"] / base["jobs_per_s"] if base else None}),
+          flush=True)
 
 
 def run_wave_only(args):

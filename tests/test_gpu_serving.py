@@ -100,8 +100,8 @@ def test_results_in_the_mix_equal_results_alone():
     from paper_1901_06503_amd.serving import Scheduler, run_serial, summary
     jobs = _trace([24, 40, 32, 48, 24, 40, 32, 24], 70)
     alone = run_serial(_clone(jobs))
-    for concurrency in (0, 2):
-        sched = Scheduler(hbm_budget=8 << 30, max_active=4, iters_per_turn=3, concurrency=concurrency)
+    for policy in ("fill", "shortest", "all"):
+        sched = Scheduler(hbm_budget=8 << 30, max_active=4, iters_per_turn=3, policy=policy)
         mixed = sched.run(_clone(jobs))
         assert sched.peak_running > 1                      # work really overlapped on the device
         for a, b in zip(sorted(alone, key=lambda j: j.job_id), sorted(mixed, key=lambda j: j.job_id)):

@@ -1,0 +1,66 @@
+"""Host logic of the serving scheduler: which admitted jobs may start their next
+chunk under each policy (no device work)."""
+import types
+
+import pytest
+
+from paper_1901_06503_amd.serving import Scheduler, _remaining_work
+
+
+class _C:
+    def __init__(self, n):
+        self.n = n
+
+    def numel(self):
+        return self.n ** 3
+
+
+def _active(job_id, arrival, n, done=0, n_iter=50, powered=True, nt=100):
+    job = types.SimpleNamespace(job_id=job_id, arrival=arrival, c=_C(n), n_iter=n_iter, n_power=20)
+    a = types.SimpleNamespace(job=job, done_iters=done, powered=powered, plan=types.SimpleNamespace(nt=nt))
+    return a
+
+
+def _ids(chosen):
+    return [a.job.job_id for a in chosen]
+
+
+def test_fill_runs_in_arrival_order_up_to_the_threshold():
+    s = Scheduler(hbm_budget=1 << 30, policy="fill", fill_voxels=192 ** 3)
+    act = [_active(3, 0.3, 64), _active(1, 0.1, 128), _active(2, 0.2, 128), _active(4, 0.4, 64)]
+    # 128^3 + 128^3 = 4.2M <= 7.1M; + 64^3 (0.26M) still fits
+    assert _ids(s._choose(act)) == [1, 2, 3, 4]
+    big = [_active(5, 0.0, 256), _active(6, 0.1, 64)]
+    assert _ids(s._choose(big)) == [5]                    # the oldest always runs, even alone
+    mid = [_active(7, 0.0, 192), _active(8, 0.1, 64), _active(9, 0.2, 128)]
+    assert _ids(s._choose(mid)) == [7]                    # 192^3 + 64^3 > 192^3: nothing joins
+    tie = [_active(11, 0.0, 64), _active(10, 0.0, 64)]
+    assert _ids(s._choose(tie)) == [10, 11]               # equal arrivals: by job id
+
+
+def test_fill_stops_at_the_first_job_that_does_not_fit():
+    s = Scheduler(hbm_budget=1 << 30, policy="fill", fill_voxels=160 ** 3)
+    act = [_active(1, 0.0, 128), _active(2, 0.1, 128), _active(3, 0.2, 64)]
+    assert _ids(s._choose(act)) == [1]                    # no overtaking past job 2
+
+
+def test_shortest_keeps_the_oldest_and_adds_the_least_remaining_work():
+    s = Scheduler(hbm_budget=1 << 30, policy="shortest", concurrency=2)
+    act = [_active(1, 0.0, 256), _active(2, 0.1, 128, done=40), _active(3, 0.2, 64)]
+    rem = {a.job.job_id: _remaining_work(a) for a in act}
+    assert rem[3] < rem[2] < rem[1]
+    assert _ids(s._choose(act)) == [1, 3]
+
+
+def test_remaining_work_counts_the_power_iteration():
+    a = _active(1, 0.0, 64, powered=False)
+    b = _active(1, 0.0, 64, powered=True)
+    assert _remaining_work(a) == pytest.approx(_remaining_work(b) * 70 / 50)
+
+
+def test_all_and_unknown_policy():
+    s = Scheduler(hbm_budget=1 << 30, policy="all")
+    act = [_active(2, 0.1, 256), _active(1, 0.0, 256)]
+    assert _ids(s._choose(act)) == [2, 1]
+    with pytest.raises(ValueError):
+        Scheduler(hbm_budget=1, policy="lifo")
