@@ -34,6 +34,7 @@ struct AngleParams {
   double hw, inv_hw;
   double w;
   long long ur_fix, b0_fix, bi_fix, bk_fix;
+  float inv_hw_f, w_f;   // inv_hw and w rounded to FP32 (the FP32 backprojector's weights)
   int major_x;
   int pad_;
 };

@@ -7,18 +7,22 @@
 // the same weights per voxel, so the two are exact transposes.
 #include "kernels.h"
 
+#include <cstdlib>
+
 namespace ffpat {
 
 // ---------------------------------------------------------------------------
-// Projector: one thread per detector bin (a, z, j), coalesced writes along s.
+// Projector: one thread per detector bin j of angle a in ZP consecutive planes
+// (the ray's crossings do not depend on z; the launch uses ZP = 1), coalesced
+// writes along s.
 // Rays march over rows (|cos| >= |sin|) or columns (|sin| > |cos|); for the
 // latter the plane is read from its transposed copy, so in both cases the two
 // taps of a lane sit in one contiguous line and neighbouring bins read
 // neighbouring addresses.  Lines carry 3 zeros on each side: every crossing
 // u of the marched range lies in [-2, nm + 1], so no tap needs a bounds check.
-// Work order: angles fastest, then planes; each XCD owns a contiguous range
-// of planes, so a plane (and its transpose) is fetched into one L2 and reused
-// by every angle.
+// Work order: angles fastest, then plane groups; each XCD owns a contiguous
+// range of planes, so a plane (and its transpose) is fetched into one L2 and
+// reused by every angle.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -49,7 +53,7 @@ pad_planes_kernel(const T *__restrict__ v, T *__restrict__ padN, T *__restrict__
   }
 }
 
-template <typename T>
+template <typename T, int ZP, int UNR>
 __global__ void __launch_bounds__(256)
 project_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__restrict__ g,
                const AngleParams *__restrict__ ap, int nx, int ny, int nz, int ns, int n_angles, int n_work)
@@ -58,24 +62,32 @@ project_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__rest
   const int per_xcd = (n_work + 7) / 8;
   const int t = (b % 8) * per_xcd + b / 8;
   if (t >= n_work) return;
+  const int nzg = (nz + ZP - 1) / ZP;
   const int a = t % n_angles;
   const int rest = t / n_angles;
-  const int z = rest % nz;
-  const int jb = rest / nz;
+  const int z0 = (rest % nzg) * ZP;
+  const int jb = rest / nzg;
   const int j = jb * 256 + threadIdx.x;
   if (j >= ns) return;
 
   const AngleParams P = ap[a];
   // padded plane (index 0 = first pad) of the marched orientation; block-uniform
   int nr, nm;
-  const char *plane;
+  const char *plane0;
+  size_t pstride;   // bytes between consecutive planes of that copy
   if (P.major_x) {  // march over columns x_r (rows of the transpose), interpolate along y
     nr = nx; nm = ny;
-    plane = reinterpret_cast<const char *>(padT + (size_t)z * nx * (ny + kLinePadL + kLinePadR));
+    pstride = (size_t)nx * (ny + kLinePadL + kLinePadR) * sizeof(T);
+    plane0 = reinterpret_cast<const char *>(padT);
   } else {          // march over rows y_r, interpolate along x
     nr = ny; nm = nx;
-    plane = reinterpret_cast<const char *>(padN + (size_t)z * ny * (nx + kLinePadL + kLinePadR));
+    pstride = (size_t)ny * (nx + kLinePadL + kLinePadR) * sizeof(T);
+    plane0 = reinterpret_cast<const char *>(padN);
   }
+  // the ZP planes of this group (past the last plane: the last plane again, never stored)
+  const char *pl[ZP];
+#pragma unroll
+  for (int q = 0; q < ZP; ++q) pl[q] = plane0 + (size_t)min(z0 + q, nz - 1) * pstride;
   const unsigned LPB = (unsigned)((nm + kLinePadL + kLinePadR) * sizeof(T));   // line pitch in bytes
   const double A = P.u0 + (double)j * P.uj;
   // marched lines whose crossing lies in (-1, nm) (where a tap is inside), widened
@@ -90,38 +102,77 @@ project_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__rest
     hi = -1.0;
   }
   const int r0 = (int)lo, r1 = (int)hi;
-  // 32-bit byte offsets from the uniform plane base keep the address math to
-  // one add per tap pair (the second tap is the same offset + sizeof(T))
+  // The crossing (offset and interpolation weight) of a marched line is the same
+  // in every plane: it is computed once and serves the ZP planes, whose loads
+  // share one 32-bit byte offset from their uniform plane bases.
   unsigned rowb = (unsigned)r0 * LPB;
-  T acc = T(0);
+  T acc[ZP];
+#pragma unroll
+  for (int q = 0; q < ZP; ++q) acc[q] = T(0);
   if (sizeof(T) == 4) {
     // exact fixed-point stepping: u(r) = U / 2^32, U += ur_fix per line
     long long U = llrint(fma((double)r0, P.ur, A) * 4294967296.0);
     const long long UR = P.ur_fix;
-#pragma unroll 8
+#pragma unroll UNR
     for (int r = r0; r <= r1; ++r) {
       const unsigned off = rowb + (unsigned)(((int)(U >> 32) + kLinePadL) * (int)sizeof(T));
       const T f = (T)(unsigned)(U & 0xffffffffLL) * T(2.3283064365386963e-10);
-      const T v0 = *reinterpret_cast<const T *>(plane + off);
-      const T v1 = *reinterpret_cast<const T *>(plane + off + sizeof(T));
-      acc += v0 + f * (v1 - v0);
+      const T e = T(1) - f;
+#pragma unroll
+      for (int q = 0; q < ZP; ++q) {
+        const T v0 = *reinterpret_cast<const T *>(pl[q] + off);
+        const T v1 = *reinterpret_cast<const T *>(pl[q] + off + sizeof(T));
+        acc[q] = fma(f, v1, fma(e, v0, acc[q]));   // linear interpolation, two FMAs per plane
+      }
       U += UR;
       rowb += LPB;
     }
   } else {
-#pragma unroll 4
+#pragma unroll(UNR > 4 ? 4 : UNR)
     for (int r = r0; r <= r1; ++r) {
       const double u = fma((double)r, P.ur, A);
       const double fl = floor(u);
       const unsigned off = rowb + (unsigned)(((int)fl + kLinePadL) * (int)sizeof(T));
       const T f = (T)(u - fl);
-      const T v0 = *reinterpret_cast<const T *>(plane + off);
-      const T v1 = *reinterpret_cast<const T *>(plane + off + sizeof(T));
-      acc += v0 + f * (v1 - v0);
+      const T e = T(1) - f;
+#pragma unroll
+      for (int q = 0; q < ZP; ++q) {
+        const T v0 = *reinterpret_cast<const T *>(pl[q] + off);
+        const T v1 = *reinterpret_cast<const T *>(pl[q] + off + sizeof(T));
+        acc[q] = fma(f, v1, fma(e, v0, acc[q]));
+      }
       rowb += LPB;
     }
   }
-  g[((size_t)a * nz + z) * ns + j] = acc * (T)P.w;
+#pragma unroll
+  for (int q = 0; q < ZP; ++q)
+    if (z0 + q < nz) g[((size_t)a * nz + z0 + q) * ns + j] = acc[q] * (T)P.w;
+}
+
+// planes per thread of the backprojector (FFPAT_XRAY_ZP = 1, 4 or 8 overrides):
+// one for fewer than four planes, else 4
+static int xray_planes(int nz)
+{
+  static const int env = [] {
+    const char *e = getenv("FFPAT_XRAY_ZP");
+    const int v = e ? atoi(e) : 0;
+    return (v == 1 || v == 4 || v == 8) ? v : 0;
+  }();
+  if (nz < 4) return 1;
+  return env ? env : 4;
+}
+
+template <typename T, int ZP, int UNR>
+static hipError_t project_dispatch(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *padN,
+                                   const T *padT, T *g, hipStream_t s)
+{
+  const int jblocks = (ns + 255) / 256;
+  const long n_work = (long)jblocks * ((d.nz + ZP - 1) / ZP) * n_angles;
+  const long grid = (n_work + 7) / 8 * 8;
+  const int tb = ns >= 256 ? 256 : ((ns + 63) / 64) * 64;
+  project_kernel<T, ZP, UNR><<<(unsigned)grid, tb, 0, s>>>(padN, padT, g, ap, d.nx, d.ny, d.nz, ns, n_angles,
+                                                            (int)n_work);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -132,30 +183,30 @@ hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams
   pad_planes_kernel<T><<<pgrid, 256, 0, s>>>(vol, padN, padT, d.nx, d.ny, need_n ? 1 : 0, need_t ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int jblocks = (ns + 255) / 256;
-  const long n_work = (long)jblocks * d.nz * n_angles;
-  const long grid = (n_work + 7) / 8 * 8;
-  const int tb = ns >= 256 ? 256 : ((ns + 63) / 64) * 64;
-  project_kernel<T><<<(unsigned)grid, tb, 0, s>>>(padN, padT, g, ap, d.nx, d.ny, d.nz, ns, n_angles, (int)n_work);
-  return hipGetLastError();
+  // one plane per thread, eight lines unrolled: measured at 256^3 / 256 angles,
+  // sharing the crossings over 2 or 4 planes per thread was no faster (2x8) or
+  // 16% slower (4x4; more planes in flight per compute unit, fewer cache hits)
+  return project_dispatch<T, 1, 8>(d, n_angles, ns, ap, padN, padT, g, s);
 }
 
 // ---------------------------------------------------------------------------
-// Backprojector: one thread per 4 voxels (i, k + 4q) of a 64 x 16 tile in a
-// plane, loop over angles, reading detector rows in the padded layout.
+// Backprojector: one thread per voxel column position (i, k) of a 64 x 4 tile
+// in ZP consecutive planes, loop over angles, reading detector rows in the
+// padded layout.  The bin position of (i, k) and its weights do not depend on
+// z: they are computed once per angle and serve the ZP planes, whose rows are
+// uniform bases with one shared 32-bit lane offset.
 // With ds >= m dx for every angle (e.g. ds = dx) the footprint covers at most
 // the bins floor(t) and floor(t) + 1: FP32 steps t in 32.32 fixed point and
 // clamps the bin to [-2, ns + 1], where the pads (zeros) absorb voxels that
 // project off the detector; FP64 evaluates t in double.  Otherwise every bin
-// within the half-width is visited.  Tiles of one plane are consecutive on
-// one XCD so the plane's detector rows stay in L2.
+// within the half-width is visited.  Tiles of one plane group are consecutive
+// on one XCD so its detector rows stay in L2.
 // ---------------------------------------------------------------------------
-template <typename T, bool TWO_TAP>
+template <typename T, bool TWO_TAP, int ZP>
 __global__ void __launch_bounds__(256)
 backproject_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const AngleParams *__restrict__ ap, int n_angles,
                    int nx, int ny, int nz, int ns, const T *__restrict__ kap, int tiles_x, int tiles_y, int n_work)
 {
-  constexpr int RY = 4;
   const int b = blockIdx.x;
   const int per_xcd = (n_work + 7) / 8;
   const int tw = (b % 8) * per_xcd + b / 8;
@@ -163,92 +214,101 @@ backproject_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const AngleP
   const int bx = tw % tiles_x;
   const int rest = tw / tiles_x;
   const int by = rest % tiles_y;
-  const int z = rest / tiles_y;
+  const int z0 = (rest / tiles_y) * ZP;
   const int i = bx * 64 + (threadIdx.x & 63);
-  const int k0 = by * 16 + (threadIdx.x >> 6);
-  if (i >= nx) return;
+  const int k = by * 4 + (threadIdx.x >> 6);
+  if (i >= nx || k >= ny) return;
 
   const int RS = ns + kRowPadL + kRowPadR;
-  T acc[RY];
+  T acc[ZP];
 #pragma unroll
-  for (int q = 0; q < RY; ++q) acc[q] = T(0);
-  // detector row of (a, z) = uniform base; lanes add 32-bit byte offsets
-  const char *gz = reinterpret_cast<const char *>(gpad + (size_t)z * RS);
+  for (int q = 0; q < ZP; ++q) acc[q] = T(0);
+  // detector rows (a, z0 + q): uniform bases; past the last plane, the last plane's row (never stored)
+  const char *gz[ZP];
+#pragma unroll
+  for (int q = 0; q < ZP; ++q) gz[q] = reinterpret_cast<const char *>(gpad + (size_t)min(z0 + q, nz - 1) * RS);
   const size_t astride = (size_t)nz * RS * sizeof(T);
 #pragma unroll 2
   for (int a = 0; a < n_angles; ++a) {
     const AngleParams &P = ap[a];
-    const char *row = gz + (size_t)a * astride;
-    if (TWO_TAP && sizeof(T) == 4) {
-      const long long T0 = P.b0_fix + (long long)i * P.bi_fix + (long long)k0 * P.bk_fix;
-      const long long BK4 = 4 * P.bk_fix;
-      const T ih = (T)P.inv_hw, wa = (T)P.w;
+    const size_t aoff = (size_t)a * astride;
+    if (TWO_TAP) {
+      unsigned off;
+      T w0, w1;
+      if (sizeof(T) == 4) {
+        const long long Tf = P.b0_fix + (long long)i * P.bi_fix + (long long)k * P.bk_fix;
+        const int j0 = min(max((int)(Tf >> 32), -2), ns + 1);
+        off = (unsigned)((j0 + kRowPadL) * (int)sizeof(T));
+        const T f = (T)(unsigned)(Tf & 0xffffffffLL) * T(2.3283064365386963e-10);
+        const T ih = P.inv_hw_f, wa = P.w_f;
+        w0 = wa * fmax(T(1) - f * ih, T(0));
+        w1 = wa * fmax(T(1) - (T(1) - f) * ih, T(0));
+      } else {
+        const double t = P.b0 + (double)i * P.bi + (double)k * P.bk;
+        const double fl = fmin(fmax(floor(t), -2.0), (double)(ns + 1));
+        off = (unsigned)(((int)fl + kRowPadL) * (int)sizeof(T));
+        const T f = (T)(t - fl);
+        const T ih = (T)P.inv_hw, wa = (T)P.w;
+        // a clamped bin reads two pads, so the weights do not matter there
+        w0 = wa * fmax(T(1) - f * ih, T(0));
+        w1 = wa * fmax(T(1) - (T(1) - f) * ih, T(0));
+      }
 #pragma unroll
-      for (int q = 0; q < RY; ++q) {
-        const long long Tq = T0 + (long long)q * BK4;
-        const int j0 = min(max((int)(Tq >> 32), -2), ns + 1);
-        const unsigned off = (unsigned)((j0 + kRowPadL) * (int)sizeof(T));
-        const T f = (T)(unsigned)(Tq & 0xffffffffLL) * T(2.3283064365386963e-10);
-        const T w0 = fmax(T(1) - f * ih, T(0));
-        const T w1 = fmax(T(1) - (T(1) - f) * ih, T(0));
+      for (int q = 0; q < ZP; ++q) {
+        const char *row = gz[q] + aoff;
         const T v0 = *reinterpret_cast<const T *>(row + off);
         const T v1 = *reinterpret_cast<const T *>(row + off + sizeof(T));
-        acc[q] += wa * (w0 * v0 + w1 * v1);
+        acc[q] = fma(w1, v1, fma(w0, v0, acc[q]));
       }
     } else {
-      const T *rowt = reinterpret_cast<const T *>(row) + kRowPadL;
-      const double t0 = P.b0 + (double)i * P.bi + (double)k0 * P.bk;
+      const double t = P.b0 + (double)i * P.bi + (double)k * P.bk;
+      const int jlo = (int)fmin(fmax(ceil(t - P.hw), 0.0), (double)ns);
+      const int jhi = (int)fmax(fmin(floor(t + P.hw), (double)(ns - 1)), -1.0);
+      for (int j = jlo; j <= jhi; ++j) {
+        const double wt = 1.0 - fabs((double)j - t) * P.inv_hw;
+        if (wt > 0.0) {
+          const T wj = (T)wt * (T)P.w;
 #pragma unroll
-      for (int q = 0; q < RY; ++q) {
-        const double t = fma((double)(4 * q), P.bk, t0);
-        if (TWO_TAP) {
-          const double fl = fmin(fmax(floor(t), -2.0), (double)(ns + 1));
-          const unsigned off = (unsigned)(((int)fl + kRowPadL) * (int)sizeof(T));
-          const T f = (T)(t - fl);
-          const T ih = (T)P.inv_hw;
-          // a clamped bin reads two pads, so the weights do not matter there
-          const T w0 = fmax(T(1) - f * ih, T(0));
-          const T w1 = fmax(T(1) - (T(1) - f) * ih, T(0));
-          const T v0 = *reinterpret_cast<const T *>(row + off);
-          const T v1 = *reinterpret_cast<const T *>(row + off + sizeof(T));
-          acc[q] += (T)P.w * (w0 * v0 + w1 * v1);
-        } else {
-          const int jlo = (int)fmin(fmax(ceil(t - P.hw), 0.0), (double)ns);
-          const int jhi = (int)fmax(fmin(floor(t + P.hw), (double)(ns - 1)), -1.0);
-          T sum = T(0);
-          for (int j = jlo; j <= jhi; ++j) {
-            const double wt = 1.0 - fabs((double)j - t) * P.inv_hw;
-            if (wt > 0.0) sum += (T)wt * rowt[j];
-          }
-          acc[q] += sum * (T)P.w;
+          for (int q = 0; q < ZP; ++q)
+            acc[q] += wj * reinterpret_cast<const T *>(gz[q] + aoff)[kRowPadL + j];
         }
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < RY; ++q) {
-    const int k = k0 + 4 * q;
-    if (k < ny) {
-      const size_t idx = ((size_t)z * ny + k) * nx + i;
+  for (int q = 0; q < ZP; ++q) {
+    if (z0 + q < nz) {
+      const size_t idx = ((size_t)(z0 + q) * ny + k) * nx + i;
       vol[idx] = kap ? acc[q] * kap[idx] : acc[q];
     }
   }
+}
+
+template <typename T, int ZP>
+static hipError_t backproject_dispatch(const Dims &d, int n_angles, int ns, const AngleParams *ap, bool two_tap,
+                                       const T *gpad, T *vol, const T *kap, hipStream_t s)
+{
+  const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + 3) / 4;
+  const long n_work = (long)tiles_x * tiles_y * ((d.nz + ZP - 1) / ZP);
+  const long grid = (n_work + 7) / 8 * 8;
+  if (two_tap)
+    backproject_kernel<T, true, ZP><<<(unsigned)grid, 256, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns,
+                                                                    kap, tiles_x, tiles_y, (int)n_work);
+  else
+    backproject_kernel<T, false, ZP><<<(unsigned)grid, 256, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns,
+                                                                     kap, tiles_x, tiles_y, (int)n_work);
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_backproject(const Dims &d, int n_angles, int ns, const AngleParams *ap, bool two_tap,
                               const T *gpad, T *vol, const T *kap, hipStream_t s)
 {
-  const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + 15) / 16;
-  const long n_work = (long)tiles_x * tiles_y * d.nz;
-  const long grid = (n_work + 7) / 8 * 8;
-  if (two_tap)
-    backproject_kernel<T, true><<<(unsigned)grid, 256, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns, kap,
-                                                                tiles_x, tiles_y, (int)n_work);
-  else
-    backproject_kernel<T, false><<<(unsigned)grid, 256, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns, kap,
-                                                                 tiles_x, tiles_y, (int)n_work);
-  return hipGetLastError();
+  switch (xray_planes(d.nz)) {
+    case 8: return backproject_dispatch<T, 8>(d, n_angles, ns, ap, two_tap, gpad, vol, kap, s);
+    case 4: return backproject_dispatch<T, 4>(d, n_angles, ns, ap, two_tap, gpad, vol, kap, s);
+    default: return backproject_dispatch<T, 1>(d, n_angles, ns, ap, two_tap, gpad, vol, kap, s);
+  }
 }
 
 template <typename T>

@@ -178,7 +178,7 @@ int resolve(const ffpat_geom *g, Resolved *r)
   if (nvox > ((size_t)1 << 33) || ndat > ((size_t)1 << 33)) return fail(FFPAT_EINVAL, "problem too large");
   // work-group counts of the projector / backprojector grids must fit in int
   if ((size_t)g->n_angles * g->nz * (size_t)((ns + 255) / 256) > (size_t)INT32_MAX - 8 ||
-      (size_t)((g->nx + 63) / 64) * ((g->ny + 15) / 16) * g->nz > (size_t)INT32_MAX - 8)
+      (size_t)((g->nx + 63) / 64) * ((g->ny + 3) / 4) * g->nz > (size_t)INT32_MAX - 8)
     return fail(FFPAT_EINVAL, "problem too large for one launch");
   r->d = Dims{g->nx, g->ny, g->nz, ndim};
   r->dtype = g->dtype;
@@ -247,6 +247,8 @@ AngleParams angle_params(double phi, const Resolved &r)
   P.b0 = cs - cx * dx * ca / ds - cy * dx * sa / ds;
   P.hw = m * dx / ds;
   P.inv_hw = 1.0 / P.hw;
+  P.inv_hw_f = (float)P.inv_hw;
+  P.w_f = (float)P.w;
   const double two32 = 4294967296.0;
   P.ur_fix = std::llrint(P.ur * two32);
   P.b0_fix = std::llrint(P.b0 * two32);
