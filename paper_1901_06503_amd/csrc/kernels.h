@@ -78,10 +78,12 @@ hipError_t launch_c_stats(const Dims &d, const T *c, double *partials, int nbloc
 // g[a][z][j] = X vol (Joseph ray march).  padN [nz][ny][nx + 6] and padT
 // [nz][nx][ny + 6] receive zero-padded copies of vol's rows and of its x-y
 // transpose (rays running along x read the transpose); need_n / need_t say
-// which copies the angle set uses.
+// which copies the angle set uses.  aorder lists the angles that march rows
+// (the first n_row_angles entries), then those that march columns.
 template <typename T>
-hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *vol, T *padN,
-                          T *padT, bool need_n, bool need_t, T *g, hipStream_t s);
+hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams *ap, const int *aorder,
+                          int n_row_angles, const T *vol, T *padN, T *padT, bool need_n, bool need_t, T *g,
+                          hipStream_t s);
 
 // vol = X^T g from detector rows in padded layout gpad [rows][ns + 5]
 // (values at offset 2), optionally multiplied point-wise by kap.

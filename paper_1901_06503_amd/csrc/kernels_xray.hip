@@ -149,6 +149,145 @@ project_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__rest
     if (z0 + q < nz) g[((size_t)a * nz + z0 + q) * ns + j] = acc[q] * (T)P.w;
 }
 
+// ---------------------------------------------------------------------------
+// Projector with the planes staged in LDS.  A 1024-thread work-group owns four
+// consecutive planes, one orientation (rays marching rows read the padded
+// planes, rays marching columns the padded transposes), 32 angles of that
+// orientation and 256 detector bins; thread (bin j, quarter s) marches the rays
+// of angles 8s..8s+7.  The marched lines are staged chunk by chunk into LDS
+// with the four planes interleaved ([line][position] of 4-vectors), so the two
+// taps of a crossing in all four planes are two vector LDS reads and the
+// crossing's position and weights serve four planes.  Every ray visits every
+// line: the tap index is clamped into the three zero pads on each side, where
+// both taps are zero exactly when the crossing misses the line (the same sums
+// as marching only the crossed lines).  Positions: exact 32.32 fixed point in
+// FP32, double arithmetic in FP64 (as in project_kernel).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct alignas(4 * sizeof(T)) Vec4 {
+  T x, y, z, w;
+};
+
+constexpr int kLdsBytes = 139264;   // 136 KiB per work-group (one work-group per compute unit)
+constexpr int kProjAngles = 32, kProjAnglesPerThread = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__restrict__ g,
+                   const AngleParams *__restrict__ ap, const int *__restrict__ aorder, int n_row_angles,
+                   int n_angles, int nx, int ny, int nz, int ns, int n_groups_rows, int n_groups, int n_work)
+{
+  constexpr int NV = kLdsBytes / sizeof(Vec4<T>);
+  __shared__ Vec4<T> lds[NV];
+  const int b = blockIdx.x;
+  const int per_xcd = (n_work + 7) / 8;
+  const int t = (b % 8) * per_xcd + b / 8;
+  if (t >= n_work) return;                  // whole group exits together
+  const int nzg = (nz + 3) / 4;
+  const int grp = t % n_groups;
+  const int rest = t / n_groups;
+  const int z0 = (rest % nzg) * 4;
+  const int jb = rest / nzg;
+  const bool rows = grp < n_groups_rows;
+  const int gi = rows ? grp : grp - n_groups_rows;
+  const int a_begin = rows ? 0 : n_row_angles;
+  const int a_count = rows ? n_row_angles : n_angles - n_row_angles;
+  const int nr = rows ? ny : nx, nm = rows ? nx : ny;
+  const int LP = nm + kLinePadL + kLinePadR;
+  const T *src = rows ? padN : padT;       // [nz][nr][LP]
+  const int j = jb * 256 + (threadIdx.x & 255);
+  const int quarter = threadIdx.x >> 8;     // uniform per wave
+  const bool jin = j < ns;
+
+  // per lane: the rays' positions at line 0 (FP32: fixed point; FP64: A = u0 + j uj)
+  long long U[kProjAnglesPerThread];
+  double A[kProjAnglesPerThread];
+  T acc[kProjAnglesPerThread][4];
+#pragma unroll
+  for (int m = 0; m < kProjAnglesPerThread; ++m) {
+    const int ia = gi * kProjAngles + quarter * kProjAnglesPerThread + m;
+    U[m] = 0;
+    A[m] = 0.0;
+    if (ia < a_count) {
+      const AngleParams &P = ap[aorder[a_begin + ia]];
+      A[m] = P.u0 + (double)j * P.uj;
+      if (sizeof(T) == 4) U[m] = llrint(A[m] * 4294967296.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[m][q] = T(0);
+  }
+  const size_t pl = (size_t)nr * LP;
+  const T *s0 = src + (size_t)min(z0, nz - 1) * pl, *s1 = src + (size_t)min(z0 + 1, nz - 1) * pl;
+  const T *s2 = src + (size_t)min(z0 + 2, nz - 1) * pl, *s3 = src + (size_t)min(z0 + 3, nz - 1) * pl;
+  const int R = min(nr, NV / LP);           // lines per chunk
+  for (int c0 = 0; c0 < nr; c0 += R) {
+    const int rc = min(R, nr - c0);
+    __syncthreads();                        // the previous chunk has been read
+    const int n_el = rc * LP;
+    const size_t off0 = (size_t)c0 * LP;
+    for (int e = threadIdx.x; e < n_el; e += 1024)
+      lds[e] = Vec4<T>{s0[off0 + e], s1[off0 + e], s2[off0 + e], s3[off0 + e]};
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kProjAnglesPerThread; ++m) {
+      const int ia = gi * kProjAngles + quarter * kProjAnglesPerThread + m;
+      if (ia >= a_count) break;             // uniform per wave
+      if (sizeof(T) == 4) {
+        const long long UR = ap[aorder[a_begin + ia]].ur_fix;
+        long long u = U[m];
+#pragma unroll 4
+        for (int r = 0; r < rc; ++r) {
+          const int i0 = min(max((int)(u >> 32), -3), nm + 1) + kLinePadL;
+          const T f = (T)(unsigned)(u & 0xffffffffLL) * T(2.3283064365386963e-10);
+          const T e = T(1) - f;
+          const Vec4<T> v0 = lds[r * LP + i0], v1 = lds[r * LP + i0 + 1];
+          acc[m][0] = fma(f, v1.x, fma(e, v0.x, acc[m][0]));
+          acc[m][1] = fma(f, v1.y, fma(e, v0.y, acc[m][1]));
+          acc[m][2] = fma(f, v1.z, fma(e, v0.z, acc[m][2]));
+          acc[m][3] = fma(f, v1.w, fma(e, v0.w, acc[m][3]));
+          u += UR;
+        }
+        U[m] = u;
+      } else {
+        const double ur = ap[aorder[a_begin + ia]].ur;
+#pragma unroll 2
+        for (int r = 0; r < rc; ++r) {
+          const double u = fma((double)(c0 + r), ur, A[m]);
+          const double fl = floor(u);
+          const int i0 = (int)fmin(fmax(fl, -3.0), (double)(nm + 1)) + kLinePadL;
+          const T f = (T)(u - fl);
+          const T e = T(1) - f;
+          const Vec4<T> v0 = lds[r * LP + i0], v1 = lds[r * LP + i0 + 1];
+          acc[m][0] = fma(f, v1.x, fma(e, v0.x, acc[m][0]));
+          acc[m][1] = fma(f, v1.y, fma(e, v0.y, acc[m][1]));
+          acc[m][2] = fma(f, v1.z, fma(e, v0.z, acc[m][2]));
+          acc[m][3] = fma(f, v1.w, fma(e, v0.w, acc[m][3]));
+        }
+      }
+    }
+  }
+  if (!jin) return;
+#pragma unroll
+  for (int m = 0; m < kProjAnglesPerThread; ++m) {
+    const int ia = gi * kProjAngles + quarter * kProjAnglesPerThread + m;
+    if (ia >= a_count) break;
+    const int a = aorder[a_begin + ia];
+    const T w = sizeof(T) == 4 ? (T)ap[a].w_f : (T)ap[a].w;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (z0 + q < nz) g[((size_t)a * nz + z0 + q) * ns + j] = acc[m][q] * w;
+  }
+}
+
+static bool xray_lds_enabled()
+{
+  static const bool on = [] {
+    const char *e = getenv("FFPAT_XRAY_LDS");
+    return e ? atoi(e) != 0 : true;
+  }();
+  return on;
+}
+
 // planes per thread of the backprojector (FFPAT_XRAY_ZP = 1, 4 or 8 overrides):
 // one for fewer than four planes, else 4
 static int xray_planes(int nz)
@@ -176,13 +315,24 @@ static hipError_t project_dispatch(const Dims &d, int n_angles, int ns, const An
 }
 
 template <typename T>
-hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams *ap, const T *vol, T *padN,
-                          T *padT, bool need_n, bool need_t, T *g, hipStream_t s)
+hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams *ap, const int *aorder,
+                          int n_row_angles, const T *vol, T *padN, T *padT, bool need_n, bool need_t, T *g,
+                          hipStream_t s)
 {
   dim3 pgrid((d.nx + 31) / 32, (d.ny + 31) / 32, d.nz);
   pad_planes_kernel<T><<<pgrid, 256, 0, s>>>(vol, padN, padT, d.nx, d.ny, need_n ? 1 : 0, need_t ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const int lp_max = (d.nx > d.ny ? d.nx : d.ny) + kLinePadL + kLinePadR;
+  if (d.nz >= 4 && lp_max <= kLdsBytes / (int)sizeof(Vec4<T>) && xray_lds_enabled()) {
+    const int gr = (n_row_angles + kProjAngles - 1) / kProjAngles;
+    const int gc = (n_angles - n_row_angles + kProjAngles - 1) / kProjAngles;
+    const long n_work = (long)(gr + gc) * ((d.nz + 3) / 4) * ((ns + 255) / 256);
+    const long grid = (n_work + 7) / 8 * 8;
+    project_lds_kernel<T><<<(unsigned)grid, 1024, 0, s>>>(padN, padT, g, ap, aorder, n_row_angles, n_angles, d.nx,
+                                                          d.ny, d.nz, ns, gr, gr + gc, (int)n_work);
+    return hipGetLastError();
+  }
   // one plane per thread, eight lines unrolled: measured at 256^3 / 256 angles,
   // sharing the crossings over 2 or 4 planes per thread was no faster (2x8) or
   // 16% slower (4x4; more planes in flight per compute unit, fewer cache hits)
@@ -284,6 +434,107 @@ backproject_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const AngleP
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two-tap backprojector with the detector rows staged in LDS.  A 1024-thread
+// work-group owns a 64 x 64 voxel tile in four consecutive planes; thread
+// (i, kk) accumulates voxels (i, kk + 16 v), v = 0..3, in the four planes.
+// Chunks of angles are staged into LDS with the four planes' rows interleaved
+// ([angle][padded bin] of 4-vectors), so the two taps of a voxel in all four
+// planes are two vector LDS reads; the bin position and weights are computed
+// once per voxel and angle.  Same arithmetic and order as backproject_kernel
+// (angles in order, two FMAs per plane).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024)
+backproject_lds_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const AngleParams *__restrict__ ap,
+                       int n_angles, int nx, int ny, int nz, int ns, const T *__restrict__ kap, int tiles_x,
+                       int tiles_y, int n_work)
+{
+  constexpr int NV = kLdsBytes / sizeof(Vec4<T>);
+  __shared__ Vec4<T> lds[NV];
+  const int b = blockIdx.x;
+  const int per_xcd = (n_work + 7) / 8;
+  const int tw = (b % 8) * per_xcd + b / 8;
+  if (tw >= n_work) return;                 // whole group exits together
+  const int bx = tw % tiles_x;
+  const int rest = tw / tiles_x;
+  const int by = rest % tiles_y;
+  const int z0 = (rest / tiles_y) * 4;
+  const int i = bx * 64 + (threadIdx.x & 63);
+  const int k0 = by * 64 + (threadIdx.x >> 6);
+  const int RS = ns + kRowPadL + kRowPadR;
+  const int AC = NV / RS;                   // angles per chunk
+
+  T acc[4][4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[v][q] = T(0);
+  const int zc[4] = {min(z0, nz - 1), min(z0 + 1, nz - 1), min(z0 + 2, nz - 1), min(z0 + 3, nz - 1)};
+  for (int a0 = 0; a0 < n_angles; a0 += AC) {
+    const int ac = min(AC, n_angles - a0);
+    __syncthreads();                        // the previous chunk has been read
+    for (int e = threadIdx.x; e < ac * RS; e += 1024) {
+      const int al = e / RS, jj = e - al * RS;
+      const size_t row = (size_t)(a0 + al) * nz;
+      lds[e] = Vec4<T>{gpad[(row + zc[0]) * RS + jj], gpad[(row + zc[1]) * RS + jj],
+                       gpad[(row + zc[2]) * RS + jj], gpad[(row + zc[3]) * RS + jj]};
+    }
+    __syncthreads();
+    for (int al = 0; al < ac; ++al) {
+      const AngleParams &P = ap[a0 + al];
+      const Vec4<T> *L = lds + al * RS;
+      if (sizeof(T) == 4) {
+        const long long T0 = P.b0_fix + (long long)i * P.bi_fix + (long long)k0 * P.bk_fix;
+        const long long BK16 = 16 * P.bk_fix;
+        const T ih = P.inv_hw_f, wa = P.w_f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const long long Tv = T0 + (long long)v * BK16;
+          const int j0 = min(max((int)(Tv >> 32), -2), ns + 1) + kRowPadL;
+          const T f = (T)(unsigned)(Tv & 0xffffffffLL) * T(2.3283064365386963e-10);
+          const T w0 = wa * fmax(T(1) - f * ih, T(0));
+          const T w1 = wa * fmax(T(1) - (T(1) - f) * ih, T(0));
+          const Vec4<T> v0 = L[j0], v1 = L[j0 + 1];
+          acc[v][0] = fma(w1, v1.x, fma(w0, v0.x, acc[v][0]));
+          acc[v][1] = fma(w1, v1.y, fma(w0, v0.y, acc[v][1]));
+          acc[v][2] = fma(w1, v1.z, fma(w0, v0.z, acc[v][2]));
+          acc[v][3] = fma(w1, v1.w, fma(w0, v0.w, acc[v][3]));
+        }
+      } else {
+        const T ih = (T)P.inv_hw, wa = (T)P.w;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double t = P.b0 + (double)i * P.bi + (double)(k0 + 16 * v) * P.bk;
+          const double fl = fmin(fmax(floor(t), -2.0), (double)(ns + 1));
+          const int j0 = (int)fl + kRowPadL;
+          const T f = (T)(t - fl);
+          // a clamped bin reads two pads, so the weights do not matter there
+          const T w0 = wa * fmax(T(1) - f * ih, T(0));
+          const T w1 = wa * fmax(T(1) - (T(1) - f) * ih, T(0));
+          const Vec4<T> v0 = L[j0], v1 = L[j0 + 1];
+          acc[v][0] = fma(w1, v1.x, fma(w0, v0.x, acc[v][0]));
+          acc[v][1] = fma(w1, v1.y, fma(w0, v0.y, acc[v][1]));
+          acc[v][2] = fma(w1, v1.z, fma(w0, v0.z, acc[v][2]));
+          acc[v][3] = fma(w1, v1.w, fma(w0, v0.w, acc[v][3]));
+        }
+      }
+    }
+  }
+  if (i >= nx) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int k = k0 + 16 * v;
+    if (k >= ny) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (z0 + q >= nz) continue;
+      const size_t idx = ((size_t)(z0 + q) * ny + k) * nx + i;
+      vol[idx] = kap ? acc[v][q] * kap[idx] : acc[v][q];
+    }
+  }
+}
+
 template <typename T, int ZP>
 static hipError_t backproject_dispatch(const Dims &d, int n_angles, int ns, const AngleParams *ap, bool two_tap,
                                        const T *gpad, T *vol, const T *kap, hipStream_t s)
@@ -304,6 +555,14 @@ template <typename T>
 hipError_t launch_backproject(const Dims &d, int n_angles, int ns, const AngleParams *ap, bool two_tap,
                               const T *gpad, T *vol, const T *kap, hipStream_t s)
 {
+  if (two_tap && d.nz >= 4 && ns + kRowPadL + kRowPadR <= kLdsBytes / (int)sizeof(Vec4<T>) && xray_lds_enabled()) {
+    const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + 63) / 64;
+    const long n_work = (long)tiles_x * tiles_y * ((d.nz + 3) / 4);
+    const long grid = (n_work + 7) / 8 * 8;
+    backproject_lds_kernel<T><<<(unsigned)grid, 1024, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns, kap,
+                                                              tiles_x, tiles_y, (int)n_work);
+    return hipGetLastError();
+  }
   switch (xray_planes(d.nz)) {
     case 8: return backproject_dispatch<T, 8>(d, n_angles, ns, ap, two_tap, gpad, vol, kap, s);
     case 4: return backproject_dispatch<T, 4>(d, n_angles, ns, ap, two_tap, gpad, vol, kap, s);
@@ -379,18 +638,101 @@ residual_ramp_kernel(const T *g, const T *__restrict__ G, const uint8_t *__restr
   }
 }
 
+// Rows of up to 2048 bins: several rows per 256-thread work-group, each row
+// in LDS with ns + 8 zeros on both sides so that every tap reads without a
+// bounds test; thread t of a row computes the 8 outputs j = t + m tpr (lanes
+// read consecutive LDS words).  Same residual, mask and FP64 partial as
+// residual_ramp_kernel; the partial of a row is summed in thread order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+residual_ramp8_kernel(const T *g, const T *__restrict__ G, const uint8_t *__restrict__ mask,
+                      const T *__restrict__ taps, T *y, int ns, int rows, int y_stride, int y_off,
+                      double *row_partials)
+{
+  extern __shared__ unsigned char smem_raw[];
+  T *lr = reinterpret_cast<T *>(smem_raw);
+  __shared__ double red[256];
+  const int tpr = (ns + 7) / 8;              // threads per row
+  const int rpb = 256 / tpr;                 // rows per work-group
+  const int P = ns + 8;                      // zeros on each side
+  const int W = 2 * P + ns;
+  const int rl = threadIdx.x / tpr, jt = threadIdx.x - rl * tpr;
+  const bool in_group = rl < rpb;
+  const size_t row = (size_t)blockIdx.x * rpb + (in_group ? rl : 0);
+  const bool act = in_group && row < (size_t)rows;
+  T *R = lr + (in_group ? rl : 0) * W;
+  if (in_group) {
+    const size_t base = row * (size_t)ns;
+    for (int e = jt; e < W; e += tpr) {
+      const int j = e - P;
+      T v = T(0);
+      if (act && j >= 0 && j < ns) {
+        v = g[base + j];
+        if (G) v -= G[base + j];
+        if (mask && !mask[base + j]) v = T(0);
+      }
+      R[e] = v;
+    }
+  }
+  __syncthreads();
+  const T *c = R + P + jt;                   // c[m tpr] = r_{jt + m tpr}
+  T acc[8];
+  if (taps) {
+    const T t0 = taps[0];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) acc[m] = t0 * c[m * tpr];
+    for (int n = 1; n < ns; n += 2) {
+      const T tn = taps[n];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) acc[m] = fma(tn, c[m * tpr - n] + c[m * tpr + n], acc[m]);
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) acc[m] = c[m * tpr];
+  }
+  double part = 0.0;
+  if (act) {
+    const size_t base = row * (size_t)ns;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int j = jt + m * tpr;
+      if (j >= ns) break;
+      T a = acc[m];
+      if (mask && !mask[base + j]) a = T(0);
+      y[row * (size_t)y_stride + y_off + j] = a;
+      part += (double)c[m * tpr] * (double)a;
+    }
+  }
+  if (!row_partials) return;
+  red[threadIdx.x] = part;
+  __syncthreads();
+  if (act && jt == 0) {
+    double sum = 0.0;
+    for (int q = 0; q < tpr; ++q) sum += red[threadIdx.x + q];
+    row_partials[row] = sum;
+  }
+}
+
 template <typename T>
 hipError_t launch_residual_ramp(int rows, int ns, const T *g, const T *G, const uint8_t *mask, const T *taps, T *y,
                                 int y_stride, int y_off, double *row_partials, hipStream_t s)
 {
+  if (ns <= 2048) {
+    const int tpr = (ns + 7) / 8, rpb = 256 / tpr;
+    const size_t shmem = (size_t)rpb * (3 * ns + 16) * sizeof(T);
+    const unsigned grid = (unsigned)((rows + rpb - 1) / rpb);
+    residual_ramp8_kernel<T><<<grid, 256, shmem, s>>>(g, G, mask, taps, y, ns, rows, y_stride, y_off,
+                                                      row_partials);
+    return hipGetLastError();
+  }
   const size_t shmem = (size_t)ns * sizeof(T);
   residual_ramp_kernel<T><<<rows, 256, shmem, s>>>(g, G, mask, taps, y, ns, y_stride, y_off, row_partials);
   return hipGetLastError();
 }
 
 #define FFPAT_INST(T)                                                                                         \
-  template hipError_t launch_project<T>(const Dims &, int, int, const AngleParams *, const T *, T *, T *, bool, \
-                                        bool, T *, hipStream_t);                                             \
+  template hipError_t launch_project<T>(const Dims &, int, int, const AngleParams *, const int *, int, const T *, \
+                                        T *, T *, bool, bool, T *, hipStream_t);                             \
   template hipError_t launch_backproject<T>(const Dims &, int, int, const AngleParams *, bool, const T *, T *, \
                                             const T *, hipStream_t);                                         \
   template hipError_t launch_pad_rows<T>(int, int, const T *, T *, hipStream_t);                             \

@@ -95,7 +95,7 @@ struct GraphCache {
 };
 
 struct Layout {
-  size_t kap, vol[6], dat, taps, ap, partials, scalars;
+  size_t kap, vol[6], dat, taps, ap, aorder, partials, scalars;
   size_t padN, padT, padD;              // zero-padded copies for the projector / backprojector
   size_t padN_bytes, padT_bytes, padD_bytes;
   size_t total;
@@ -125,6 +125,7 @@ struct ffpat_plan {
   bool two_tap = true;    // every footprint half-width m dx / ds <= 1 bin
   bool need_n = false;    // some angle marches rows (reads the padded plane)
   bool need_t = false;    // some angle marches columns (reads the padded transpose)
+  int n_row_angles = 0;   // angles that march rows (listed first in aorder)
   bool use_graphs = true; // replay captured graphs for the power iteration and FB iterations
   bool use_pairs = true;  // two leapfrog steps per pass where possible
   hipStream_t cap_stream = nullptr;
@@ -138,6 +139,7 @@ struct ffpat_plan {
   void *padT() const { return base + lay.padT; }
   void *padD() const { return base + lay.padD; }
   AngleParams *ap() const { return reinterpret_cast<AngleParams *>(base + lay.ap); }
+  int *aorder() const { return reinterpret_cast<int *>(base + lay.aorder); }
   double *partials() const { return reinterpret_cast<double *>(base + lay.partials); }
   double *scalars() const { return reinterpret_cast<double *>(base + lay.scalars); }
 };
@@ -207,6 +209,7 @@ Layout layout(const Resolved &r)
   L.dat = off; off = align_up(off + ndat * esz);
   L.taps = off; off = align_up(off + (size_t)r.ns * esz);
   L.ap = off; off = align_up(off + (size_t)r.n_angles * sizeof(AngleParams));
+  L.aorder = off; off = align_up(off + (size_t)r.n_angles * sizeof(int));
   L.n_partials = rows > (size_t)3 * kReduceBlocks ? rows : (size_t)3 * kReduceBlocks;
   L.partials = off; off = align_up(off + L.n_partials * sizeof(double));
   L.scalars = off; off = align_up(off + SC_COUNT * sizeof(double));
@@ -362,7 +365,8 @@ int wave_adjoint_op(ffpat_plan *P, const T *g, T *q, hipStream_t s)
 template <typename T>
 hipError_t project(ffpat_plan *P, const T *vol, T *g, hipStream_t s)
 {
-  return launch_project<T>(P->d, P->n_angles, P->ns, P->ap(), vol, static_cast<T *>(P->padN()),
+  return launch_project<T>(P->d, P->n_angles, P->ns, P->ap(), P->aorder(), P->n_row_angles, vol,
+                           static_cast<T *>(P->padN()),
                            static_cast<T *>(P->padT()), P->need_n, P->need_t, g, s);
 }
 
@@ -768,12 +772,20 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
   if (e != hipSuccess) return cleanup(hip_fail(e, "make_kappa"));
 
   std::vector<AngleParams> ap((size_t)r.n_angles);
+  std::vector<int> aorder;
+  aorder.reserve((size_t)r.n_angles);
   for (int a = 0; a < r.n_angles; ++a) {
     ap[(size_t)a] = angle_params(geom->angles[a], r);
     if (ap[(size_t)a].hw > 1.0) P->two_tap = false;
     if (ap[(size_t)a].major_x) P->need_t = true;
-    else P->need_n = true;
+    else {
+      P->need_n = true;
+      aorder.push_back(a);
+    }
   }
+  P->n_row_angles = (int)aorder.size();
+  for (int a = 0; a < r.n_angles; ++a)
+    if (ap[(size_t)a].major_x) aorder.push_back(a);
   // the pads of the padded copies stay zero for the life of the plan
   e = hipMemsetAsync(P->padN(), 0, P->lay.padN_bytes, s);
   if (e == hipSuccess) e = hipMemsetAsync(P->padT(), 0, P->lay.padT_bytes, s);
@@ -783,11 +795,13 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
     std::vector<double> t = ramp_taps<double>(r);
     e = hipMemcpyAsync(P->taps(), t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(P->ap(), ap.data(), ap.size() * sizeof(AngleParams), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->aorder(), aorder.data(), aorder.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   } else {
     std::vector<float> t = ramp_taps<float>(r);
     e = hipMemcpyAsync(P->taps(), t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(P->ap(), ap.data(), ap.size() * sizeof(AngleParams), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->aorder(), aorder.data(), aorder.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
   if (e != hipSuccess) return cleanup(hip_fail(e, "plan upload"));
