@@ -104,6 +104,35 @@ def test_project_backproject(oracle, shape, dtype, ds_ratio, ns_extra):
         assert rel_l2(bp, oracle.backproject(g, d)) <= TOL_X[dtype]
 
 
+LDS_LAYOUTS = {
+    # (nz, ny, nx), ns, angles
+    "wide": ((5, 40, 300), 301, np.linspace(0.0, math.pi, 9, endpoint=False) + 0.05),
+    "rows_only": ((6, 30, 50), 50, np.concatenate([np.linspace(0.0, 0.7, 6), np.linspace(2.45, 3.1, 5)])),
+    "cols_only": ((6, 30, 50), 50, np.linspace(0.9, 2.2, 11)),
+    "many_angles": ((7, 33, 35), 35, np.linspace(0.0, math.pi, 100, endpoint=False)),
+}
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("layout", sorted(LDS_LAYOUTS))
+def test_project_backproject_work_decompositions(oracle, dtype, layout):
+    """X and X^T where the staged kernels split the work unevenly: more than 256
+    bins (two bin blocks, lines longer than one LDS chunk), angle sets of one
+    orientation only, more than 32 angles per orientation, plane counts that
+    are not multiples of 4."""
+    shape, ns, angles = LDS_LAYOUTS[layout]
+    k = make_case(shape, 31, n_angles=len(angles), ns=ns)
+    k["angles"] = np.asarray(angles, dtype=np.float64)
+    g = oracle_geom(oracle, k)
+    v = rounded(k["h"], dtype)
+    d = rounded(k["rng"].standard_normal(g.data_shape), dtype)
+    with gpu_plan(k, dtype) as P:
+        gp = to_np(P.project(to_dev(v, dtype)))
+        assert rel_l2(gp, oracle.project(g, v)) <= TOL_X[dtype]
+        bp = to_np(P.backproject(to_dev(d, dtype)))
+        assert rel_l2(bp, oracle.backproject(g, d)) <= TOL_X[dtype]
+
+
 @pytest.mark.parametrize("dtype", [F64, F32])
 @pytest.mark.parametrize("ns", [1, 2, 48, 257, 700])
 def test_ramp(oracle, dtype, ns):
