@@ -67,6 +67,8 @@ hipError_t launch_wave_pair(const Dims &d, const T *pm1, const T *pk, T *q, T *o
 // Whether the two-step kernel is the faster choice for this grid and element size
 // (FFPAT_STENCIL_TB=0/1 in the environment overrides the rule).
 bool wave_pairs_preferred(const Dims &d, size_t esz);
+// Whether the two-step kernel can address a plane of this grid (plane bytes < 2^31).
+bool wave_pairs_fit(const Dims &d, size_t esz);
 
 // k' = (c dt)^2 / (12 dx^2) from c, and c range / finiteness into stats[0..2]
 // (min, max, count of non-finite or non-positive values) via block partials.

@@ -16,6 +16,8 @@
 //     registers, so every p(k) value is fetched from HBM about once.
 #include "kernels.h"
 
+#include <type_traits>
+
 #include <cfloat>
 #include <cstdlib>
 
@@ -218,15 +220,35 @@ wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__res
 // zs from zbeg - 2 to zend + 1; stage 2 follows two planes behind (z = zs - 2).
 // Every thread owns up to PPT points of the extended tile (64 + 4) x (BY + 4)
 // and keeps, per point, p(k) at zs-2..zs+2, q at zs-4..zs and k' at zs-2..zs in
-// registers (loads of the next plane are issued one plane ahead).  LDS holds
-// p(k) of plane zs with a 4-point halo (stage-1 x-y neighbours) and a ring of
-// three q planes with a 2-point halo (stage-2 x-y neighbours).  q is zero
-// outside the grid (the zero values outside).
+// registers; LDS holds p(k) of plane zs with a 4-point halo (stage-1 x-y
+// neighbours) and q of the last five planes with a 2-point halo (stage-2 x-y
+// neighbours).  Every ring slot is a plane index modulo 5 and the z loop is
+// unrolled five times, so the slots are fixed registers and LDS offsets (no
+// copies when the window moves).  The loads of plane zs + 1 are issued during
+// plane zs, unconditionally (clamped in-grid addresses, values masked where
+// used), so they stay in flight across the barrier; loads and stores address a
+// uniform plane base plus the lane's 32-bit byte offset (measured faster here
+// than buffer-resource addressing, which saves the 64-bit adds).  q is zero
+// outside the grid
+// (the zero values outside).
 // Inputs and outputs are four distinct buffers (neighbouring groups read the
-// inputs in their halos while this group writes).
+// inputs in their halos while this group writes).  Requires plane bytes < 2^31.
 // ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ldb(const T *base, unsigned boff)
+{
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
+}
+
+template <typename T>
+__device__ __forceinline__ void stb(T *base, unsigned boff, T v)
+{
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff) = v;
+}
+
 template <typename T, int NDIM, int RY, int NTH>
-__global__ void __launch_bounds__(NTH)
+// FP32 with 512 threads: at most 128 VGPRs, so two work-groups share a compute unit
+__global__ void __launch_bounds__(NTH, (sizeof(T) == 4 && NTH >= 512) ? 4 : 1)
 wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__restrict__ q_out,
                    T *__restrict__ o_out, const T *__restrict__ kap, int nx, int ny, int nz, int zchunk, int tiles_x,
                    int tiles_y, int n_tiles, int xy_fastest)
@@ -237,8 +259,9 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
   constexpr int NE = EX * EY;
   constexpr int PPT = (NE + NTH - 1) / NTH;
   constexpr int NRING = KX * KY - NE;        // outer 2-point ring of the p(k) plane
+  constexpr int RPT = (NRING + NTH - 1) / NTH;
   __shared__ T lk[KY * KX];
-  __shared__ T lq[3][EY * EX];
+  __shared__ T lq[5][EY * EX];
 
   const int b = blockIdx.x;
   const int per_xcd = (n_tiles + 7) / 8;
@@ -258,15 +281,15 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
   const int zbeg = zc * zchunk;
   const int zend = min(nz, zbeg + zchunk);
   const size_t plane = (size_t)nx * ny;
+  const int zstart = zbeg - 2;              // first stage-1 plane; ring slot of plane p: (p - zstart) mod 5
 
-  // Per point: its place in the extended tile, flags, and its offset within a
-  // plane, clamped into the grid so that every load below is in bounds (a point
-  // outside reads a neighbour's value and its flag zeroes it).  The plane base
-  // is uniform, so each load is one scalar base plus one 32-bit offset.
+  // Per point: its place in the extended tile, flags, and the byte offset of its
+  // position within a plane, clamped into the grid so that every load is in
+  // bounds (a point outside reads a neighbour's value and its flag zeroes it).
   int ex[PPT], ey[PPT];
-  unsigned off[PPT];
+  unsigned boff[PPT];
   bool ev[PPT], ing[PPT], inter[PPT];
-  T w[PPT][5], r1[PPT][5], kr[PPT][3];
+  T w[PPT][5], r1[PPT][5], kr[PPT][5];
 #pragma unroll
   for (int m = 0; m < PPT; ++m) {
     const int e = threadIdx.x + NTH * m;
@@ -276,25 +299,25 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
     const int gx = x0 - 2 + ex[m], gy = y0 - 2 + ey[m];
     ing[m] = ev[m] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     inter[m] = ing[m] && ex[m] >= 2 && ex[m] < EX - 2 && ey[m] >= 2 && ey[m] < EY - 2;
-    off[m] = (unsigned)(min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1));
+    boff[m] = (unsigned)((min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1)) * sizeof(T));
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int zq = zbeg - 4 + q;
+    for (int q = 0; q < 5; ++q) {
       w[m][q] = T(0);
-      if ((NDIM == 3 || q == 2) && zq >= 0 && zq < nz) {
-        const T v = pk[(size_t)zq * plane + off[m]];
-        w[m][q] = ing[m] ? v : T(0);
+      r1[m][q] = T(0);
+      kr[m][q] = T(0);
+    }
+    // 3D: p(k) at zstart-2..zstart+1 in slots 3, 4, 0, 1 (zstart + 2 arrives with the first plane)
+#pragma unroll
+    for (int d = -2; d <= 1; ++d) {
+      const int zq = zstart + d;
+      if (NDIM == 3 && zq >= 0 && zq < nz) {
+        const T v = ldb(pk + (size_t)zq * plane, boff[m]);
+        w[m][(d + 5) % 5] = ing[m] ? v : T(0);
       }
     }
-    w[m][4] = T(0);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) r1[m][q] = T(0);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) kr[m][q] = T(1);
   }
 
   // ring elements of the p(k) plane owned by this thread (fixed positions)
-  constexpr int RPT = (NRING + NTH - 1) / NTH;
   int rl[RPT];
   unsigned roff[RPT];
   bool rin[RPT];
@@ -319,44 +342,46 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
     rl[j] = rv ? lr * KX + lc : -1;
     const int gx = x0 - 4 + lc, gy = y0 - 4 + lr;
     rin[j] = rv && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    roff[j] = (unsigned)(min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1));
+    roff[j] = (unsigned)((min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1)) * sizeof(T));
   }
+
   // software pipeline: the loads of plane zs + 1 are issued during plane zs
   T nw[PPT], npv[PPT], nkv[PPT], nring[RPT];
-  // The loads are unconditional (plane index clamped too) and their values are
-  // masked only where they are used, one plane later, so that they stay in
-  // flight across the barrier and the arithmetic of the current plane.
   auto fetch = [&](int zf) {
-    const int zw = min(max(NDIM == 3 ? zf + 2 : zf, 0), nz - 1);
-    const int zc = min(max(zf, 0), nz - 1);
-    const T *bw = pk + (size_t)zw * plane, *bp = pm1 + (size_t)zc * plane, *bk = kap + (size_t)zc * plane;
-    const T *br = pk + (size_t)zc * plane;
+    const int zw = min(max(NDIM == 3 ? zf + 2 : zf, 0), nz - 1);   // p(k) plane entering the window
+    const int zc2 = min(max(zf, 0), nz - 1);
+    const T *bw = pk + (size_t)zw * plane, *bp = pm1 + (size_t)zc2 * plane, *bk = kap + (size_t)zc2 * plane;
+    const T *br = pk + (size_t)zc2 * plane;
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-      nw[m] = bw[off[m]];
-      npv[m] = bp[off[m]];
-      nkv[m] = bk[off[m]];
+      nw[m] = ldb(bw, boff[m]);
+      npv[m] = ldb(bp, boff[m]);
+      nkv[m] = ldb(bk, boff[m]);
     }
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) nring[j] = br[roff[j]];
+    for (int j = 0; j < RPT; ++j) nring[j] = ldb(br, roff[j]);
   };
-  fetch(zbeg - 2);
+  fetch(zstart);
 
-  for (int zs = zbeg - 2; zs < zend + 2; ++zs) {
+  // one stage-1 plane zs with ring phase P = (zs - zstart) mod 5; slot of plane zs + d: (P + d) mod 5
+  auto step = [&](auto phase, int zs) {
+    constexpr int P = decltype(phase)::value;
+    constexpr int Sm2 = (P + 3) % 5, Sm1 = (P + 4) % 5, S0 = P, Sp1 = (P + 1) % 5, Sp2 = (P + 2) % 5;
+    constexpr int Sm3 = (P + 2) % 5, Sm4 = (P + 1) % 5;
     const int z = zs - 2;
     const bool zs_in = zs >= 0 && zs < nz;
-    // stage-1 inputs of plane zs (fetched one plane ahead); p(k) and q are zero outside the grid
     const int zw = NDIM == 3 ? zs + 2 : zs;
     const bool zw_in = zw >= 0 && zw < nz;
+    // stage-1 inputs of plane zs (fetched one plane ahead)
     T pv[PPT], kv[PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
       const T v = (ing[m] && zw_in) ? nw[m] : T(0);
-      if (NDIM == 3) w[m][4] = v;
-      else w[m][2] = v;
+      if (NDIM == 3) w[m][Sp2] = v;
+      else w[m][S0] = v;
       pv[m] = npv[m];   // used only where the point and plane zs are inside the grid
       kv[m] = nkv[m];
-      if (ev[m]) lk[(ey[m] + 2) * KX + ex[m] + 2] = w[m][2];
+      if (ev[m]) lk[(ey[m] + 2) * KX + ex[m] + 2] = w[m][S0];
     }
 #pragma unroll
     for (int j = 0; j < RPT; ++j)
@@ -364,7 +389,8 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
     fetch(zs + 1);   // clamped: past the last plane it re-reads valid memory, unused
     __syncthreads();
     // stage 1: q(zs) on the extended tile
-    T *Lq = lq[(zs + 3) % 3];
+    T *q_pl = q_out + (size_t)min(max(zs, 0), nz - 1) * plane;
+    const bool zs_own = zs >= zbeg && zs < zend;
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
       if (!ev[m]) continue;
@@ -372,53 +398,50 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
       T s1 = (c[-1] + c[1]) + (c[-KX] + c[KX]);
       T s2 = (c[-2] + c[2]) + (c[-2 * KX] + c[2 * KX]);
       if (NDIM == 3) {
-        s1 += w[m][1] + w[m][3];
-        s2 += w[m][0] + w[m][4];
+        s1 += w[m][Sm1] + w[m][Sp1];
+        s2 += w[m][Sm2] + w[m][Sp2];
       }
-      const T c0 = w[m][2];
+      const T c0 = w[m][S0];
       const T S = T(16) * s1 - s2 - T(NDIM == 3 ? 90 : 60) * c0;
       const T q = (ing[m] && zs_in) ? T(2) * c0 - pv[m] + kv[m] * S : T(0);
-      Lq[ey[m] * EX + ex[m]] = q;
-      r1[m][4] = q;
-      kr[m][2] = kv[m];
-      if (inter[m] && zs >= zbeg && zs < zend) q_out[(size_t)zs * plane + off[m]] = q;
+      lq[S0][ey[m] * EX + ex[m]] = q;
+      r1[m][S0] = q;
+      kr[m][S0] = kv[m];
+      if (inter[m] && zs_own) stb(q_pl, boff[m], q);   // the point's own plane in its own chunk
     }
     __syncthreads();
-    // stage 2: o(z) on the tile, z = zs - 2
+    // stage 2: o(z) on the tile, z = zs - 2: q(z) x-y neighbours from LDS, z neighbours
+    // (planes z-2..z+2 = zs-4..zs) from registers
     if (z >= zbeg) {
-      const T *Q = lq[(z + 3) % 3];
+      T *o_pl = o_out + (size_t)z * plane;
 #pragma unroll
       for (int m = 0; m < PPT; ++m) {
         if (!inter[m]) continue;
-        const T *c = &Q[ey[m] * EX + ex[m]];
+        const T *c = &lq[Sm2][ey[m] * EX + ex[m]];
         T s1 = (c[-1] + c[1]) + (c[-EX] + c[EX]);
         T s2 = (c[-2] + c[2]) + (c[-2 * EX] + c[2 * EX]);
         if (NDIM == 3) {
-          s1 += r1[m][1] + r1[m][3];
-          s2 += r1[m][0] + r1[m][4];
+          s1 += r1[m][Sm3] + r1[m][Sm1];
+          s2 += r1[m][Sm4] + r1[m][S0];
         }
-        const T c0 = r1[m][2];
+        const T c0 = r1[m][Sm2];
         const T S = T(16) * s1 - s2 - T(NDIM == 3 ? 90 : 60) * c0;
-        // p(k) at z: w[m][0] in 3D (the ring is at zs-2..zs+2); in 2D the ring holds only zs
-        const T pkz = NDIM == 3 ? w[m][0] : pk[(size_t)z * plane + off[m]];
-        o_out[(size_t)z * plane + off[m]] = T(2) * c0 - pkz + kr[m][0] * S;
+        stb(o_pl, boff[m], T(2) * c0 - w[m][Sm2] + kr[m][Sm2] * S);
       }
     }
-#pragma unroll
-    for (int m = 0; m < PPT; ++m) {
-      if (NDIM == 3) {
-        w[m][0] = w[m][1];
-        w[m][1] = w[m][2];
-        w[m][2] = w[m][3];
-        w[m][3] = w[m][4];
-      }
-      r1[m][0] = r1[m][1];
-      r1[m][1] = r1[m][2];
-      r1[m][2] = r1[m][3];
-      r1[m][3] = r1[m][4];
-      kr[m][0] = kr[m][1];
-      kr[m][1] = kr[m][2];
-    }
+  };
+
+  const int zlast = zend + 1;               // last stage-1 plane
+  for (int zb = zstart; zb <= zlast; zb += 5) {
+    step(std::integral_constant<int, 0>{}, zb);
+    if (zb + 1 > zlast) break;
+    step(std::integral_constant<int, 1>{}, zb + 1);
+    if (zb + 2 > zlast) break;
+    step(std::integral_constant<int, 2>{}, zb + 2);
+    if (zb + 3 > zlast) break;
+    step(std::integral_constant<int, 3>{}, zb + 3);
+    if (zb + 4 > zlast) break;
+    step(std::integral_constant<int, 4>{}, zb + 4);
   }
 }
 
@@ -568,9 +591,15 @@ bool wave_pairs_preferred(const Dims &d, size_t esz)
     return e ? (atoi(e) != 0 ? 1 : 0) : -1;
   }();
   if (env >= 0) return env == 1;
-  // measured on MI355X: FP64 at 128^3..384^3 runs 11-22% faster per step with two
-  // steps per pass; FP32 ties up to 256^3 and gains from 384^3 on
-  return esz == 8 || d.nvox() > (size_t)256 * 256 * 256;
+  // measured on MI355X, us per step one / two steps per pass: FP32 128^3 10.6 / 9.6,
+  // 256^3 49.7 / 47.8, 384^3 198 / 164; FP64 128^3 16.2 / 14.0, 256^3 111 / 76.5,
+  // 384^3 391 / 298.  Smaller FP32 grids keep one step per pass.
+  return esz == 8 || d.nvox() >= (size_t)128 * 128 * 128;
+}
+
+bool wave_pairs_fit(const Dims &d, size_t esz)
+{
+  return (size_t)d.nx * d.ny * esz < ((size_t)1 << 31);
 }
 
 template <typename T>

@@ -727,7 +727,7 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
   P->flags = r.flags;
   P->stencil = (r.flags & FFPAT_PLAN_NAIVE_STENCIL) ? STENCIL_NAIVE : STENCIL_BLOCKED;
   P->use_graphs = !(r.flags & FFPAT_PLAN_NO_GRAPHS);
-  P->use_pairs = P->stencil == STENCIL_BLOCKED &&
+  P->use_pairs = P->stencil == STENCIL_BLOCKED && wave_pairs_fit(r.d, r.dtype == FFPAT_F64 ? 8 : 4) &&
                  ((r.flags & FFPAT_PLAN_TWO_STEP) ||
                   (!(r.flags & FFPAT_PLAN_SINGLE_STEP) && wave_pairs_preferred(r.d, r.dtype == FFPAT_F64 ? 8 : 4)));
   P->nvox = r.d.nvox();
