@@ -223,10 +223,11 @@ wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__res
 // registers; LDS holds p(k) of plane zs with a 4-point halo (stage-1 x-y
 // neighbours) and q of the last five planes with a 2-point halo (stage-2 x-y
 // neighbours).  Every ring slot is a plane index modulo 5 and the z loop is
-// unrolled five times, so the slots are fixed registers and LDS offsets (no
-// copies when the window moves).  The loads of plane zs + 1 are issued during
-// plane zs, unconditionally (clamped in-grid addresses, values masked where
-// used), so they stay in flight across the barrier; loads and stores address a
+// unrolled ten times, so the slots are fixed registers and LDS offsets (no
+// copies when the window moves).  The loads of plane zs + 2 are issued during
+// plane zs (two buffer sets, alternating), unconditionally (clamped in-grid
+// addresses, values masked where used), so they stay in flight across two
+// barriers; loads and stores address a
 // uniform plane base plus the lane's 32-bit byte offset (measured faster here
 // than buffer-resource addressing, which saves the 64-bit adds).  q is zero
 // outside the grid
@@ -257,11 +258,14 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
   constexpr int EX = BX + 4, EY = BY + 4;   // extended tile: stage-1 output region
   constexpr int KX = BX + 8, KY = BY + 8;   // p(k) plane in LDS: stage-1 input region
   constexpr int NE = EX * EY;
-  constexpr int PPT = (NE + NTH - 1) / NTH;
+  // threads walk the extended tile with the LDS row pitch KX (the last 4 slots of a
+  // row idle), so consecutive lanes address consecutive LDS words across row ends
+  constexpr int NES = KX * EY;
+  constexpr int PPT = (NES + NTH - 1) / NTH;
   constexpr int NRING = KX * KY - NE;        // outer 2-point ring of the p(k) plane
   constexpr int RPT = (NRING + NTH - 1) / NTH;
   __shared__ T lk[KY * KX];
-  __shared__ T lq[5][EY * EX];
+  __shared__ T lq[5][EY * KX];   // q planes, row pitch KX
 
   const int b = blockIdx.x;
   const int per_xcd = (n_tiles + 7) / 8;
@@ -293,9 +297,9 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
 #pragma unroll
   for (int m = 0; m < PPT; ++m) {
     const int e = threadIdx.x + NTH * m;
-    ev[m] = e < NE;
-    ey[m] = ev[m] ? e / EX : 0;
-    ex[m] = ev[m] ? e - ey[m] * EX : 0;
+    ey[m] = e < NES ? e / KX : 0;
+    ex[m] = e < NES ? e - ey[m] * KX : 0;
+    ev[m] = e < NES && ex[m] < EX;
     const int gx = x0 - 2 + ex[m], gy = y0 - 2 + ey[m];
     ing[m] = ev[m] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     inter[m] = ing[m] && ex[m] >= 2 && ex[m] < EX - 2 && ey[m] >= 2 && ey[m] < EY - 2;
@@ -345,27 +349,32 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
     roff[j] = (unsigned)((min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1)) * sizeof(T));
   }
 
-  // software pipeline: the loads of plane zs + 1 are issued during plane zs
-  T nw[PPT], npv[PPT], nkv[PPT], nring[RPT];
-  auto fetch = [&](int zf) {
+  // software pipeline: the loads of plane zs + 2 are issued during plane zs, into
+  // the buffer set that plane zs has just been consumed from (sets alternate)
+  T nw[2][PPT], npv[2][PPT], nkv[2][PPT], nring[2][RPT];
+  auto fetch = [&](auto buf, int zf) {
+    constexpr int B = decltype(buf)::value;
     const int zw = min(max(NDIM == 3 ? zf + 2 : zf, 0), nz - 1);   // p(k) plane entering the window
     const int zc2 = min(max(zf, 0), nz - 1);
     const T *bw = pk + (size_t)zw * plane, *bp = pm1 + (size_t)zc2 * plane, *bk = kap + (size_t)zc2 * plane;
     const T *br = pk + (size_t)zc2 * plane;
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-      nw[m] = ldb(bw, boff[m]);
-      npv[m] = ldb(bp, boff[m]);
-      nkv[m] = ldb(bk, boff[m]);
+      nw[B][m] = ldb(bw, boff[m]);
+      npv[B][m] = ldb(bp, boff[m]);
+      nkv[B][m] = ldb(bk, boff[m]);
     }
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) nring[j] = ldb(br, roff[j]);
+    for (int j = 0; j < RPT; ++j) nring[B][j] = ldb(br, roff[j]);
   };
-  fetch(zstart);
+  fetch(std::integral_constant<int, 0>{}, zstart);
+  fetch(std::integral_constant<int, 1>{}, zstart + 1);
 
-  // one stage-1 plane zs with ring phase P = (zs - zstart) mod 5; slot of plane zs + d: (P + d) mod 5
+  // one stage-1 plane zs with phase Q = (zs - zstart) mod 10: window slot of plane zs + d is
+  // (P + d) mod 5 with P = Q mod 5, the plane's loads sit in buffer set Q mod 2
   auto step = [&](auto phase, int zs) {
-    constexpr int P = decltype(phase)::value;
+    constexpr int Q = decltype(phase)::value;
+    constexpr int P = Q % 5, B = Q % 2;
     constexpr int Sm2 = (P + 3) % 5, Sm1 = (P + 4) % 5, S0 = P, Sp1 = (P + 1) % 5, Sp2 = (P + 2) % 5;
     constexpr int Sm3 = (P + 2) % 5, Sm4 = (P + 1) % 5;
     const int z = zs - 2;
@@ -376,17 +385,17 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
     T pv[PPT], kv[PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-      const T v = (ing[m] && zw_in) ? nw[m] : T(0);
+      const T v = (ing[m] && zw_in) ? nw[B][m] : T(0);
       if (NDIM == 3) w[m][Sp2] = v;
       else w[m][S0] = v;
-      pv[m] = npv[m];   // used only where the point and plane zs are inside the grid
-      kv[m] = nkv[m];
+      pv[m] = npv[B][m];   // used only where the point and plane zs are inside the grid
+      kv[m] = nkv[B][m];
       if (ev[m]) lk[(ey[m] + 2) * KX + ex[m] + 2] = w[m][S0];
     }
 #pragma unroll
     for (int j = 0; j < RPT; ++j)
-      if (rl[j] >= 0) lk[rl[j]] = (rin[j] && zs_in) ? nring[j] : T(0);
-    fetch(zs + 1);   // clamped: past the last plane it re-reads valid memory, unused
+      if (rl[j] >= 0) lk[rl[j]] = (rin[j] && zs_in) ? nring[B][j] : T(0);
+    fetch(std::integral_constant<int, B>{}, zs + 2);   // clamped: past the last plane it re-reads valid memory, unused
     __syncthreads();
     // stage 1: q(zs) on the extended tile
     T *q_pl = q_out + (size_t)min(max(zs, 0), nz - 1) * plane;
@@ -404,7 +413,7 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
       const T c0 = w[m][S0];
       const T S = T(16) * s1 - s2 - T(NDIM == 3 ? 90 : 60) * c0;
       const T q = (ing[m] && zs_in) ? T(2) * c0 - pv[m] + kv[m] * S : T(0);
-      lq[S0][ey[m] * EX + ex[m]] = q;
+      lq[S0][ey[m] * KX + ex[m]] = q;
       r1[m][S0] = q;
       kr[m][S0] = kv[m];
       if (inter[m] && zs_own) stb(q_pl, boff[m], q);   // the point's own plane in its own chunk
@@ -417,9 +426,9 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
 #pragma unroll
       for (int m = 0; m < PPT; ++m) {
         if (!inter[m]) continue;
-        const T *c = &lq[Sm2][ey[m] * EX + ex[m]];
-        T s1 = (c[-1] + c[1]) + (c[-EX] + c[EX]);
-        T s2 = (c[-2] + c[2]) + (c[-2 * EX] + c[2 * EX]);
+        const T *c = &lq[Sm2][ey[m] * KX + ex[m]];
+        T s1 = (c[-1] + c[1]) + (c[-KX] + c[KX]);
+        T s2 = (c[-2] + c[2]) + (c[-2 * KX] + c[2 * KX]);
         if (NDIM == 3) {
           s1 += r1[m][Sm3] + r1[m][Sm1];
           s2 += r1[m][Sm4] + r1[m][S0];
@@ -432,7 +441,7 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
   };
 
   const int zlast = zend + 1;               // last stage-1 plane
-  for (int zb = zstart; zb <= zlast; zb += 5) {
+  for (int zb = zstart; zb <= zlast; zb += 10) {
     step(std::integral_constant<int, 0>{}, zb);
     if (zb + 1 > zlast) break;
     step(std::integral_constant<int, 1>{}, zb + 1);
@@ -442,6 +451,16 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
     step(std::integral_constant<int, 3>{}, zb + 3);
     if (zb + 4 > zlast) break;
     step(std::integral_constant<int, 4>{}, zb + 4);
+    if (zb + 5 > zlast) break;
+    step(std::integral_constant<int, 5>{}, zb + 5);
+    if (zb + 6 > zlast) break;
+    step(std::integral_constant<int, 6>{}, zb + 6);
+    if (zb + 7 > zlast) break;
+    step(std::integral_constant<int, 7>{}, zb + 7);
+    if (zb + 8 > zlast) break;
+    step(std::integral_constant<int, 8>{}, zb + 8);
+    if (zb + 9 > zlast) break;
+    step(std::integral_constant<int, 9>{}, zb + 9);
   }
 }
 
