@@ -356,9 +356,20 @@ def cpu_baseline(case, G, step):
     oracle.fb(g, case.c, G_np, case.lam, step=step, n_iter=1, flags=oracle.POSITIVITY | oracle.PRECOND)
     t = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the oracle's own wave-solve rate, on a bounded sample: one W_T of the 128^3 grid
+    # (same dx rule, T and sound-speed recipe)
+    import synth
+    small = synth.make_case("c128", 2001)
+    gs = oracle.Geometry(nx=small.n, ny=small.n, nz=small.n, dx=small.dx, T=small.T, angles=small.angles)
+    nt_small = oracle.plan_info(gs, small.c)[0]
+    t1 = time.perf_counter()
+    oracle.wave(gs, small.c, small.h_true)
+    tw = time.perf_counter() - t1
     return {"value": 1.0 / t, "unit": "FB iter/s", "cores": cores, "kind": "oracle",
             "sample": f"one full FB iteration of the {n}^3 / {len(case.angles)}-angle workload in FP64 "
-                      f"({t:.1f} s: 2 wave solves, X, Lambda, X^T, prox)"}
+                      f"({t:.1f} s: 2 wave solves, X, Lambda, X^T, prox)",
+            "oracle_wave_gpt_updates_per_s": small.n ** 3 * nt_small / tw / 1e9,
+            "oracle_wave_sample": f"one W_T of the 128^3 grid, n_t = {nt_small} ({tw:.2f} s)"}
 
 
 def stored_traffic(kernel, recipe, dtype_name):

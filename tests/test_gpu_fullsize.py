@@ -87,6 +87,31 @@ def test_c256_autograd_gradient_crop_and_fd(c256):
         assert _fd_check(P, h.detach(), d, 16, 1e-3, 11) <= 1e-3
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_c48_reconstruction_end_to_end(oracle, dtype):
+    """48^3 / 48 angles / T = 0.5 / 1% noise / 5 iterations of Algorithm 8 with the
+    20-step power iteration: data simulation, step size and iterates by the oracle,
+    live (a second or two on the host), against the GPU in FP64 and FP32."""
+    import time
+    import paper_1901_06503_amd as ff
+    import synth
+    mg = _golden_mod()
+    case = mg.as_f32_values(synth.make_case("c48_f64", 1001))
+    g = mg.geometry(case)
+    t0 = time.perf_counter()
+    G = mg.simulate(case, g)
+    h_ref, obj_ref, s_ref = oracle.fb(g, case.c, G, case.lam, step=0.0, n_iter=case.n_iter, n_power=case.n_power,
+                                      flags=oracle.POSITIVITY | oracle.PRECOND)
+    print(f"[fullsize] 48^3 oracle end to end {time.perf_counter() - t0:.2f} s, {dtype}", flush=True)
+    with ff.Plan(to_dev(case.c, dtype), case.dx, case.T, case.angles) as P:
+        assert P.nt == oracle.plan_info(g, case.c)[0]
+        res = P.reconstruct(to_dev(G, dtype), case.lam, case.n_iter, step=0.0, n_power=case.n_power)
+    tol = 1e-10 if dtype == torch.float64 else 1e-4
+    assert res.step == pytest.approx(s_ref, rel=tol)
+    assert rel_l2(to_np(res.h), h_ref) <= tol
+    assert np.allclose(res.objective, obj_ref, rtol=tol, atol=0)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_c128_reconstruction_100_iterations(oracle, dtype):
     import paper_1901_06503_amd as ff
