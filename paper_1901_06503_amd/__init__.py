@@ -69,6 +69,13 @@ class Plan:
 
     c: sound speed c(x) > 0 as a contiguous [nz][ny][nx] device tensor; its
     dtype (float32 or float64) sets the precision of every field.
+    dx, T, angles, ns, ds, cfl, ndim: the geometry of ffpat_geom (ns = 0: nx bins,
+    ds = 0: dx; ndim = 2: the z-invariant mode, every plane its own 2D problem).
+    naive_stencil: the unblocked leapfrog kernel (for comparison).
+    use_graphs: replay captured graphs in fb_enqueue / reconstruct.
+    two_step_stencil: None lets the plan choose one or two leapfrog steps per
+    stencil pass; True / False force two / one (FFPAT_PLAN_TWO_STEP / _SINGLE_STEP).
+    stream: torch stream (or None: the current one) for the plan's set-up.
     """
 
     def __init__(self, c, dx, T, angles, ns=0, ds=0.0, cfl=0.3, ndim=3, naive_stencil=False, use_graphs=True,
