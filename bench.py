@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--concurrency", type=int, default=2,
                     help="--mode serve, policy shortest: jobs advancing at a time")
     ap.add_argument("--serial", type=int, default=1, help="--mode serve: also run the serial baseline (1/0)")
+    ap.add_argument("--serve-jobs", type=int, default=40,
+                    help="--mode fb: jobs in the short serving leg (p50/p99 latency, 4 jobs/s); 0 skips it")
     return ap.parse_args()
 
 
@@ -171,48 +173,50 @@ def run_serve(args):
     """Serving workload: Poisson arrivals, grids uniform over {64,128,192,256}^3,
     angles = grid edge, 50 FB iterations + 20 power steps each, FP32.  Runs the
     same trace through the serial baseline and the continuous-batching scheduler."""
+    print(json.dumps(serve_summary(args.jobs, args.rate, args.iters or 50, args.slots, args.concurrency,
+                                   args.policy, args.fill_voxels, args.serial, args.seed)), flush=True)
+
+
+def serve_summary(n_jobs, rate, iters, slots, concurrency, policy, fill_voxels, serial, seed):
     import numpy as np
     import torch
     import paper_1901_06503_amd as ff
     from paper_1901_06503_amd import serving
     import synth
-    rng = np.random.default_rng(args.seed)
-    sizes = rng.choice([64, 128, 192, 256], size=args.jobs)
-    gaps = rng.exponential(1.0 / args.rate, size=args.jobs)
+    rng = np.random.default_rng(seed)
+    sizes = rng.choice([64, 128, 192, 256], size=n_jobs)
+    gaps = rng.exponential(1.0 / rate, size=n_jobs)
     arrivals = np.cumsum(gaps) - gaps[0]
     jobs = []
     for i, (n, t) in enumerate(zip(sizes, arrivals)):
-        dx, angles, c, h = synth.torch_case(int(n), int(n), args.seed * 1000 + i)
+        dx, angles, c, h = synth.torch_case(int(n), int(n), seed * 1000 + i)
         with ff.Plan(c, dx, 0.5, angles) as P:
             g = P.forward(h)
             noise = torch.from_numpy(rng.standard_normal(P.data_shape)).to(g.device, g.dtype)
             G = g + 0.02 * float(g.double().mean()) * noise
         torch.cuda.synchronize()
         jobs.append(serving.Job(job_id=i, arrival=float(t), c=c.cpu().pin_memory(), G=G.cpu().pin_memory(), dx=dx,
-                                T=0.5, angles=angles, lam=1e-3, n_iter=args.iters or 50, n_power=20))
+                                T=0.5, angles=angles, lam=1e-3, n_iter=iters, n_power=20))
         if (i + 1) % 20 == 0:
-            log(f"trace: {i + 1}/{args.jobs} jobs generated")
+            log(f"trace: {i + 1}/{n_jobs} jobs generated")
     clone = lambda: [serving.Job(job_id=j.job_id, arrival=j.arrival, c=j.c, G=j.G, dx=j.dx, T=j.T,
                                  angles=j.angles, lam=j.lam, n_iter=j.n_iter, n_power=j.n_power) for j in jobs]
     base = None
-    if args.serial:
+    if serial:
         log("serial baseline")
         base = serving.summary(serving.run_serial(clone()))
         log(f"serial: {base}")
     free, total = torch.cuda.mem_get_info()
-    sched = serving.Scheduler(hbm_budget=int(0.5 * free), max_active=args.slots, iters_per_turn=5,
-                              concurrency=args.concurrency, policy=args.policy, fill_voxels=args.fill_voxels)
+    sched = serving.Scheduler(hbm_budget=int(0.5 * free), max_active=slots, iters_per_turn=5,
+                              concurrency=concurrency, policy=policy, fill_voxels=fill_voxels)
     log("continuous batching")
     mixed_jobs = sched.run(clone())
     mixed = serving.summary(mixed_jobs)
     log(f"scheduler: {mixed}")
-    print(json.dumps({"mode": "serve", "jobs": args.jobs, "rate_per_s": args.rate, "iters": args.iters or 50,
-                      "slots": args.slots, "policy": args.policy, "fill_voxels": args.fill_voxels,
-                      "concurrency": args.concurrency, "serial": base,
-                      "continuous_batching": mixed, "peak_active": sched.peak_active,
-                      "peak_running": sched.peak_running, "peak_bytes": sched.peak_bytes,
-                      "throughput_gain": mixed["jobs_per_s"] / base["jobs_per_s"] if base else None}),
-          flush=True)
+    return {"mode": "serve", "jobs": n_jobs, "rate_per_s": rate, "iters": iters, "slots": slots, "policy": policy,
+            "fill_voxels": fill_voxels, "concurrency": concurrency, "serial": base, "continuous_batching": mixed,
+            "peak_active": sched.peak_active, "peak_running": sched.peak_running, "peak_bytes": sched.peak_bytes,
+            "throughput_gain": mixed["jobs_per_s"] / base["jobs_per_s"] if base else None}
 
 
 def run_wave_only(args):
@@ -448,6 +452,22 @@ def main():
         log(f"cpu baseline {cpu}")
     traffic = stored_traffic(roof["kernel"], args.recipe, args.dtype)
 
+    serve = None
+    if args.serve_jobs > 0:
+        log(f"serving leg: {args.serve_jobs} jobs at 4 jobs/s")
+        try:
+            sv = serve_summary(args.serve_jobs, 4.0, 50, args.slots, args.concurrency, args.policy,
+                               args.fill_voxels, 1, args.seed)
+            cb, se = sv["continuous_batching"], sv["serial"]
+            serve = {"trace": f"{args.serve_jobs} jobs, Poisson 4 jobs/s, grids 64^3..256^3, 50 FB iterations each, "
+                              f"FP32, policy {args.policy}",
+                     "latency_p50_s": cb["latency_p50_s"], "latency_p99_s": cb["latency_p99_s"],
+                     "jobs_per_s": cb["jobs_per_s"], "serial_latency_p50_s": se["latency_p50_s"],
+                     "serial_latency_p99_s": se["latency_p99_s"], "serial_jobs_per_s": se["jobs_per_s"]}
+        except Exception as e:          # the serving leg never costs the benchmark line
+            serve = {"error": f"{type(e).__name__}: {e}"}
+        log(f"serving {serve}")
+
     line = {
         "metric": METRIC,
         "value": args.steps / t,
@@ -473,6 +493,7 @@ def main():
                      "kernel": roof["kernel"], "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": t_launch * 1e6},
         "cpu_baseline": cpu,
+        "serving": serve,
         "objective_last": float(out.objective[-1]) if len(out.objective) else None,
     }
     print(json.dumps(line), flush=True)
