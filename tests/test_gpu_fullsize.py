@@ -88,6 +88,29 @@ def test_c256_autograd_gradient_crop_and_fd(c256):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_c384_full_size_adjoint_dot_test(dtype):
+    """384^3 / 360 angles / T = 0.6 at full size, in the kernels the plan picks (two
+    leapfrog steps per pass, staged X and X^T): <A h, g> = <h, A^T g> for random h
+    and g (a property of the exact discrete transpose that holds at any size)."""
+    import paper_1901_06503_amd as ff
+    import synth
+    case = synth.make_case("c384", 4001)
+    print(f"[fullsize] 384^3 dot test {dtype}", flush=True)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    with ff.Plan(to_dev(case.c, dtype), case.dx, case.T, case.angles) as P:
+        assert P.steps_per_pass == 2
+        h = torch.randn(P.shape, dtype=dtype, device="cuda", generator=gen)
+        g = torch.randn(P.data_shape, dtype=dtype, device="cuda", generator=gen)
+        Ah = P.forward(h)
+        ATg = P.adjoint(g)
+        lhs = float(torch.dot(Ah.double().flatten(), g.double().flatten()))
+        rhs = float(torch.dot(h.double().flatten(), ATg.double().flatten()))
+        scale = float(Ah.double().norm() * g.double().norm())
+    tol = 1e-12 if dtype == torch.float64 else 2e-5
+    assert abs(lhs - rhs) <= tol * scale
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_c48_reconstruction_end_to_end(oracle, dtype):
     """48^3 / 48 angles / T = 0.5 / 1% noise / 5 iterations of Algorithm 8 with the
     20-step power iteration: data simulation, step size and iterates by the oracle,
