@@ -150,43 +150,43 @@ project_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Projector with the planes staged in LDS.  A 1024-thread work-group owns four
-// consecutive planes, one orientation (rays marching rows read the padded
-// planes, rays marching columns the padded transposes), 32 angles of that
-// orientation and 256 detector bins; thread (bin j, quarter s) marches the rays
+// Projector with the planes staged in LDS.  A 1024-thread work-group owns ZP
+// consecutive planes (the launch uses 4), one orientation (rays marching rows
+// read the padded planes, rays marching columns the padded transposes), 32
+// angles of that orientation and 256 detector bins; thread (bin j, quarter s) marches the rays
 // of angles 8s..8s+7.  The marched lines are staged chunk by chunk into LDS
-// with the four planes interleaved ([line][position] of 4-vectors), so the two
-// taps of a crossing in all four planes are two vector LDS reads and the
-// crossing's position and weights serve four planes.  Every ray visits every
+// with the ZP planes interleaved ([line][position] of ZP-vectors), so the two
+// taps of a crossing in all ZP planes are a few vector LDS reads and the
+// crossing's position and weights serve ZP planes.  Every ray visits every
 // line: the tap index is clamped into the three zero pads on each side, where
 // both taps are zero exactly when the crossing misses the line (the same sums
 // as marching only the crossed lines).  Positions: exact 32.32 fixed point in
 // FP32, double arithmetic in FP64 (as in project_kernel).
 // ---------------------------------------------------------------------------
-template <typename T>
-struct alignas(4 * sizeof(T)) Vec4 {
-  T x, y, z, w;
+template <typename T, int ZP>
+struct alignas(ZP * sizeof(T) >= 16 ? 16 : ZP * sizeof(T)) VecZ {
+  T v[ZP];
 };
 
 constexpr int kLdsBytes = 139264;   // 136 KiB per work-group (one work-group per compute unit)
 constexpr int kProjAngles = 32, kProjAnglesPerThread = 8;
 
-template <typename T>
+template <typename T, int ZP>
 __global__ void __launch_bounds__(1024)
 project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__restrict__ g,
                    const AngleParams *__restrict__ ap, const int *__restrict__ aorder, int n_row_angles,
                    int n_angles, int nx, int ny, int nz, int ns, int n_groups_rows, int n_groups, int n_work)
 {
-  constexpr int NV = kLdsBytes / sizeof(Vec4<T>);
-  __shared__ Vec4<T> lds[NV];
+  constexpr int NV = kLdsBytes / sizeof(VecZ<T, ZP>);
+  __shared__ VecZ<T, ZP> lds[NV];
   const int b = blockIdx.x;
   const int per_xcd = (n_work + 7) / 8;
   const int t = (b % 8) * per_xcd + b / 8;
   if (t >= n_work) return;                  // whole group exits together
-  const int nzg = (nz + 3) / 4;
+  const int nzg = (nz + ZP - 1) / ZP;
   const int grp = t % n_groups;
   const int rest = t / n_groups;
-  const int z0 = (rest % nzg) * 4;
+  const int z0 = (rest % nzg) * ZP;
   const int jb = rest / nzg;
   const bool rows = grp < n_groups_rows;
   const int gi = rows ? grp : grp - n_groups_rows;
@@ -202,7 +202,7 @@ project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__
   // per lane: the rays' positions at line 0 (FP32: fixed point; FP64: A = u0 + j uj)
   long long U[kProjAnglesPerThread];
   double A[kProjAnglesPerThread];
-  T acc[kProjAnglesPerThread][4];
+  T acc[kProjAnglesPerThread][ZP];
 #pragma unroll
   for (int m = 0; m < kProjAnglesPerThread; ++m) {
     const int ia = gi * kProjAngles + quarter * kProjAnglesPerThread + m;
@@ -214,19 +214,24 @@ project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__
       if (sizeof(T) == 4) U[m] = llrint(A[m] * 4294967296.0);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[m][q] = T(0);
+    for (int q = 0; q < ZP; ++q) acc[m][q] = T(0);
   }
   const size_t pl = (size_t)nr * LP;
-  const T *s0 = src + (size_t)min(z0, nz - 1) * pl, *s1 = src + (size_t)min(z0 + 1, nz - 1) * pl;
-  const T *s2 = src + (size_t)min(z0 + 2, nz - 1) * pl, *s3 = src + (size_t)min(z0 + 3, nz - 1) * pl;
+  const T *sp[ZP];   // the group's planes (past the last plane: the last plane again, never stored)
+#pragma unroll
+  for (int q = 0; q < ZP; ++q) sp[q] = src + (size_t)min(z0 + q, nz - 1) * pl;
   const int R = min(nr, NV / LP);           // lines per chunk
   for (int c0 = 0; c0 < nr; c0 += R) {
     const int rc = min(R, nr - c0);
     __syncthreads();                        // the previous chunk has been read
     const int n_el = rc * LP;
     const size_t off0 = (size_t)c0 * LP;
-    for (int e = threadIdx.x; e < n_el; e += 1024)
-      lds[e] = Vec4<T>{s0[off0 + e], s1[off0 + e], s2[off0 + e], s3[off0 + e]};
+    for (int e = threadIdx.x; e < n_el; e += 1024) {
+      VecZ<T, ZP> v;
+#pragma unroll
+      for (int q = 0; q < ZP; ++q) v.v[q] = sp[q][off0 + e];
+      lds[e] = v;
+    }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < kProjAnglesPerThread; ++m) {
@@ -240,11 +245,9 @@ project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__
           const int i0 = min(max((int)(u >> 32), -3), nm + 1) + kLinePadL;
           const T f = (T)(unsigned)(u & 0xffffffffLL) * T(2.3283064365386963e-10);
           const T e = T(1) - f;
-          const Vec4<T> v0 = lds[r * LP + i0], v1 = lds[r * LP + i0 + 1];
-          acc[m][0] = fma(f, v1.x, fma(e, v0.x, acc[m][0]));
-          acc[m][1] = fma(f, v1.y, fma(e, v0.y, acc[m][1]));
-          acc[m][2] = fma(f, v1.z, fma(e, v0.z, acc[m][2]));
-          acc[m][3] = fma(f, v1.w, fma(e, v0.w, acc[m][3]));
+          const VecZ<T, ZP> v0 = lds[r * LP + i0], v1 = lds[r * LP + i0 + 1];
+#pragma unroll
+          for (int q = 0; q < ZP; ++q) acc[m][q] = fma(f, v1.v[q], fma(e, v0.v[q], acc[m][q]));
           u += UR;
         }
         U[m] = u;
@@ -257,11 +260,9 @@ project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__
           const int i0 = (int)fmin(fmax(fl, -3.0), (double)(nm + 1)) + kLinePadL;
           const T f = (T)(u - fl);
           const T e = T(1) - f;
-          const Vec4<T> v0 = lds[r * LP + i0], v1 = lds[r * LP + i0 + 1];
-          acc[m][0] = fma(f, v1.x, fma(e, v0.x, acc[m][0]));
-          acc[m][1] = fma(f, v1.y, fma(e, v0.y, acc[m][1]));
-          acc[m][2] = fma(f, v1.z, fma(e, v0.z, acc[m][2]));
-          acc[m][3] = fma(f, v1.w, fma(e, v0.w, acc[m][3]));
+          const VecZ<T, ZP> v0 = lds[r * LP + i0], v1 = lds[r * LP + i0 + 1];
+#pragma unroll
+          for (int q = 0; q < ZP; ++q) acc[m][q] = fma(f, v1.v[q], fma(e, v0.v[q], acc[m][q]));
         }
       }
     }
@@ -274,7 +275,7 @@ project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__
     const int a = aorder[a_begin + ia];
     const T w = sizeof(T) == 4 ? (T)ap[a].w_f : (T)ap[a].w;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < ZP; ++q)
       if (z0 + q < nz) g[((size_t)a * nz + z0 + q) * ns + j] = acc[m][q] * w;
   }
 }
@@ -286,6 +287,24 @@ static bool xray_lds_enabled()
     return e ? atoi(e) != 0 : true;
   }();
   return on;
+}
+
+// planes per work-group of the staged backprojector (0: use the L2-gather
+// kernel): 8 in FP32 from 8 planes on (the bin position and weights serve 8
+// planes; 3% faster than 4 at 256^3 / 256 angles), else 4 (FP64: 8 planes of
+// accumulators would not fit the register budget); FFPAT_XRAY_LDS_ZP = 4 or 8
+// overrides for FP32
+static int xray_lds_planes(int nz, size_t esz)
+{
+  static const int env = [] {
+    const char *e = getenv("FFPAT_XRAY_LDS_ZP");
+    const int v = e ? atoi(e) : 0;
+    return (v == 4 || v == 8) ? v : 0;
+  }();
+  if (nz < 4) return 0;
+  if (esz == 8) return 4;
+  if (env) return nz >= env ? env : 4;
+  return nz >= 8 ? 8 : 4;
 }
 
 // planes per thread of the backprojector (FFPAT_XRAY_ZP = 1, 4 or 8 overrides):
@@ -324,13 +343,15 @@ hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int lp_max = (d.nx > d.ny ? d.nx : d.ny) + kLinePadL + kLinePadR;
-  if (d.nz >= 4 && lp_max <= kLdsBytes / (int)sizeof(Vec4<T>) && xray_lds_enabled()) {
+  // four planes per work-group: eight (in FP32) measured 14% slower at 256^3 / 256
+  // angles (half the work-groups, half the lines per LDS chunk)
+  if (d.nz >= 4 && lp_max <= kLdsBytes / (int)(4 * sizeof(T)) && xray_lds_enabled()) {
     const int gr = (n_row_angles + kProjAngles - 1) / kProjAngles;
     const int gc = (n_angles - n_row_angles + kProjAngles - 1) / kProjAngles;
     const long n_work = (long)(gr + gc) * ((d.nz + 3) / 4) * ((ns + 255) / 256);
     const long grid = (n_work + 7) / 8 * 8;
-    project_lds_kernel<T><<<(unsigned)grid, 1024, 0, s>>>(padN, padT, g, ap, aorder, n_row_angles, n_angles, d.nx,
-                                                          d.ny, d.nz, ns, gr, gr + gc, (int)n_work);
+    project_lds_kernel<T, 4><<<(unsigned)grid, 1024, 0, s>>>(padN, padT, g, ap, aorder, n_row_angles, n_angles,
+                                                             d.nx, d.ny, d.nz, ns, gr, gr + gc, (int)n_work);
     return hipGetLastError();
   }
   // one plane per thread, eight lines unrolled: measured at 256^3 / 256 angles,
@@ -436,22 +457,22 @@ backproject_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const AngleP
 
 // ---------------------------------------------------------------------------
 // Two-tap backprojector with the detector rows staged in LDS.  A 1024-thread
-// work-group owns a 64 x 64 voxel tile in four consecutive planes; thread
-// (i, kk) accumulates voxels (i, kk + 16 v), v = 0..3, in the four planes.
-// Chunks of angles are staged into LDS with the four planes' rows interleaved
-// ([angle][padded bin] of 4-vectors), so the two taps of a voxel in all four
-// planes are two vector LDS reads; the bin position and weights are computed
+// work-group owns a 64 x 64 voxel tile in ZP consecutive planes (8 in FP32, 4
+// in FP64); thread (i, kk) accumulates voxels (i, kk + 16 v), v = 0..3, in the
+// ZP planes.  Chunks of angles are staged into LDS with the planes' rows interleaved
+// ([angle][padded bin] of ZP-vectors), so the two taps of a voxel in all ZP
+// planes are a few vector LDS reads; the bin position and weights are computed
 // once per voxel and angle.  Same arithmetic and order as backproject_kernel
 // (angles in order, two FMAs per plane).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int ZP>
 __global__ void __launch_bounds__(1024)
 backproject_lds_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const AngleParams *__restrict__ ap,
                        int n_angles, int nx, int ny, int nz, int ns, const T *__restrict__ kap, int tiles_x,
                        int tiles_y, int n_work)
 {
-  constexpr int NV = kLdsBytes / sizeof(Vec4<T>);
-  __shared__ Vec4<T> lds[NV];
+  constexpr int NV = kLdsBytes / sizeof(VecZ<T, ZP>);
+  __shared__ VecZ<T, ZP> lds[NV];
   const int b = blockIdx.x;
   const int per_xcd = (n_work + 7) / 8;
   const int tw = (b % 8) * per_xcd + b / 8;
@@ -459,31 +480,35 @@ backproject_lds_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const An
   const int bx = tw % tiles_x;
   const int rest = tw / tiles_x;
   const int by = rest % tiles_y;
-  const int z0 = (rest / tiles_y) * 4;
+  const int z0 = (rest / tiles_y) * ZP;
   const int i = bx * 64 + (threadIdx.x & 63);
   const int k0 = by * 64 + (threadIdx.x >> 6);
   const int RS = ns + kRowPadL + kRowPadR;
   const int AC = NV / RS;                   // angles per chunk
 
-  T acc[4][4];
+  T acc[4][ZP];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[v][q] = T(0);
-  const int zc[4] = {min(z0, nz - 1), min(z0 + 1, nz - 1), min(z0 + 2, nz - 1), min(z0 + 3, nz - 1)};
+    for (int q = 0; q < ZP; ++q) acc[v][q] = T(0);
+  int zc[ZP];   // the group's planes (past the last plane: the last plane again, never stored)
+#pragma unroll
+  for (int q = 0; q < ZP; ++q) zc[q] = min(z0 + q, nz - 1);
   for (int a0 = 0; a0 < n_angles; a0 += AC) {
     const int ac = min(AC, n_angles - a0);
     __syncthreads();                        // the previous chunk has been read
     for (int e = threadIdx.x; e < ac * RS; e += 1024) {
       const int al = e / RS, jj = e - al * RS;
       const size_t row = (size_t)(a0 + al) * nz;
-      lds[e] = Vec4<T>{gpad[(row + zc[0]) * RS + jj], gpad[(row + zc[1]) * RS + jj],
-                       gpad[(row + zc[2]) * RS + jj], gpad[(row + zc[3]) * RS + jj]};
+      VecZ<T, ZP> v;
+#pragma unroll
+      for (int q = 0; q < ZP; ++q) v.v[q] = gpad[(row + zc[q]) * RS + jj];
+      lds[e] = v;
     }
     __syncthreads();
     for (int al = 0; al < ac; ++al) {
       const AngleParams &P = ap[a0 + al];
-      const Vec4<T> *L = lds + al * RS;
+      const VecZ<T, ZP> *L = lds + al * RS;
       if (sizeof(T) == 4) {
         const long long T0 = P.b0_fix + (long long)i * P.bi_fix + (long long)k0 * P.bk_fix;
         const long long BK16 = 16 * P.bk_fix;
@@ -495,11 +520,9 @@ backproject_lds_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const An
           const T f = (T)(unsigned)(Tv & 0xffffffffLL) * T(2.3283064365386963e-10);
           const T w0 = wa * fmax(T(1) - f * ih, T(0));
           const T w1 = wa * fmax(T(1) - (T(1) - f) * ih, T(0));
-          const Vec4<T> v0 = L[j0], v1 = L[j0 + 1];
-          acc[v][0] = fma(w1, v1.x, fma(w0, v0.x, acc[v][0]));
-          acc[v][1] = fma(w1, v1.y, fma(w0, v0.y, acc[v][1]));
-          acc[v][2] = fma(w1, v1.z, fma(w0, v0.z, acc[v][2]));
-          acc[v][3] = fma(w1, v1.w, fma(w0, v0.w, acc[v][3]));
+          const VecZ<T, ZP> v0 = L[j0], v1 = L[j0 + 1];
+#pragma unroll
+          for (int q = 0; q < ZP; ++q) acc[v][q] = fma(w1, v1.v[q], fma(w0, v0.v[q], acc[v][q]));
         }
       } else {
         const T ih = (T)P.inv_hw, wa = (T)P.w;
@@ -512,11 +535,9 @@ backproject_lds_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const An
           // a clamped bin reads two pads, so the weights do not matter there
           const T w0 = wa * fmax(T(1) - f * ih, T(0));
           const T w1 = wa * fmax(T(1) - (T(1) - f) * ih, T(0));
-          const Vec4<T> v0 = L[j0], v1 = L[j0 + 1];
-          acc[v][0] = fma(w1, v1.x, fma(w0, v0.x, acc[v][0]));
-          acc[v][1] = fma(w1, v1.y, fma(w0, v0.y, acc[v][1]));
-          acc[v][2] = fma(w1, v1.z, fma(w0, v0.z, acc[v][2]));
-          acc[v][3] = fma(w1, v1.w, fma(w0, v0.w, acc[v][3]));
+          const VecZ<T, ZP> v0 = L[j0], v1 = L[j0 + 1];
+#pragma unroll
+          for (int q = 0; q < ZP; ++q) acc[v][q] = fma(w1, v1.v[q], fma(w0, v0.v[q], acc[v][q]));
         }
       }
     }
@@ -527,7 +548,7 @@ backproject_lds_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const An
     const int k = k0 + 16 * v;
     if (k >= ny) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < ZP; ++q) {
       if (z0 + q >= nz) continue;
       const size_t idx = ((size_t)(z0 + q) * ny + k) * nx + i;
       vol[idx] = kap ? acc[v][q] * kap[idx] : acc[v][q];
@@ -555,12 +576,20 @@ template <typename T>
 hipError_t launch_backproject(const Dims &d, int n_angles, int ns, const AngleParams *ap, bool two_tap,
                               const T *gpad, T *vol, const T *kap, hipStream_t s)
 {
-  if (two_tap && d.nz >= 4 && ns + kRowPadL + kRowPadR <= kLdsBytes / (int)sizeof(Vec4<T>) && xray_lds_enabled()) {
+  const int zp = xray_lds_planes(d.nz, sizeof(T));
+  if (two_tap && zp > 0 && ns + kRowPadL + kRowPadR <= kLdsBytes / (int)(zp * sizeof(T)) && xray_lds_enabled()) {
     const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + 63) / 64;
-    const long n_work = (long)tiles_x * tiles_y * ((d.nz + 3) / 4);
+    const long n_work = (long)tiles_x * tiles_y * ((d.nz + zp - 1) / zp);
     const long grid = (n_work + 7) / 8 * 8;
-    backproject_lds_kernel<T><<<(unsigned)grid, 1024, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns, kap,
-                                                              tiles_x, tiles_y, (int)n_work);
+    if constexpr (sizeof(T) == 4) {
+      if (zp == 8) {
+        backproject_lds_kernel<T, 8><<<(unsigned)grid, 1024, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns,
+                                                                     kap, tiles_x, tiles_y, (int)n_work);
+        return hipGetLastError();
+      }
+    }
+    backproject_lds_kernel<T, 4><<<(unsigned)grid, 1024, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns,
+                                                                 kap, tiles_x, tiles_y, (int)n_work);
     return hipGetLastError();
   }
   switch (xray_planes(d.nz)) {
