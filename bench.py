@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--fp64-compare", type=int, default=1, help="also time FB iterations in FP64 (1/0)")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="time the oracle on a bounded sample (1/0)")
     ap.add_argument("--naive-stencil", action="store_true")
+    ap.add_argument("--n", type=int, default=0, help="--mode wave: grid edge instead of the recipe's")
     ap.add_argument("--stencil", default="auto", choices=["auto", "single", "pairs"],
                     help="--mode wave: leapfrog steps per stencil pass (auto: the plan's choice)")
     ap.add_argument("--seed", type=int, default=3001)
@@ -227,7 +228,7 @@ def run_wave_only(args):
     import numpy as np
     dtype = torch.float32 if args.dtype == "float32" else torch.float64
     r = synth.RECIPES[args.recipe]
-    n = r["n"]
+    n = args.n or r["n"]
     dx = synth.grid_spacing(n)
     c = synth.sound_speed((n, n, n), dx, np.random.default_rng(args.seed), r["bumps"], r["amp"], r["clamp"])
     plan = ff.Plan(torch.from_numpy(c).to("cuda", dtype), dx, r["T"], synth.uniform_angles(r["n_angles"]),
