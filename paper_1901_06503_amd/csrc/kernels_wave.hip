@@ -555,6 +555,36 @@ static hipError_t blocked_select(StepMode mode, const Dims &d, const T *p, const
   }
 }
 
+// Planes per work-group of the two-step kernel.  Its groups are long (a whole
+// z-chunk each) and all of a launch's groups take about the same time, so a
+// launch runs in rounds of `resident` groups and a last round that is only
+// partly filled costs as much as a full one.  Where every chunk fits in one
+// round at zmax planes or fewer, take as many chunks per x-y tile as fit
+// (8 planes at least); otherwise zmax.  Measured on MI355X, us per leapfrog step
+// (this rule / a fixed target of 512 FP32 or 256 FP64 groups, which overshot one
+// round by 5-12% at these sizes): FP32 160^3 14.1 / 18.9, 192^3 17.4 / 24.0,
+// 224^3 27.6 (28 planes) / 36.8; FP64 160^3 22.7 / 37.1, 192^3 36.4 / 58.5,
+// 224^3 64.3 / 101.4; from 256^3 on both rules pick the same chunk.
+static int pair_zchunk(int nz, long xy, long resident, int zmax)
+{
+  const long fit = resident / (xy > 0 ? xy : 1);
+  if (fit < 1) return zmax;
+  const long zc = (nz + fit - 1) / fit;
+  return (int)(zc < 8 ? 8 : (zc > zmax ? zmax : zc));
+}
+
+// Groups of `kernel` (nth threads, static LDS only) the current device holds at
+// once; `fallback` if the runtime cannot say.  The per-unit occupancy depends on
+// the kernel only and is cached by the caller; the unit count is the device's.
+static long resident_groups(int per_cu, long fallback)
+{
+  int dev = 0, cus = 0;
+  if (per_cu <= 0 || hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return fallback;
+  return (long)cus * per_cu;
+}
+
 template <typename T, int NDIM, int RY, int NTH>
 static hipError_t pair_dispatch(const Dims &d, const T *pm1, const T *pk, T *q_out, T *o_out, const T *kap,
                                 const BlockedConfig &cfg, hipStream_t s)
@@ -563,13 +593,15 @@ static hipError_t pair_dispatch(const Dims &d, const T *pm1, const T *pk, T *q_o
   const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + BY - 1) / BY;
   int zchunk = cfg.zchunk2;
   if (zchunk <= 0) {
-    const long xy = (long)tiles_x * tiles_y;
-    // FP32: about 512 work-groups (two fit on a compute unit), 8 to 32 planes each;
-    // FP64: about 256 (one fits), 8 to 64 planes each
+    static const int per_cu = [] {
+      int n = 0;
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wave_step2_blocked<T, NDIM, RY, NTH>, NTH, 0) ==
+                     hipSuccess ? n : 0;
+    }();
     const bool f64 = sizeof(T) == 8;
-    const long zc = (long)d.nz * xy / (f64 ? 256 : 512);
-    const long zmax = f64 ? 64 : 32;
-    zchunk = (int)(zc < 8 ? 8 : (zc > zmax ? zmax : zc));
+    // FP32 (512 threads): two groups per compute unit; FP64: one
+    const long resident = resident_groups(per_cu, f64 ? 256 : 512);
+    zchunk = pair_zchunk(d.nz, (long)tiles_x * tiles_y, resident, f64 ? 64 : 32);
   }
   if (zchunk > d.nz) zchunk = d.nz;
   const int n_zc = (d.nz + zchunk - 1) / zchunk;
@@ -610,10 +642,11 @@ bool wave_pairs_preferred(const Dims &d, size_t esz)
     return e ? (atoi(e) != 0 ? 1 : 0) : -1;
   }();
   if (env >= 0) return env == 1;
-  // measured on MI355X, us per step one / two steps per pass: FP32 128^3 10.6 / 9.6,
-  // 256^3 49.7 / 47.8, 384^3 198 / 164; FP64 128^3 16.2 / 14.0, 256^3 111 / 76.5,
-  // 384^3 391 / 298.  Smaller FP32 grids keep one step per pass.
-  return esz == 8 || d.nvox() >= (size_t)128 * 128 * 128;
+  // measured on MI355X, us per step one / two steps per pass: FP32 96^3 9.1 / 9.3,
+  // 128^3 10.5 / 9.6, 256^3 49.6 / 47.2, 384^3 198 / 161; FP64 64^3 11.1 / 12.3,
+  // 96^3 12.8 / 12.4, 256^3 111 / 75.1, 384^3 391 / 296.  Smaller grids keep one
+  // step per pass.
+  return d.nvox() >= (esz == 8 ? (size_t)96 * 96 * 96 : (size_t)128 * 128 * 128);
 }
 
 bool wave_pairs_fit(const Dims &d, size_t esz)

@@ -88,6 +88,28 @@ def test_wave_and_transpose(oracle, shape, dtype, variant):
         assert rel_l2(q, oracle.wave_T(g, c, h)) <= TOL_WAVE[dtype]
 
 
+# Mid-size grids where the two-step kernel splits z into several chunks of a length
+# chosen from the resident work-group count (on 256 compute units: FP32 160^3 ->
+# 16 chunks of 10 planes, 224^3 -> 9 of 25 with a last one of 24; FP64 192^3 -> 7
+# of 28, last 24).  Short solves (T = 0.04: n_t 8 to 12) keep the oracle quick.
+MID_SIZES = [((160, 160, 160), F32), ((224, 224, 224), F32), ((192, 192, 192), F64)]
+
+
+@pytest.mark.parametrize("shape,dtype", MID_SIZES, ids=["f32-160", "f32-224", "f64-192"])
+def test_wave_pairs_mid_size_chunking(oracle, shape, dtype):
+    _case_tag(shape, dtype, "pairs-auto")
+    k = make_case(shape, 5, T=0.04)
+    g = oracle_geom(oracle, k)
+    c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
+    import paper_1901_06503_amd as ff
+    with ff.Plan(to_dev(c, dtype), k["dx"], k["T"], k["angles"], cfl=k["cfl"]) as P:
+        assert P.steps_per_pass == 2 and P.nt >= 5
+        p = to_np(P.wave(to_dev(h, dtype)))
+        assert rel_l2(p, oracle.wave(g, c, h)) <= TOL_WAVE[dtype]
+        q = to_np(P.wave_adjoint(to_dev(h, dtype)))
+        assert rel_l2(q, oracle.wave_T(g, c, h)) <= TOL_WAVE[dtype]
+
+
 @pytest.mark.parametrize("dtype", [F64, F32])
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("ds_ratio,ns_extra", [(1.0, 0), (0.83, 7), (1.3, -5)])
