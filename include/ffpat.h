@@ -140,6 +140,13 @@ int ffpat_plan_info(const ffpat_plan *plan, int32_t *nt, double *dt, double *cma
  * remaining n_t - 1 steps are odd. */
 int ffpat_plan_steps_per_pass(const ffpat_plan *plan, int32_t *steps);
 
+/* Launch shape of the plan's leapfrog stencil kernel (informational; the kernel
+ * that ffpat_plan_steps_per_pass names): tile width and height in grid points and
+ * z-planes per work-group.  Chosen per grid, element size and the device the plan
+ * was created on (compute units, work-groups a unit holds at once).  0 for all three
+ * with FFPAT_PLAN_NAIVE_STENCIL (no tiles).  Any pointer may be NULL. */
+int ffpat_plan_stencil_shape(const ffpat_plan *plan, int32_t *tile_x, int32_t *tile_y, int32_t *zchunk);
+
 /* Releases the plan and its device memory (synchronises the device first). */
 int ffpat_plan_destroy(ffpat_plan *plan);
 

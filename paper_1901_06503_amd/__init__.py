@@ -113,6 +113,9 @@ class Plan:
         sp = ctypes.c_int32()
         _lib.check(self._lib.ffpat_plan_steps_per_pass(self._h, ctypes.byref(sp)))
         self.steps_per_pass = sp.value          # 2: temporally blocked stencil kernel
+        tx, ty, zc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(self._lib.ffpat_plan_stencil_shape(self._h, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(zc)))
+        self.stencil_shape = (tx.value, ty.value, zc.value)   # tile width, height, planes per work-group
 
     # ------------------------------------------------------------------ helpers
     def _check_tensor(self, t, shape, name):

@@ -63,7 +63,12 @@ hipError_t launch_wave_step(StencilKind kind, StepMode mode, const Dims &d, cons
 // All four buffers must be distinct.
 template <typename T>
 hipError_t launch_wave_pair(const Dims &d, const T *pm1, const T *pk, T *q, T *o, const T *kap, hipStream_t s);
-// Whether the plan layer should use launch_wave_pair (FFPAT_STENCIL_TB=0 disables it).
+// Tile (width, height) and planes per work-group that launch_wave_pair takes on the
+// current device for this grid.
+template <typename T>
+void wave_pair_shape(const Dims &d, int *tile_x, int *tile_y, int *zchunk);
+// The same for the one-step blocked kernel (launch_wave_step with STENCIL_BLOCKED).
+void wave_step_shape(const Dims &d, size_t esz, int *tile_x, int *tile_y, int *zchunk);
 // Whether the two-step kernel is the faster choice for this grid and element size
 // (FFPAT_STENCIL_TB=0/1 in the environment overrides the rule).
 bool wave_pairs_preferred(const Dims &d, size_t esz);

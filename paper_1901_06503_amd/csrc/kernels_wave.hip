@@ -247,14 +247,14 @@ __device__ __forceinline__ void stb(T *base, unsigned boff, T v)
   *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff) = v;
 }
 
-template <typename T, int NDIM, int RY, int NTH>
+template <typename T, int NDIM, int RY, int NTH, int BX>
 // FP32 with 512 threads: at most 128 VGPRs, so two work-groups share a compute unit
 __global__ void __launch_bounds__(NTH, (sizeof(T) == 4 && NTH >= 512) ? 4 : 1)
 wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__restrict__ q_out,
                    T *__restrict__ o_out, const T *__restrict__ kap, int nx, int ny, int nz, int zchunk, int tiles_x,
                    int tiles_y, int n_tiles, int xy_fastest)
 {
-  constexpr int BX = 64, BY = 4 * RY;
+  constexpr int BY = 4 * RY;
   constexpr int EX = BX + 4, EY = BY + 4;   // extended tile: stage-1 output region
   constexpr int KX = BX + 8, KY = BY + 8;   // p(k) plane in LDS: stage-1 input region
   constexpr int NE = EX * EY;
@@ -475,6 +475,7 @@ struct BlockedConfig {
   int ry2 = 0;       // two-step kernel: tile height / 4 (0: default 4)
   int zchunk2 = 0;   // two-step kernel: planes per work-group (0: from the grid size)
   int threads2 = 512; // two-step kernel: work-group size (256, 512 or 1024)
+  int bx2 = 0;       // two-step kernel: tile width (0: chosen per grid; 64, or 128 in FP32 3D)
 };
 
 static BlockedConfig blocked_config(const Dims &d, size_t esz)
@@ -492,6 +493,7 @@ static BlockedConfig blocked_config(const Dims &d, size_t esz)
     if (const char *e = getenv("FFPAT_STENCIL_NT")) c.nt = atoi(e) ? 1 : 0;
     if (const char *e = getenv("FFPAT_STENCIL2_RY")) c.ry2 = atoi(e);
     if (const char *e = getenv("FFPAT_STENCIL2_ZCHUNK")) c.zchunk2 = atoi(e);
+    if (const char *e = getenv("FFPAT_STENCIL2_BX")) c.bx2 = atoi(e) == 128 ? 128 : (atoi(e) == 64 ? 64 : 0);
     if (const char *e = getenv("FFPAT_STENCIL2_THREADS")) {
       const int v = atoi(e);
       c.threads2 = v == 1024 ? 1024 : (v == 256 ? 256 : 512);
@@ -505,22 +507,37 @@ static BlockedConfig blocked_config(const Dims &d, size_t esz)
   return cfg;
 }
 
+// Planes per work-group of the one-step kernel: about cfg.groups work-groups, 4..16
+// planes per group (measured on MI355X: longer chunks lose parallelism, shorter ones
+// re-read more z halo).
+static int step_zchunk(const Dims &d, const BlockedConfig &cfg, int tiles_x, int tiles_y)
+{
+  int zchunk = cfg.zchunk;
+  if (zchunk <= 0) {
+    const long xy = (long)tiles_x * tiles_y;
+    const long zc = (long)d.nz * xy / cfg.groups;
+    zchunk = (int)(zc < 4 ? 4 : (zc > 16 ? 16 : zc));
+  }
+  return zchunk > d.nz ? d.nz : zchunk;
+}
+
+void wave_step_shape(const Dims &d, size_t esz, int *tile_x, int *tile_y, int *zchunk)
+{
+  const BlockedConfig cfg = blocked_config(d, esz);
+  const int by = 4 * cfg.ry;
+  *tile_x = 64;
+  *tile_y = by;
+  *zchunk = step_zchunk(d, cfg, (d.nx + 63) / 64, (d.ny + by - 1) / by);
+}
+
 template <typename T, int NDIM, int RY>
 static hipError_t blocked_dispatch(StepMode mode, const Dims &d, const T *p, const T *prev, T *out, const T *kap,
                                    const BlockedConfig &cfg, hipStream_t s)
 {
   constexpr int BY = 4 * RY;
   const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + BY - 1) / BY;
-  int zchunk = cfg.zchunk;
+  const int zchunk = step_zchunk(d, cfg, tiles_x, tiles_y);
   const int xyf = cfg.order;
-  if (zchunk <= 0) {
-    // about cfg.groups work-groups, 4..16 planes per group (measured on MI355X:
-    // longer chunks lose parallelism, shorter ones re-read more z halo)
-    const long xy = (long)tiles_x * tiles_y;
-    const long zc = (long)d.nz * xy / cfg.groups;
-    zchunk = (int)(zc < 4 ? 4 : (zc > 16 ? 16 : zc));
-  }
-  if (zchunk > d.nz) zchunk = d.nz;
   const int n_zc = (d.nz + zchunk - 1) / zchunk;
   const int n_tiles = tiles_x * tiles_y * n_zc;
   const int grid = ((n_tiles + 7) / 8) * 8;
@@ -573,66 +590,158 @@ static int pair_zchunk(int nz, long xy, long resident, int zmax)
   return (int)(zc < 8 ? 8 : (zc > zmax ? zmax : zc));
 }
 
-// Groups of `kernel` (nth threads, static LDS only) the current device holds at
-// once; `fallback` if the runtime cannot say.  The per-unit occupancy depends on
-// the kernel only and is cached by the caller; the unit count is the device's.
-static long resident_groups(int per_cu, long fallback)
+// Compute units of the current device (0 if the runtime cannot say).
+static int device_cus()
 {
   int dev = 0, cus = 0;
-  if (per_cu <= 0 || hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-    return fallback;
-  return (long)cus * per_cu;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return cus;
 }
 
-template <typename T, int NDIM, int RY, int NTH>
-static hipError_t pair_dispatch(const Dims &d, const T *pm1, const T *pk, T *q_out, T *o_out, const T *kap,
-                                const BlockedConfig &cfg, hipStream_t s)
+// Launch shape of one instantiation of the two-step kernel on a grid.
+struct PairShape {
+  int bx, by;              // tile
+  int tiles_x, tiles_y;
+  int zchunk, n_tiles;     // planes per group, groups
+  int per_cu, cus;         // groups a compute unit holds at once, compute units
+};
+
+template <typename T, int NDIM, int RY, int NTH, int BX>
+static PairShape pair_shape(const Dims &d, const BlockedConfig &cfg)
 {
-  constexpr int BY = 4 * RY;
-  const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + BY - 1) / BY;
-  int zchunk = cfg.zchunk2;
-  if (zchunk <= 0) {
-    static const int per_cu = [] {
-      int n = 0;
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wave_step2_blocked<T, NDIM, RY, NTH>, NTH, 0) ==
-                     hipSuccess ? n : 0;
-    }();
-    const bool f64 = sizeof(T) == 8;
-    // FP32 (512 threads): two groups per compute unit; FP64: one
-    const long resident = resident_groups(per_cu, f64 ? 256 : 512);
-    zchunk = pair_zchunk(d.nz, (long)tiles_x * tiles_y, resident, f64 ? 64 : 32);
-  }
+  static const int occ = [] {
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wave_step2_blocked<T, NDIM, RY, NTH, BX>, NTH, 0) ==
+                   hipSuccess ? n : 0;
+  }();
+  const bool f64 = sizeof(T) == 8;
+  PairShape p;
+  p.bx = BX;
+  p.by = 4 * RY;
+  p.tiles_x = (d.nx + BX - 1) / BX;
+  p.tiles_y = (d.ny + p.by - 1) / p.by;
+  // if the runtime cannot say: FP32 with up to 512 threads two groups per unit, else one
+  p.per_cu = occ > 0 ? occ : ((!f64 && NTH <= 512) ? 2 : 1);
+  const int cus = device_cus();
+  p.cus = cus > 0 ? cus : 256;
+  int zchunk = cfg.zchunk2 > 0 ? cfg.zchunk2
+                               : pair_zchunk(d.nz, (long)p.tiles_x * p.tiles_y, (long)p.cus * p.per_cu, f64 ? 64 : 32);
   if (zchunk > d.nz) zchunk = d.nz;
-  const int n_zc = (d.nz + zchunk - 1) / zchunk;
-  const int n_tiles = tiles_x * tiles_y * n_zc;
-  const int grid = ((n_tiles + 7) / 8) * 8;
-  wave_step2_blocked<T, NDIM, RY, NTH><<<grid, NTH, 0, s>>>(pm1, pk, q_out, o_out, kap, d.nx, d.ny, d.nz, zchunk,
-                                                             tiles_x, tiles_y, n_tiles, cfg.order);
-  return hipGetLastError();
+  p.zchunk = zchunk;
+  p.n_tiles = p.tiles_x * p.tiles_y * ((d.nz + zchunk - 1) / zchunk);
+  return p;
+}
+
+// Estimated duration of a launch: rounds of resident groups times planes per group,
+// in units of one plane of a group.  t_shared: a group's plane time while its
+// compute unit is full; t_alone: in a last round that leaves at most one group per
+// unit.
+static double pair_cost(const PairShape &p, double t_shared, double t_alone)
+{
+  const long resident = (long)p.cus * p.per_cu;
+  const long full = p.n_tiles / resident, rem = p.n_tiles % resident;
+  double t = (double)full * t_shared;
+  if (rem > 0) t += rem <= p.cus ? t_alone : t_shared;
+  return t * p.zchunk;
+}
+
+// The instantiations of the two-step kernel: <NDIM, RY (tile height / 4), threads, tile width>.
+enum PairVariant {
+  PAIR_2D_RY4, PAIR_2D_RY2,                                  // 256 threads, 64 wide
+  PAIR_WIDE,                                                 // FP32 3D: 128 x 16, 1024 threads
+  PAIR_RY8_T1024, PAIR_RY4_T1024, PAIR_RY8_T512, PAIR_RY4_T512, PAIR_RY2_T512, PAIR_RY4_T256, PAIR_RY2_T256,
+};
+
+// FP32 3D with the default work-group (512 threads, tile 64 x 16): whether the
+// 128 x 16 tile (1024 threads, one group per compute unit) is faster.  The wide tile
+// reads fewer bytes (a 64-wide tile's 2-point x halo costs a whole 128-byte line on
+// each side: at 256^3 the wide tile's L2 fetches are 23% lower) but pads nx to a
+// multiple of 128 and halves the group count.  Plane times of a group measured on
+// MI355X, relative to a 64-wide group sharing its unit: 128-wide 0.9, 64-wide alone
+// 0.55.  With them the estimate picks the faster tile at all twelve cubes measured
+// from 128^3 to 640^3 (us per step, wide / narrow: 224^3 24.8 / 26.4, 256^3 42.3 /
+// 47.0, 288^3 74.8 / 78.3, 512^3 347 / 391, 640^3 690 / 746; narrow kept at 128^3
+// 9.8 / 11.3, 192^3 18.4 / 20.5, 320^3 91.4 / 107, 384^3 160.5 / 162.5, 448^3
+// 248 / 274).  FFPAT_STENCIL2_BX=64 or 128 forces the width.
+template <typename T>
+static bool pair_wide_preferred(const Dims &d, const BlockedConfig &cfg)
+{
+  if constexpr (sizeof(T) != 4) {
+    return false;
+  } else {
+    if (d.ndim != 3 || cfg.bx2 == 64) return false;
+    if (cfg.bx2 == 128) return true;
+    if (cfg.threads2 != 512 || (cfg.ry2 > 0 && cfg.ry2 != 4)) return false;
+    return pair_cost(pair_shape<T, 3, 4, 1024, 128>(d, cfg), 0.9, 0.9) <
+           pair_cost(pair_shape<T, 3, 4, 512, 64>(d, cfg), 1.0, 0.55);
+  }
+}
+
+template <typename T>
+static PairVariant pair_variant(const Dims &d, const BlockedConfig &cfg)
+{
+  const int ry = cfg.ry2 > 0 ? cfg.ry2 : 4;
+  if (d.ndim == 2) return ry == 4 ? PAIR_2D_RY4 : PAIR_2D_RY2;
+  if (pair_wide_preferred<T>(d, cfg)) return PAIR_WIDE;
+  if (cfg.threads2 == 1024) return ry == 8 ? PAIR_RY8_T1024 : PAIR_RY4_T1024;
+  if (cfg.threads2 == 512) return ry == 8 ? PAIR_RY8_T512 : (ry == 4 ? PAIR_RY4_T512 : PAIR_RY2_T512);
+  return ry == 4 ? PAIR_RY4_T256 : PAIR_RY2_T256;
+}
+
+// Calls f with the kernel instantiation of variant v (as a null pointer of its type
+// tag) so that the shape and the launch are taken from the same list.
+template <int NDIM, int RY, int NTH, int BX>
+struct PairTag {
+  static constexpr int ndim = NDIM, ry = RY, nth = NTH, bx = BX;
+};
+
+template <typename T, typename F>
+static auto visit_pair(PairVariant v, F &&f)
+{
+  switch (v) {
+    case PAIR_2D_RY4: return f(PairTag<2, 4, 256, 64>{});
+    case PAIR_2D_RY2: return f(PairTag<2, 2, 256, 64>{});
+    case PAIR_WIDE:
+      if constexpr (sizeof(T) == 4) return f(PairTag<3, 4, 1024, 128>{});
+      else return f(PairTag<3, 4, 512, 64>{});   // never chosen in FP64
+    case PAIR_RY8_T1024: return f(PairTag<3, 8, 1024, 64>{});
+    case PAIR_RY4_T1024: return f(PairTag<3, 4, 1024, 64>{});
+    case PAIR_RY8_T512: return f(PairTag<3, 8, 512, 64>{});
+    case PAIR_RY4_T512: return f(PairTag<3, 4, 512, 64>{});
+    case PAIR_RY2_T512: return f(PairTag<3, 2, 512, 64>{});
+    case PAIR_RY4_T256: return f(PairTag<3, 4, 256, 64>{});
+    default: return f(PairTag<3, 2, 256, 64>{});
+  }
 }
 
 template <typename T>
 hipError_t launch_wave_pair(const Dims &d, const T *pm1, const T *pk, T *q_out, T *o_out, const T *kap,
                             hipStream_t s)
 {
-  BlockedConfig cfg = blocked_config(d, sizeof(T));
-  const int ry = cfg.ry2 > 0 ? cfg.ry2 : 4;
-  if (d.ndim == 2) {
-    if (ry == 4) return pair_dispatch<T, 2, 4, 256>(d, pm1, pk, q_out, o_out, kap, cfg, s);
-    return pair_dispatch<T, 2, 2, 256>(d, pm1, pk, q_out, o_out, kap, cfg, s);
-  }
-  if (cfg.threads2 == 1024) {
-    if (ry == 8) return pair_dispatch<T, 3, 8, 1024>(d, pm1, pk, q_out, o_out, kap, cfg, s);
-    return pair_dispatch<T, 3, 4, 1024>(d, pm1, pk, q_out, o_out, kap, cfg, s);
-  }
-  if (cfg.threads2 == 512) {
-    if (ry == 8) return pair_dispatch<T, 3, 8, 512>(d, pm1, pk, q_out, o_out, kap, cfg, s);
-    if (ry == 4) return pair_dispatch<T, 3, 4, 512>(d, pm1, pk, q_out, o_out, kap, cfg, s);
-    return pair_dispatch<T, 3, 2, 512>(d, pm1, pk, q_out, o_out, kap, cfg, s);
-  }
-  if (ry == 4) return pair_dispatch<T, 3, 4, 256>(d, pm1, pk, q_out, o_out, kap, cfg, s);
-  return pair_dispatch<T, 3, 2, 256>(d, pm1, pk, q_out, o_out, kap, cfg, s);
+  const BlockedConfig cfg = blocked_config(d, sizeof(T));
+  return visit_pair<T>(pair_variant<T>(d, cfg), [&](auto tag) {
+    using Tag = decltype(tag);
+    const PairShape p = pair_shape<T, Tag::ndim, Tag::ry, Tag::nth, Tag::bx>(d, cfg);
+    const int grid = ((p.n_tiles + 7) / 8) * 8;
+    wave_step2_blocked<T, Tag::ndim, Tag::ry, Tag::nth, Tag::bx><<<grid, Tag::nth, 0, s>>>(
+        pm1, pk, q_out, o_out, kap, d.nx, d.ny, d.nz, p.zchunk, p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+void wave_pair_shape(const Dims &d, int *tile_x, int *tile_y, int *zchunk)
+{
+  const BlockedConfig cfg = blocked_config(d, sizeof(T));
+  const PairShape p = visit_pair<T>(pair_variant<T>(d, cfg), [&](auto tag) {
+    using Tag = decltype(tag);
+    return pair_shape<T, Tag::ndim, Tag::ry, Tag::nth, Tag::bx>(d, cfg);
+  });
+  *tile_x = p.bx;
+  *tile_y = p.by;
+  *zchunk = p.zchunk;
 }
 
 bool wave_pairs_preferred(const Dims &d, size_t esz)
@@ -758,6 +867,7 @@ hipError_t launch_c_stats(const Dims &d, const T *c, double *partials, int nbloc
 
 #define FFPAT_INST(T)                                                                                        \
   template hipError_t launch_wave_pair<T>(const Dims &, const T *, const T *, T *, T *, const T *, hipStream_t); \
+  template void wave_pair_shape<T>(const Dims &, int *, int *, int *);                                     \
   template hipError_t launch_wave_step<T>(StencilKind, StepMode, const Dims &, const T *, const T *, T *,  \
                                           const T *, hipStream_t);                                          \
   template hipError_t launch_make_kappa<T>(const Dims &, const T *, double, double, T *, hipStream_t);     \

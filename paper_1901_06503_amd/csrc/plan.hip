@@ -826,6 +826,23 @@ int ffpat_plan_steps_per_pass(const ffpat_plan *plan, int32_t *steps)
   return FFPAT_OK;
 }
 
+int ffpat_plan_stencil_shape(const ffpat_plan *plan, int32_t *tile_x, int32_t *tile_y, int32_t *zchunk)
+{
+  CHECK_PLAN(plan);
+  int tx = 0, ty = 0, zc = 0;
+  if (plan->stencil == STENCIL_BLOCKED) {
+    DeviceGuard guard(plan->device);
+    const size_t esz = plan->dtype == FFPAT_F64 ? 8 : 4;
+    if (!plan->use_pairs) wave_step_shape(plan->d, esz, &tx, &ty, &zc);
+    else if (esz == 8) wave_pair_shape<double>(plan->d, &tx, &ty, &zc);
+    else wave_pair_shape<float>(plan->d, &tx, &ty, &zc);
+  }
+  if (tile_x) *tile_x = tx;
+  if (tile_y) *tile_y = ty;
+  if (zchunk) *zchunk = zc;
+  return FFPAT_OK;
+}
+
 int ffpat_plan_destroy(ffpat_plan *plan)
 {
   if (!plan) return FFPAT_OK;

@@ -103,6 +103,9 @@ def test_null_plan_is_rejected(lib):
     for name in ["ffpat_forward", "ffpat_adjoint", "ffpat_wave", "ffpat_wave_adjoint", "ffpat_project",
                  "ffpat_backproject", "ffpat_ramp"]:
         assert getattr(lib, name)(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == -1
+    i32 = ctypes.c_int32()
+    assert lib.ffpat_plan_steps_per_pass(None, ctypes.byref(i32)) == -1
+    assert lib.ffpat_plan_stencil_shape(None, ctypes.byref(i32), None, None) == -1
     assert lib.ffpat_plan_destroy(None) == 0
 
 

@@ -88,15 +88,23 @@ def test_wave_and_transpose(oracle, shape, dtype, variant):
         assert rel_l2(q, oracle.wave_T(g, c, h)) <= TOL_WAVE[dtype]
 
 
-# Mid-size grids where the two-step kernel splits z into several chunks of a length
-# chosen from the resident work-group count (on 256 compute units: FP32 160^3 ->
-# 16 chunks of 10 planes, 224^3 -> 9 of 25 with a last one of 24; FP64 192^3 -> 7
-# of 28, last 24).  Short solves (T = 0.04: n_t 8 to 12) keep the oracle quick.
-MID_SIZES = [((160, 160, 160), F32), ((224, 224, 224), F32), ((192, 192, 192), F64)]
+# Grids where the two-step kernel splits z into several chunks of a length chosen
+# from the resident work-group count, and picks its tile width per grid.  Expected
+# launch shapes (tile width, height, planes per group) on 256 compute units:
+# FP32 160^3 64 x 16, 16 chunks of 10 planes; FP32 224^3 128 x 16, 9 chunks of 25
+# (last 24); FP64 192^3 64 x 16, 7 of 28 (last 24); FP32 96 x 250 x 250 (nz, ny, nx)
+# 128 x 16 with ragged x and y tails (122 columns, 10 rows), 8 chunks of 12.
+# Short solves (T = 0.04: n_t 8 to 12) keep the oracle quick.
+MID_SIZES = [((160, 160, 160), F32, (64, 16, 10)), ((224, 224, 224), F32, (128, 16, 25)),
+             ((192, 192, 192), F64, (64, 16, 28)), ((96, 250, 250), F32, (128, 16, 12))]
 
 
-@pytest.mark.parametrize("shape,dtype", MID_SIZES, ids=["f32-160", "f32-224", "f64-192"])
-def test_wave_pairs_mid_size_chunking(oracle, shape, dtype):
+def _compute_units():
+    return torch.cuda.get_device_properties(0).multi_processor_count
+
+
+@pytest.mark.parametrize("shape,dtype,launch", MID_SIZES, ids=["f32-160", "f32-224", "f64-192", "f32-wide-ragged"])
+def test_wave_pairs_mid_size_chunking(oracle, shape, dtype, launch):
     _case_tag(shape, dtype, "pairs-auto")
     k = make_case(shape, 5, T=0.04)
     g = oracle_geom(oracle, k)
@@ -104,6 +112,10 @@ def test_wave_pairs_mid_size_chunking(oracle, shape, dtype):
     import paper_1901_06503_amd as ff
     with ff.Plan(to_dev(c, dtype), k["dx"], k["T"], k["angles"], cfl=k["cfl"]) as P:
         assert P.steps_per_pass == 2 and P.nt >= 5
+        if _compute_units() == 256:
+            assert P.stencil_shape == launch
+        else:
+            assert P.stencil_shape[0] in (64, 128)
         p = to_np(P.wave(to_dev(h, dtype)))
         assert rel_l2(p, oracle.wave(g, c, h)) <= TOL_WAVE[dtype]
         q = to_np(P.wave_adjoint(to_dev(h, dtype)))
