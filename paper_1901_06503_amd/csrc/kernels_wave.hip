@@ -572,22 +572,53 @@ static hipError_t blocked_select(StepMode mode, const Dims &d, const T *p, const
   }
 }
 
+// z-planes a two-step work-group recomputes beyond its chunk (the stage-1 planes
+// on either side), in the launch-time estimates below.
+constexpr int kPairHalo = 4;
+
 // Planes per work-group of the two-step kernel.  Its groups are long (a whole
 // z-chunk each) and all of a launch's groups take about the same time, so a
 // launch runs in rounds of `resident` groups and a last round that is only
 // partly filled costs as much as a full one.  Where every chunk fits in one
-// round at zmax planes or fewer, take as many chunks per x-y tile as fit
-// (8 planes at least); otherwise zmax.  Measured on MI355X, us per leapfrog step
-// (this rule / a fixed target of 512 FP32 or 256 FP64 groups, which overshot one
-// round by 5-12% at these sizes): FP32 160^3 14.1 / 18.9, 192^3 17.4 / 24.0,
-// 224^3 27.6 (28 planes) / 36.8; FP64 160^3 22.7 / 37.1, 192^3 36.4 / 58.5,
-// 224^3 64.3 / 101.4; from 256^3 on both rules pick the same chunk.
-static int pair_zchunk(int nz, long xy, long resident, int zmax)
+// round at zmax planes or fewer, take as many chunks per x-y tile as fit (8
+// planes at least).  Otherwise, with one group per compute unit, take the chunk
+// that minimises rounds x (planes + halo), the longest on ties; with two per unit
+// (whose short last round runs its groups alone on their units, faster), zmax.
+// Measured on MI355X, us per leapfrog step (this rule / a fixed target of 512
+// FP32 or 256 FP64 groups, which overshot one round by 5-12% at these sizes):
+// FP32 160^3 14.1 / 18.9, 192^3 17.4 / 24.0, 224^3 27.6 (28 planes) / 36.8;
+// FP64 160^3 22.7 / 37.1, 192^3 36.4 / 58.5, 224^3 64.3 / 101.4.  Beyond one round
+// the estimate ranks the chunks as measured (one group per unit, 20..32 planes
+// FP32 128-wide and 40..64 FP64, at 320^3..512^3); its picks, e.g. 128-wide FP32
+// 384^3 28 planes 152.1 us (32: 163.1), FP64 384^3 56 planes 276.5 (64: 296.6),
+// 448^3 50 planes 446.3 (64: 455.4); 64 at 320^3 and 512^3.
+static long pair_rounds(long groups, long resident)
 {
-  const long fit = resident / (xy > 0 ? xy : 1);
-  if (fit < 1) return zmax;
-  const long zc = (nz + fit - 1) / fit;
-  return (int)(zc < 8 ? 8 : (zc > zmax ? zmax : zc));
+  return (groups + resident - 1) / resident;
+}
+
+static int pair_zchunk(int nz, long xy, long resident, int per_cu, int zmax)
+{
+  if (xy < 1) xy = 1;
+  const int zlo = nz < 8 ? nz : 8, zhi = nz < zmax ? nz : zmax;
+  const long fit = resident / xy;
+  if (fit >= 1) {
+    const long zc = (nz + fit - 1) / fit;
+    if (zc <= zhi) return (int)(zc < zlo ? zlo : zc);
+  }
+  if (per_cu > 1) return zhi;
+  int best = zhi;
+  long best_cost = 0;
+  for (int zc = zhi; zc >= zlo; --zc) {
+    const int n_zc = (nz + zc - 1) / zc;
+    const int bal = (nz + n_zc - 1) / n_zc;   // the same chunk count with balanced chunks
+    const long cost = pair_rounds(xy * n_zc, resident) * (bal + kPairHalo);
+    if (zc == zhi || cost < best_cost) {
+      best = bal;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 
 // Compute units of the current device (0 if the runtime cannot say).
@@ -627,24 +658,25 @@ static PairShape pair_shape(const Dims &d, const BlockedConfig &cfg)
   const int cus = device_cus();
   p.cus = cus > 0 ? cus : 256;
   int zchunk = cfg.zchunk2 > 0 ? cfg.zchunk2
-                               : pair_zchunk(d.nz, (long)p.tiles_x * p.tiles_y, (long)p.cus * p.per_cu, f64 ? 64 : 32);
+                               : pair_zchunk(d.nz, (long)p.tiles_x * p.tiles_y, (long)p.cus * p.per_cu, p.per_cu,
+                                             f64 ? 64 : 32);
   if (zchunk > d.nz) zchunk = d.nz;
   p.zchunk = zchunk;
   p.n_tiles = p.tiles_x * p.tiles_y * ((d.nz + zchunk - 1) / zchunk);
   return p;
 }
 
-// Estimated duration of a launch: rounds of resident groups times planes per group,
-// in units of one plane of a group.  t_shared: a group's plane time while its
-// compute unit is full; t_alone: in a last round that leaves at most one group per
-// unit.
+// Estimated duration of a launch: rounds of resident groups times the planes a
+// group computes, in units of one plane of a group.  t_shared: a group's plane
+// time while its compute unit is full; t_alone: in a last round that leaves at
+// most one group per unit.
 static double pair_cost(const PairShape &p, double t_shared, double t_alone)
 {
   const long resident = (long)p.cus * p.per_cu;
   const long full = p.n_tiles / resident, rem = p.n_tiles % resident;
   double t = (double)full * t_shared;
-  if (rem > 0) t += rem <= p.cus ? t_alone : t_shared;
-  return t * p.zchunk;
+  if (rem > 0) t += (rem <= p.cus && p.per_cu > 1) ? t_alone : t_shared;
+  return t * (p.zchunk + kPairHalo);
 }
 
 // The instantiations of the two-step kernel: <NDIM, RY (tile height / 4), threads, tile width>.
@@ -662,9 +694,10 @@ enum PairVariant {
 // MI355X, relative to a 64-wide group sharing its unit: 128-wide 0.9, 64-wide alone
 // 0.55.  With them the estimate picks the faster tile at all twelve cubes measured
 // from 128^3 to 640^3 (us per step, wide / narrow: 224^3 24.8 / 26.4, 256^3 42.3 /
-// 47.0, 288^3 74.8 / 78.3, 512^3 347 / 391, 640^3 690 / 746; narrow kept at 128^3
-// 9.8 / 11.3, 192^3 18.4 / 20.5, 320^3 91.4 / 107, 384^3 160.5 / 162.5, 448^3
-// 248 / 274).  FFPAT_STENCIL2_BX=64 or 128 forces the width.
+// 47.0, 288^3 74.8 / 78.3, 384^3 152.1 / 160.5 (28 planes per group), 512^3 347 /
+// 391, 640^3 690 / 746; narrow / wide where narrow is kept: 128^3 9.8 / 11.3,
+// 192^3 18.4 / 20.5, 320^3 91.4 / 101.9, 448^3 248 / 254).  FFPAT_STENCIL2_BX=64
+// or 128 forces the width.
 template <typename T>
 static bool pair_wide_preferred(const Dims &d, const BlockedConfig &cfg)
 {

@@ -94,16 +94,21 @@ def test_wave_and_transpose(oracle, shape, dtype, variant):
 # FP32 160^3 64 x 16, 16 chunks of 10 planes; FP32 224^3 128 x 16, 9 chunks of 25
 # (last 24); FP64 192^3 64 x 16, 7 of 28 (last 24); FP32 96 x 250 x 250 (nz, ny, nx)
 # 128 x 16 with ragged x and y tails (122 columns, 10 rows), 8 chunks of 12.
-# Short solves (T = 0.04: n_t 8 to 12) keep the oracle quick.
+# 97 x 380 x 383 needs more than one round of groups: the chunk comes from the
+# rounds x (planes + halo) estimate, FP32 128 x 16 with 7 chunks of 14 (last 13,
+# 504 groups), FP64 64 x 16 with 5 chunks of 20 (last 17, 720 groups).
+# Short solves (T = 0.04: n_t 8 to 22) keep the oracle quick.
 MID_SIZES = [((160, 160, 160), F32, (64, 16, 10)), ((224, 224, 224), F32, (128, 16, 25)),
-             ((192, 192, 192), F64, (64, 16, 28)), ((96, 250, 250), F32, (128, 16, 12))]
+             ((192, 192, 192), F64, (64, 16, 28)), ((96, 250, 250), F32, (128, 16, 12)),
+             ((97, 380, 383), F32, (128, 16, 14)), ((97, 380, 383), F64, (64, 16, 20))]
 
 
 def _compute_units():
     return torch.cuda.get_device_properties(0).multi_processor_count
 
 
-@pytest.mark.parametrize("shape,dtype,launch", MID_SIZES, ids=["f32-160", "f32-224", "f64-192", "f32-wide-ragged"])
+@pytest.mark.parametrize("shape,dtype,launch", MID_SIZES,
+                         ids=["f32-160", "f32-224", "f64-192", "f32-wide-ragged", "f32-rounds", "f64-rounds"])
 def test_wave_pairs_mid_size_chunking(oracle, shape, dtype, launch):
     _case_tag(shape, dtype, "pairs-auto")
     k = make_case(shape, 5, T=0.04)
