@@ -85,9 +85,8 @@ typedef struct {
 #define FFPAT_PLAN_SINGLE_STEP 4u     /* one leapfrog step per stencil pass (no temporal blocking) */
 #define FFPAT_PLAN_TWO_STEP 8u        /* two leapfrog steps per stencil pass wherever the chain allows.
                                          With neither of these two flags the plan chooses: two steps per
-                                         pass for grids of 96^3 voxels or more in FP64 and of 128^3 or more
-                                         in FP32, where that kernel is measured faster, one step otherwise.
-                                         Both: EINVAL.
+                                         pass for grids of 128^3 voxels or more, where that kernel is
+                                         measured faster, one step otherwise.  Both: EINVAL.
                                          Planes of 2^31 bytes or more always take one step per pass. */
 
 /* Reconstruction flags (ffpat_fb_params.flags) */

@@ -18,6 +18,7 @@
 
 #include <type_traits>
 
+#include <atomic>
 #include <cfloat>
 #include <cstdlib>
 
@@ -485,9 +486,9 @@ struct BlockedConfig {
 
 static BlockedConfig blocked_config(const Dims &d, size_t esz)
 {
-  // default tile height (measured on MI355X): FP32 8 rows up to 256-wide grids,
-  // 16 rows beyond (fewer halo re-reads once the fields no longer fit in the
-  // 256 MB MALL); FP64 16 rows
+  // default tile height (measured on MI355X): 8 rows up to 256-row grids, 16 rows
+  // beyond (fewer halo re-reads once the fields no longer fit in the 256 MB MALL);
+  // FP64 16 rows from 128 rows on (8 below: more work-groups for small grids)
   static BlockedConfig env = [] {
     BlockedConfig c;
     c.ry = 0;
@@ -508,20 +509,23 @@ static BlockedConfig blocked_config(const Dims &d, size_t esz)
     return c;
   }();
   BlockedConfig cfg = env;
-  if (cfg.ry == 0) cfg.ry = (esz == 8 || d.ny > 256) ? 4 : 2;
+  if (cfg.ry == 0) cfg.ry = (d.ny > 256 || (esz == 8 && d.ny >= 128)) ? 4 : 2;
   return cfg;
 }
 
-// Planes per work-group of the one-step kernel: about cfg.groups work-groups, 4..16
-// planes per group (measured on MI355X: longer chunks lose parallelism, shorter ones
-// re-read more z halo).
+// Planes per work-group of the one-step kernel: about cfg.groups work-groups (the
+// planes rounded to nearest), 1..16 planes per group.  Longer chunks lose
+// parallelism, shorter ones re-read more z halo; below 128^3 parallelism wins.
+// Measured on MI355X, us per step (this rule / the earlier floor of 4 planes):
+// FP32 48^3 4.1 / 7.3, 64^3 4.5 / 8.0, 80^3 6.8 / 8.6, 96^3 8.2 / 9.2, 112^3 9.3 /
+// 10.6; FP64 (tile height 8 below 128 rows) 64^3 4.9 / 11.2, 96^3 9.6 / 12.8.
 static int step_zchunk(const Dims &d, const BlockedConfig &cfg, int tiles_x, int tiles_y)
 {
   int zchunk = cfg.zchunk;
   if (zchunk <= 0) {
     const long xy = (long)tiles_x * tiles_y;
-    const long zc = (long)d.nz * xy / cfg.groups;
-    zchunk = (int)(zc < 4 ? 4 : (zc > 16 ? 16 : zc));
+    const long zc = ((long)d.nz * xy + cfg.groups / 2) / cfg.groups;
+    zchunk = (int)(zc < 1 ? 1 : (zc > 16 ? 16 : zc));
   }
   return zchunk > d.nz ? d.nz : zchunk;
 }
@@ -626,13 +630,21 @@ static int pair_zchunk(int nz, long xy, long resident, int per_cu, int zmax)
   return best;
 }
 
-// Compute units of the current device (0 if the runtime cannot say).
+// Compute units of the current device (0 if the runtime cannot say), cached per
+// device: launches ask for it several times.
 static int device_cus()
 {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 0;
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> cache[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (dev >= 0 && dev < kMaxDevices) {
+    const int c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 0;
+  if (dev >= 0 && dev < kMaxDevices) cache[dev].store(cus, std::memory_order_relaxed);
   return cus;
 }
 
@@ -789,11 +801,12 @@ bool wave_pairs_preferred(const Dims &d, size_t esz)
     return e ? (atoi(e) != 0 ? 1 : 0) : -1;
   }();
   if (env >= 0) return env == 1;
-  // measured on MI355X, us per step one / two steps per pass: FP32 96^3 9.1 / 9.3,
-  // 128^3 10.5 / 9.6, 256^3 49.6 / 47.2, 384^3 198 / 161; FP64 64^3 11.1 / 12.3,
-  // 96^3 12.8 / 12.4, 256^3 111 / 75.1, 384^3 391 / 296.  Smaller grids keep one
-  // step per pass.
-  return d.nvox() >= (esz == 8 ? (size_t)96 * 96 * 96 : (size_t)128 * 128 * 128);
+  // measured on MI355X, us per step one / two steps per pass: FP32 112^3 9.3 / 9.5,
+  // 128^3 10.3 / 9.8, 256^3 49.6 / 42.4, 384^3 198 / 152; FP64 96^3 9.6 / 12.0,
+  // 112^3 11.0 / 12.2, 128^3 13.9 / 13.3, 256^3 111 / 74.4, 384^3 391 / 271.
+  // Smaller grids keep one step per pass.
+  (void)esz;
+  return d.nvox() >= (size_t)128 * 128 * 128;
 }
 
 bool wave_pairs_fit(const Dims &d, size_t esz)
