@@ -76,6 +76,10 @@ class Plan:
     two_step_stencil: None lets the plan choose one or two leapfrog steps per
     stencil pass; True / False force two / one (FFPAT_PLAN_TWO_STEP / _SINGLE_STEP).
     stream: torch stream (or None: the current one) for the plan's set-up.
+
+    After creation: nt, dt, cmax (the time grid), steps_per_pass (1 or 2 leapfrog
+    steps per stencil pass) and stencil_shape (tile width, tile height, z-planes per
+    work-group of that stencil kernel on this device; zeros for the naive kernel).
     """
 
     def __init__(self, c, dx, T, angles, ns=0, ds=0.0, cfl=0.3, ndim=3, naive_stencil=False, use_graphs=True,
