@@ -21,10 +21,10 @@ policy:
 
 On the 120-job trace (grids 64^3..256^3, 50 iterations each, FP32) at 4 jobs/s,
 above the device's capacity for the mix, "shortest" with concurrency 2 beat the
-serial baseline in throughput (+7%), median latency (-40%) and 99th percentile
-(-18%); "fill" gained 3-9% on each.  Below capacity (2 jobs/s) "shortest" still
-halves the median but its 99th percentile is 15% above serial; "fill" keeps
-arrival order.  Most of the work is in the 192^3 and 256^3 jobs, whose kernels
+serial baseline in throughput (+5%), median latency (-34%) and 99th percentile
+(-13%); "fill" gained 3%, 12% and 9%.  Below capacity (2 jobs/s) "shortest" cuts
+the median by a quarter but its 99th percentile is 17% above serial; "fill"
+keeps arrival order and the serial tail.  Most of the work is in the 192^3 and 256^3 jobs, whose kernels
 fill the device by themselves, which bounds what overlap can gain.
 
 Finished jobs release their slot and memory.
