@@ -408,8 +408,8 @@ def main():
     if args.mode == "paper2d":
         return run_paper2d(args)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the sharded design is described in DESIGN.md)"}))
+        print(json.dumps({"error": "ffpat runs on one GPU; --gpus must be 1 "
+                                   "(z-slab sharding across GPUs is designed, not built)"}))
         sys.exit(2)
     import torch
     import paper_1901_06503_amd as ff
