@@ -220,11 +220,15 @@ wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__res
 // A work-group owns a BX x BY tile (BX 64, or 128 in FP32) and a z-chunk.  It
 // marches the stage-1 plane zs from zbeg - 2 to zend + 1; stage 2 follows two
 // planes behind (z = zs - 2).
-// Every thread owns up to PPT points of the extended tile (BX + 4) x (BY + 4)
-// and keeps, per point, p(k) at zs-2..zs+2, q at zs-4..zs and k' at zs-2..zs in
-// registers; LDS holds p(k) of plane zs with a 4-point halo (stage-1 x-y
-// neighbours) and q of the last five planes with a 2-point halo (stage-2 x-y
-// neighbours).  Every ring slot is a plane index modulo 5 and the z loop is
+// Every thread owns up to PPT slots of rows 0..BY+3 of the p(k) plane's LDS
+// region, BX + 8 wide: the extended tile (BX + 4) x (BY + 4) plus the two outer
+// columns on each side, and keeps, per slot, p(k) at zs-2..zs+2 and, per
+// extended-tile point, q at zs-4..zs and k' at zs-2..zs in registers (the outer
+// columns then arrive in the same coalesced row loads; only the two outer rows
+// above and below are loaded apart: 3-4% faster than loading the outer columns
+// point by point, one cache line each).  LDS holds p(k) of plane zs with a
+// 4-point halo (stage-1 x-y neighbours) and q of the last five planes with a
+// 2-point halo (stage-2 x-y neighbours).  Every ring slot is a plane index modulo 5 and the z loop is
 // unrolled ten times, so the slots are fixed registers and LDS offsets (no
 // copies when the window moves).  The loads of plane zs + 2 are issued during
 // plane zs (two buffer sets, alternating), unconditionally (clamped in-grid
@@ -258,12 +262,11 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
   constexpr int BY = 4 * RY;
   constexpr int EX = BX + 4, EY = BY + 4;   // extended tile: stage-1 output region
   constexpr int KX = BX + 8, KY = BY + 8;   // p(k) plane in LDS: stage-1 input region
-  constexpr int NE = EX * EY;
   // threads walk the extended tile with the LDS row pitch KX (the last 4 slots of a
   // row idle), so consecutive lanes address consecutive LDS words across row ends
   constexpr int NES = KX * EY;
   constexpr int PPT = (NES + NTH - 1) / NTH;
-  constexpr int NRING = KX * KY - NE;        // outer 2-point ring of the p(k) plane
+  constexpr int NRING = 4 * KX;              // rows 0, 1, KY-2, KY-1 of the p(k) plane
   constexpr int RPT = (NRING + NTH - 1) / NTH;
   // FP64: the p(k) plane double-buffered by plane parity, so that the next plane's
   // write cannot race this plane's stage-1 reads and one barrier per plane suffices
@@ -298,17 +301,22 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
   // bounds (a point outside reads a neighbour's value and its flag zeroes it).
   int ex[PPT], ey[PPT];
   unsigned boff[PPT];
-  bool ev[PPT], ing[PPT], inter[PPT];
+  bool win[PPT], ev[PPT], ingw[PPT], ing[PPT], inter[PPT];
   T w[PPT][5], r1[PPT][5], kr[PPT][5];
 #pragma unroll
   for (int m = 0; m < PPT; ++m) {
     const int e = threadIdx.x + NTH * m;
+    // ex: column of the p(k) plane in LDS (0..KX-1); every slot of rows 0..EY-1
+    // keeps a p(k) window (the two outer columns on each side only feed the plane),
+    // and the stage-1 points are columns 2..EX+1
     ey[m] = e < NES ? e / KX : 0;
     ex[m] = e < NES ? e - ey[m] * KX : 0;
-    ev[m] = e < NES && ex[m] < EX;
-    const int gx = x0 - 2 + ex[m], gy = y0 - 2 + ey[m];
-    ing[m] = ev[m] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    inter[m] = ing[m] && ex[m] >= 2 && ex[m] < EX - 2 && ey[m] >= 2 && ey[m] < EY - 2;
+    win[m] = e < NES;
+    ev[m] = win[m] && ex[m] >= 2 && ex[m] < EX + 2;
+    const int gx = x0 - 4 + ex[m], gy = y0 - 2 + ey[m];
+    ingw[m] = win[m] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    ing[m] = ev[m] && ingw[m];
+    inter[m] = ing[m] && ex[m] >= 4 && ex[m] < EX && ey[m] >= 2 && ey[m] < EY - 2;
     boff[m] = (unsigned)((min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1)) * sizeof(T));
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -322,7 +330,7 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
       const int zq = zstart + d;
       if (NDIM == 3 && zq >= 0 && zq < nz) {
         const T v = ldb(pk + (size_t)zq * plane, boff[m]);
-        w[m][(d + 5) % 5] = ing[m] ? v : T(0);
+        w[m][(d + 5) % 5] = ingw[m] ? v : T(0);
       }
     }
   }
@@ -337,17 +345,9 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
     const bool rv = e < NRING;
     int lr = 0, lc = 0;
     if (rv) {
-      // rows 0, 1, KY-2, KY-1 (full width), then columns 0, 1, KX-2, KX-1 of rows 2..KY-3
-      if (e < 4 * KX) {
-        const int hr = e / KX;
-        lr = hr < 2 ? hr : KY - 4 + hr;
-        lc = e - hr * KX;
-      } else {
-        const int e2 = e - 4 * KX;
-        const int hc = e2 / (KY - 4);
-        lc = hc < 2 ? hc : KX - 4 + hc;
-        lr = 2 + (e2 - hc * (KY - 4));
-      }
+      const int hr = e / KX;
+      lr = hr < 2 ? hr : KY - 4 + hr;
+      lc = e - hr * KX;
     }
     rl[j] = rv ? lr * KX + lc : -1;
     const int gx = x0 - 4 + lc, gy = y0 - 4 + lr;
@@ -391,12 +391,12 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
     T pv[PPT], kv[PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-      const T v = (ing[m] && zw_in) ? nw[B][m] : T(0);
+      const T v = (ingw[m] && zw_in) ? nw[B][m] : T(0);
       if (NDIM == 3) w[m][Sp2] = v;
       else w[m][S0] = v;
       pv[m] = npv[B][m];   // used only where the point and plane zs are inside the grid
       kv[m] = nkv[B][m];
-      if (ev[m]) lk[B % NLK][(ey[m] + 2) * KX + ex[m] + 2] = w[m][S0];
+      if (win[m]) lk[B % NLK][(ey[m] + 2) * KX + ex[m]] = w[m][S0];
     }
 #pragma unroll
     for (int j = 0; j < RPT; ++j)
@@ -409,7 +409,7 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
       if (!ev[m]) continue;
-      const T *c = &lk[B % NLK][(ey[m] + 2) * KX + ex[m] + 2];
+      const T *c = &lk[B % NLK][(ey[m] + 2) * KX + ex[m]];
       T s1 = (c[-1] + c[1]) + (c[-KX] + c[KX]);
       T s2 = (c[-2] + c[2]) + (c[-2 * KX] + c[2 * KX]);
       if (NDIM == 3) {
