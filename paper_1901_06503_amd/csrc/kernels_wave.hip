@@ -225,11 +225,11 @@ wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__res
 // columns on each side, and keeps, per slot, p(k) at zs-2..zs+2 and, per
 // extended-tile point, q at zs-4..zs and k' at zs-2..zs in registers (the outer
 // columns then arrive in the same coalesced row loads; only the two outer rows
-// above and below are loaded apart: 3-4% faster than loading the outer columns
-// point by point, one cache line each).  LDS holds p(k) of plane zs with a
-// 4-point halo (stage-1 x-y neighbours) and q of the last five planes with a
-// 2-point halo (stage-2 x-y neighbours).  Every ring slot is a plane index modulo 5 and the z loop is
-// unrolled ten times, so the slots are fixed registers and LDS offsets (no
+// above and below are loaded apart: 2.5-5.6% faster at 224^3..512^3 than loading
+// the outer columns point by point, one cache line each).  LDS holds p(k) of plane
+// zs with a 4-point halo (stage-1 x-y neighbours) and q of the last five planes
+// with a 2-point halo (stage-2 x-y neighbours).  Every window slot is a plane
+// index modulo 5 and the z loop is unrolled ten times, so the slots are fixed registers and LDS offsets (no
 // copies when the window moves).  The loads of plane zs + 2 are issued during
 // plane zs (two buffer sets, alternating), unconditionally (clamped in-grid
 // addresses, values masked where used), so they stay in flight across the
@@ -254,6 +254,7 @@ __device__ __forceinline__ void stb(T *base, unsigned boff, T v)
 
 template <typename T, int NDIM, int RY, int NTH, int BX>
 // FP32 with 512 threads: at most 128 VGPRs, so two work-groups share a compute unit
+// (1024 threads allow no more than 128 in any case)
 __global__ void __launch_bounds__(NTH, (sizeof(T) == 4 && NTH >= 512) ? 4 : 1)
 wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__restrict__ q_out,
                    T *__restrict__ o_out, const T *__restrict__ kap, int nx, int ny, int nz, int zchunk, int tiles_x,
@@ -262,8 +263,8 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
   constexpr int BY = 4 * RY;
   constexpr int EX = BX + 4, EY = BY + 4;   // extended tile: stage-1 output region
   constexpr int KX = BX + 8, KY = BY + 8;   // p(k) plane in LDS: stage-1 input region
-  // threads walk the extended tile with the LDS row pitch KX (the last 4 slots of a
-  // row idle), so consecutive lanes address consecutive LDS words across row ends
+  // threads walk rows 0..EY-1 of the LDS region, all KX columns, so consecutive
+  // lanes address consecutive LDS words and consecutive grid points
   constexpr int NES = KX * EY;
   constexpr int PPT = (NES + NTH - 1) / NTH;
   constexpr int NRING = 4 * KX;              // rows 0, 1, KY-2, KY-1 of the p(k) plane
@@ -296,8 +297,8 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
   const size_t plane = (size_t)nx * ny;
   const int zstart = zbeg - 2;              // first stage-1 plane; ring slot of plane p: (p - zstart) mod 5
 
-  // Per point: its place in the extended tile, flags, and the byte offset of its
-  // position within a plane, clamped into the grid so that every load is in
+  // Per slot: its LDS column and extended-tile row, flags, and the byte offset of
+  // its position within a plane, clamped into the grid so that every load is in
   // bounds (a point outside reads a neighbour's value and its flag zeroes it).
   int ex[PPT], ey[PPT];
   unsigned boff[PPT];
