@@ -15,6 +15,7 @@
 //     with a 2-point halo, the four z-neighbours of each column stay in
 //     registers, so every p(k) value is fetched from HBM about once.
 #include "kernels.h"
+#include "launch_rules.h"
 
 #include <type_traits>
 
@@ -510,25 +511,13 @@ static BlockedConfig blocked_config(const Dims &d, size_t esz)
     return c;
   }();
   BlockedConfig cfg = env;
-  if (cfg.ry == 0) cfg.ry = (d.ny > 256 || (esz == 8 && d.ny >= 128)) ? 4 : 2;
+  cfg.ry = step_ry(d.ny, (int)esz, cfg.ry);
   return cfg;
 }
 
-// Planes per work-group of the one-step kernel: about cfg.groups work-groups (the
-// planes rounded to nearest), 1..16 planes per group.  Longer chunks lose
-// parallelism, shorter ones re-read more z halo; below 128^3 parallelism wins.
-// Measured on MI355X, us per step (this rule / the earlier floor of 4 planes):
-// FP32 48^3 4.1 / 7.3, 64^3 4.5 / 8.0, 80^3 6.8 / 8.6, 96^3 8.2 / 9.2, 112^3 9.3 /
-// 10.6; FP64 (tile height 8 below 128 rows) 64^3 4.9 / 11.2, 96^3 9.6 / 12.8.
 static int step_zchunk(const Dims &d, const BlockedConfig &cfg, int tiles_x, int tiles_y)
 {
-  int zchunk = cfg.zchunk;
-  if (zchunk <= 0) {
-    const long xy = (long)tiles_x * tiles_y;
-    const long zc = ((long)d.nz * xy + cfg.groups / 2) / cfg.groups;
-    zchunk = (int)(zc < 1 ? 1 : (zc > 16 ? 16 : zc));
-  }
-  return zchunk > d.nz ? d.nz : zchunk;
+  return ffpat::step_zchunk(d.nz, (long)tiles_x * tiles_y, cfg.groups, cfg.zchunk);
 }
 
 void wave_step_shape(const Dims &d, size_t esz, int *tile_x, int *tile_y, int *zchunk)
@@ -582,55 +571,6 @@ static hipError_t blocked_select(StepMode mode, const Dims &d, const T *p, const
   }
 }
 
-// z-planes a two-step work-group recomputes beyond its chunk (the stage-1 planes
-// on either side), in the launch-time estimates below.
-constexpr int kPairHalo = 4;
-
-// Planes per work-group of the two-step kernel.  Its groups are long (a whole
-// z-chunk each) and all of a launch's groups take about the same time, so a
-// launch runs in rounds of `resident` groups and a last round that is only
-// partly filled costs as much as a full one.  Where every chunk fits in one
-// round at zmax planes or fewer, take as many chunks per x-y tile as fit (8
-// planes at least).  Otherwise, with one group per compute unit, take the chunk
-// that minimises rounds x (planes + halo), the longest on ties; with two per unit
-// (whose short last round runs its groups alone on their units, faster), zmax.
-// Measured on MI355X, us per leapfrog step (this rule / a fixed target of 512
-// FP32 or 256 FP64 groups, which overshot one round by 5-12% at these sizes):
-// FP32 160^3 14.1 / 18.9, 192^3 17.4 / 24.0, 224^3 27.6 (28 planes) / 36.8;
-// FP64 160^3 22.7 / 37.1, 192^3 36.4 / 58.5, 224^3 64.3 / 101.4.  Beyond one round
-// the estimate ranks the chunks as measured (one group per unit, 20..32 planes
-// FP32 128-wide and 40..64 FP64, at 320^3..512^3); its picks, e.g. 128-wide FP32
-// 384^3 28 planes 152.1 us (32: 163.1), FP64 384^3 56 planes 276.5 (64: 296.6),
-// 448^3 50 planes 446.3 (64: 455.4); 64 at 320^3 and 512^3.
-static long pair_rounds(long groups, long resident)
-{
-  return (groups + resident - 1) / resident;
-}
-
-static int pair_zchunk(int nz, long xy, long resident, int per_cu, int zmax)
-{
-  if (xy < 1) xy = 1;
-  const int zlo = nz < 8 ? nz : 8, zhi = nz < zmax ? nz : zmax;
-  const long fit = resident / xy;
-  if (fit >= 1) {
-    const long zc = (nz + fit - 1) / fit;
-    if (zc <= zhi) return (int)(zc < zlo ? zlo : zc);
-  }
-  if (per_cu > 1) return zhi;
-  int best = zhi;
-  long best_cost = 0;
-  for (int zc = zhi; zc >= zlo; --zc) {
-    const int n_zc = (nz + zc - 1) / zc;
-    const int bal = (nz + n_zc - 1) / n_zc;   // the same chunk count with balanced chunks
-    const long cost = pair_rounds(xy * n_zc, resident) * (bal + kPairHalo);
-    if (zc == zhi || cost < best_cost) {
-      best = bal;
-      best_cost = cost;
-    }
-  }
-  return best;
-}
-
 // Compute units of the current device (0 if the runtime cannot say), cached per
 // device: launches ask for it several times.
 static int device_cus()
@@ -649,14 +589,6 @@ static int device_cus()
   return cus;
 }
 
-// Launch shape of one instantiation of the two-step kernel on a grid.
-struct PairShape {
-  int bx, by;              // tile
-  int tiles_x, tiles_y;
-  int zchunk, n_tiles;     // planes per group, groups
-  int per_cu, cus;         // groups a compute unit holds at once, compute units
-};
-
 template <typename T, int NDIM, int RY, int NTH, int BX>
 static PairShape pair_shape(const Dims &d, const BlockedConfig &cfg)
 {
@@ -666,35 +598,10 @@ static PairShape pair_shape(const Dims &d, const BlockedConfig &cfg)
                    hipSuccess ? n : 0;
   }();
   const bool f64 = sizeof(T) == 8;
-  PairShape p;
-  p.bx = BX;
-  p.by = 4 * RY;
-  p.tiles_x = (d.nx + BX - 1) / BX;
-  p.tiles_y = (d.ny + p.by - 1) / p.by;
   // if the runtime cannot say: FP32 with up to 512 threads two groups per unit, else one
-  p.per_cu = occ > 0 ? occ : ((!f64 && NTH <= 512) ? 2 : 1);
+  const int per_cu = occ > 0 ? occ : ((!f64 && NTH <= 512) ? 2 : 1);
   const int cus = device_cus();
-  p.cus = cus > 0 ? cus : 256;
-  int zchunk = cfg.zchunk2 > 0 ? cfg.zchunk2
-                               : pair_zchunk(d.nz, (long)p.tiles_x * p.tiles_y, (long)p.cus * p.per_cu, p.per_cu,
-                                             f64 ? 64 : 32);
-  if (zchunk > d.nz) zchunk = d.nz;
-  p.zchunk = zchunk;
-  p.n_tiles = p.tiles_x * p.tiles_y * ((d.nz + zchunk - 1) / zchunk);
-  return p;
-}
-
-// Estimated duration of a launch: rounds of resident groups times the planes a
-// group computes, in units of one plane of a group.  t_shared: a group's plane
-// time while its compute unit is full; t_alone: in a last round that leaves at
-// most one group per unit.
-static double pair_cost(const PairShape &p, double t_shared, double t_alone)
-{
-  const long resident = (long)p.cus * p.per_cu;
-  const long full = p.n_tiles / resident, rem = p.n_tiles % resident;
-  double t = (double)full * t_shared;
-  if (rem > 0) t += (rem <= p.cus && p.per_cu > 1) ? t_alone : t_shared;
-  return t * (p.zchunk + kPairHalo);
+  return pair_shape_for(d.nx, d.ny, d.nz, BX, 4 * RY, per_cu, cus > 0 ? cus : 256, f64, cfg.zchunk2);
 }
 
 // The instantiations of the two-step kernel: <NDIM, RY (tile height / 4), threads, tile width>.
@@ -705,17 +612,7 @@ enum PairVariant {
 };
 
 // FP32 3D with the default work-group (512 threads, tile 64 x 16): whether the
-// 128 x 16 tile (1024 threads, one group per compute unit) is faster.  The wide tile
-// reads fewer bytes (a 64-wide tile's 2-point x halo costs a whole 128-byte line on
-// each side: at 256^3 the wide tile's L2 fetches are 23% lower) but pads nx to a
-// multiple of 128 and halves the group count.  Plane times of a group measured on
-// MI355X, relative to a 64-wide group sharing its unit: 128-wide 0.9, 64-wide alone
-// 0.55.  With them the estimate picks the faster tile at all twelve cubes measured
-// from 128^3 to 640^3 (us per step, wide / narrow: 224^3 24.8 / 26.4, 256^3 42.3 /
-// 47.0, 288^3 74.8 / 78.3, 384^3 152.1 / 160.5 (28 planes per group), 512^3 347 /
-// 391, 640^3 690 / 746; narrow / wide where narrow is kept: 128^3 9.8 / 11.3,
-// 192^3 18.4 / 20.5, 320^3 91.4 / 101.9, 448^3 248 / 254).  FFPAT_STENCIL2_BX=64
-// or 128 forces the width.
+// 128 x 16 tile (1024 threads) is used; FFPAT_STENCIL2_BX=64 or 128 forces the width.
 template <typename T>
 static bool pair_wide_preferred(const Dims &d, const BlockedConfig &cfg)
 {
@@ -725,8 +622,7 @@ static bool pair_wide_preferred(const Dims &d, const BlockedConfig &cfg)
     if (d.ndim != 3 || cfg.bx2 == 64) return false;
     if (cfg.bx2 == 128) return true;
     if (cfg.threads2 != 512 || (cfg.ry2 > 0 && cfg.ry2 != 4)) return false;
-    return pair_cost(pair_shape<T, 3, 4, 1024, 128>(d, cfg), 0.9, 0.9) <
-           pair_cost(pair_shape<T, 3, 4, 512, 64>(d, cfg), 1.0, 0.55);
+    return pair_wide_better(pair_shape<T, 3, 4, 512, 64>(d, cfg), pair_shape<T, 3, 4, 1024, 128>(d, cfg));
   }
 }
 

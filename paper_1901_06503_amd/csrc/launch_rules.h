@@ -1,0 +1,146 @@
+// Launch-shape rules of the leapfrog stencil kernels: tile height and z-chunk of
+// the one-step kernel, z-chunk and tile width of the two-step kernel.  Plain host
+// arithmetic on the grid, the element size, the device's compute units and the
+// work-groups a unit holds at once (the callers query those from the runtime);
+// nothing here touches the device, so the rules are testable on any host.
+#pragma once
+
+namespace ffpat {
+
+// ---------------------------------------------------------------- one step per pass
+
+// Tile height / 4 of the one-step kernel (measured on MI355X): tiles of 8 rows up to
+// 256-row grids, 16 rows beyond (fewer halo re-reads once the fields no longer fit
+// in the 256 MB MALL); FP64 16 rows from 128 rows on (8 below: more work-groups for
+// small grids).  ry > 0 overrides.
+inline int step_ry(int ny, int esz, int ry)
+{
+  if (ry > 0) return ry;
+  return (ny > 256 || (esz == 8 && ny >= 128)) ? 4 : 2;
+}
+
+// Planes per work-group of the one-step kernel: about `groups` work-groups (the
+// planes rounded to nearest), 1..16 planes per group.  Longer chunks lose
+// parallelism, shorter ones re-read more z halo; below 128^3 parallelism wins.
+// Measured on MI355X, us per step (this rule / the earlier floor of 4 planes):
+// FP32 48^3 4.1 / 7.3, 64^3 4.5 / 8.0, 80^3 6.8 / 8.6, 96^3 8.2 / 9.2, 112^3 9.3 /
+// 10.6; FP64 (tile height 8 below 128 rows) 64^3 4.9 / 11.2, 96^3 9.6 / 12.8.
+// zchunk > 0 overrides (clamped to nz).
+inline int step_zchunk(int nz, long xy, int groups, int zchunk)
+{
+  if (zchunk <= 0) {
+    const long zc = ((long)nz * xy + groups / 2) / groups;
+    zchunk = (int)(zc < 1 ? 1 : (zc > 16 ? 16 : zc));
+  }
+  return zchunk > nz ? nz : zchunk;
+}
+
+// --------------------------------------------------------------- two steps per pass
+
+// z-planes a two-step work-group recomputes beyond its chunk (the stage-1 planes on
+// either side), in the launch-time estimates below.
+constexpr int kPairHalo = 4;
+
+inline long pair_rounds(long groups, long resident)
+{
+  return (groups + resident - 1) / resident;
+}
+
+// Planes per work-group of the two-step kernel.  Its groups are long (a whole
+// z-chunk each) and all of a launch's groups take about the same time, so a launch
+// runs in rounds of `resident` groups and a last round that is only partly filled
+// costs as much as a full one.  Where every chunk fits in one round at zmax planes
+// or fewer, take as many chunks per x-y tile as fit (8 planes at least).
+// Otherwise, with one group per compute unit, take the chunk that minimises
+// rounds x (planes + halo), the longest on ties; with two per unit (whose short
+// last round runs its groups alone on their units, faster), zmax.
+// Measured on MI355X, us per leapfrog step (this rule / a fixed target of 512 FP32
+// or 256 FP64 groups, which overshot one round by 5-12% at these sizes): FP32
+// 160^3 14.1 / 18.9, 192^3 17.4 / 24.0, 224^3 27.6 (28 planes) / 36.8; FP64 160^3
+// 22.7 / 37.1, 192^3 36.4 / 58.5, 224^3 64.3 / 101.4.  Beyond one round the
+// estimate ranks the chunks as measured (one group per unit, 20..32 planes FP32
+// 128-wide and 40..64 FP64, at 320^3..512^3); its picks, e.g. 128-wide FP32 384^3
+// 28 planes 152.1 us (32: 163.1), FP64 384^3 55 planes 274.2 (64: 296.6), 448^3 50
+// planes 446.0 (64: 455.4); 64 at 320^3 and 512^3.
+inline int pair_zchunk(int nz, long xy, long resident, int per_cu, int zmax)
+{
+  if (xy < 1) xy = 1;
+  const int zlo = nz < 8 ? nz : 8, zhi = nz < zmax ? nz : zmax;
+  const long fit = resident / xy;
+  if (fit >= 1) {
+    const long zc = (nz + fit - 1) / fit;
+    if (zc <= zhi) return (int)(zc < zlo ? zlo : zc);
+  }
+  if (per_cu > 1) return zhi;
+  int best = zhi;
+  long best_cost = 0;
+  for (int zc = zhi; zc >= zlo; --zc) {
+    const int n_zc = (nz + zc - 1) / zc;
+    const int bal = (nz + n_zc - 1) / n_zc;   // the same chunk count with balanced chunks
+    const long cost = pair_rounds(xy * n_zc, resident) * (bal + kPairHalo);
+    if (zc == zhi || cost < best_cost) {
+      best = bal;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+// Launch shape of the two-step kernel with a bx x by tile on a grid.
+struct PairShape {
+  int bx, by;              // tile
+  int tiles_x, tiles_y;
+  int zchunk, n_tiles;     // planes per group, groups
+  int per_cu, cus;         // groups a compute unit holds at once, compute units
+};
+
+// zchunk > 0 overrides the chunk rule (clamped to nz).
+inline PairShape pair_shape_for(int nx, int ny, int nz, int bx, int by, int per_cu, int cus, bool f64, int zchunk)
+{
+  PairShape p;
+  p.bx = bx;
+  p.by = by;
+  p.tiles_x = (nx + bx - 1) / bx;
+  p.tiles_y = (ny + by - 1) / by;
+  p.per_cu = per_cu;
+  p.cus = cus;
+  if (zchunk <= 0)
+    zchunk = pair_zchunk(nz, (long)p.tiles_x * p.tiles_y, (long)cus * per_cu, per_cu, f64 ? 64 : 32);
+  if (zchunk > nz) zchunk = nz;
+  p.zchunk = zchunk;
+  p.n_tiles = p.tiles_x * p.tiles_y * ((nz + zchunk - 1) / zchunk);
+  return p;
+}
+
+// Estimated duration of a launch: rounds of resident groups times the planes a
+// group computes, in units of one plane of a group.  t_shared: a group's plane time
+// while its compute unit is full; t_alone: in a last round that leaves at most one
+// group per unit.
+inline double pair_cost(const PairShape &p, double t_shared, double t_alone)
+{
+  const long resident = (long)p.cus * p.per_cu;
+  const long full = p.n_tiles / resident, rem = p.n_tiles % resident;
+  double t = (double)full * t_shared;
+  if (rem > 0) t += (rem <= p.cus && p.per_cu > 1) ? t_alone : t_shared;
+  return t * (p.zchunk + kPairHalo);
+}
+
+// FP32 3D: whether the 128 x 16 tile (1024 threads, one group per compute unit) is
+// faster than 64 x 16 (512 threads, two per unit).  The wide tile reads fewer bytes
+// (a 64-wide tile's 2-point x halo costs a whole 128-byte line on each side: at
+// 256^3 the wide tile's L2 fetches are 23% lower) but pads nx to a multiple of 128
+// and halves the group count.  Plane times of a group measured on MI355X, relative
+// to a 64-wide group sharing its unit: 128-wide 0.9, 64-wide alone 0.55.  With them
+// the estimate picks the faster tile at all twelve cubes measured from 128^3 to
+// 640^3 (us per step, wide / narrow: 224^3 24.8 / 26.4, 256^3 42.3 / 47.0, 288^3
+// 74.8 / 78.3, 384^3 152.1 / 160.5 (28 planes per group), 512^3 347 / 391, 640^3
+// 690 / 746; narrow / wide where narrow is kept: 128^3 9.8 / 11.3, 192^3 18.4 /
+// 20.5, 320^3 91.4 / 101.9, 448^3 248 / 254).  A 64 x 32 tile with 1024 threads was
+// 3-6% faster at 160^3 and 192^3 but 4-6% slower at 224^3 and 448^3 and is not a
+// candidate.
+inline bool pair_wide_better(const PairShape &narrow, const PairShape &wide)
+{
+  return pair_cost(wide, 0.9, 0.9) < pair_cost(narrow, 1.0, 0.55);
+}
+
+}  // namespace ffpat

@@ -1,0 +1,100 @@
+"""Host logic: the launch-shape rules of the leapfrog stencil kernels.
+
+The rules (csrc/launch_rules.h) are plain arithmetic on the grid, the element size,
+the device's compute units and the work-groups a unit holds at once; the library
+feeds them the runtime's figures.  A small C++ driver compiled here with g++ runs
+the same header on the host.  Expected shapes are for MI355X (256 compute units;
+two 64 x 16 FP32 groups per unit, one 128 x 16 FP32 group, one FP64 group): the
+picks that were measured fastest among the candidates swept on that device, and the
+ones the GPU tests assert through ffpat_plan_stencil_shape.
+"""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_1901_06503_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def cli(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("rules") / "launch_rules_cli")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Werror", "-I" + CSRC,
+                    os.path.join(HERE, "launch_rules_cli.cpp"), "-o", exe], check=True)
+    return exe
+
+
+def _run(exe, *args):
+    out = subprocess.run([exe] + [str(a) for a in args], check=True, capture_output=True, text=True).stdout
+    return tuple(int(v) for v in out.split())
+
+
+def pair(exe, nz, ny, nx, f64):
+    return _run(exe, "pair", nx, ny, nz, 8 if f64 else 4, 256, 1 if f64 else 2, 1)
+
+
+# (nz, ny, nx): (tile width, planes per group) on 256 compute units
+PAIR_FP32 = {
+    (128, 128, 128): (64, 8), (160, 160, 160): (64, 10), (192, 192, 192): (64, 14),
+    (224, 224, 224): (128, 25), (256, 256, 256): (128, 32), (288, 288, 288): (128, 32),
+    (320, 320, 320): (64, 32), (384, 384, 384): (128, 28), (448, 448, 448): (64, 32),
+    (512, 512, 512): (128, 32), (640, 640, 640): (128, 32),
+    (96, 250, 250): (128, 12), (97, 380, 383): (128, 14),
+}
+PAIR_FP64 = {
+    (128, 128, 128): 8, (160, 160, 160): 20, (192, 192, 192): 28, (224, 224, 224): 56,
+    (256, 256, 256): 64, (320, 320, 320): 64, (384, 384, 384): 55, (448, 448, 448): 50,
+    (512, 512, 512): 64, (97, 380, 383): 20,
+}
+
+
+@pytest.mark.parametrize("shape", sorted(PAIR_FP32))
+def test_two_step_fp32_tile_and_chunk(cli, shape):
+    bx, by, zc, groups = pair(cli, *shape, f64=False)
+    assert (bx, zc) == PAIR_FP32[shape] and by == 16
+
+
+@pytest.mark.parametrize("shape", sorted(PAIR_FP64))
+def test_two_step_fp64_chunk(cli, shape):
+    bx, by, zc, groups = pair(cli, *shape, f64=True)
+    assert (bx, by, zc) == (64, 16, PAIR_FP64[shape])
+
+
+@pytest.mark.parametrize("n", [128, 160, 192, 224, 256])
+def test_two_step_fills_one_round_where_it_can(cli, n):
+    """Below the point where the longest chunk is needed, the groups fit in one round
+    of resident groups and the chunk is the shortest that does (8 planes at least)."""
+    for f64 in (False, True):
+        bx, by, zc, groups = pair(cli, n, n, n, f64)
+        resident = 256 * (1 if (f64 or bx == 128) else 2)
+        assert groups <= resident
+        if zc > 8:
+            xy = -(-n // bx) * -(-n // by)
+            assert xy * -(-n // (zc - 1)) > resident
+
+
+def test_two_step_handles_thin_grids(cli):
+    """Fewer planes than the minimum chunk: one chunk of all planes."""
+    for nz in (1, 3, 7):
+        bx, by, zc, groups = pair(cli, nz, 200, 300, f64=False)
+        assert zc == nz
+
+
+# (nz, ny, nx, esz): (tile height, planes per group) of the one-step kernel
+STEP = {
+    (256, 256, 256, 4): (8, 16), (384, 384, 384, 4): (16, 16), (64, 64, 64, 4): (8, 1),
+    (112, 112, 112, 4): (8, 2), (64, 64, 64, 8): (8, 1), (256, 256, 256, 8): (16, 8),
+    (48, 48, 48, 8): (8, 1), (3, 40, 40, 4): (8, 1),
+}
+
+
+@pytest.mark.parametrize("key", sorted(STEP))
+def test_one_step_tile_and_chunk(cli, key):
+    nz, ny, nx, esz = key
+    tx, ty, zc = _run(cli, "step", nx, ny, nz, esz)
+    assert (tx, ty, zc) == (64,) + STEP[key]
