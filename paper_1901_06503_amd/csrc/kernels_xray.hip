@@ -155,8 +155,9 @@ project_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__rest
 // read the padded planes, rays marching columns the padded transposes), 32
 // angles of that orientation and 256 detector bins; thread (bin j, quarter s) marches the rays
 // of angles 8s..8s+7.  The marched lines are staged chunk by chunk into LDS
-// with the ZP planes interleaved ([line][position] of ZP-vectors), so the two
-// taps of a crossing in all ZP planes are a few vector LDS reads and the
+// with the ZP planes interleaved ([line][position] of ZP-vectors, in 16-byte
+// slices: FP64 as two arrays of 2-vectors), so the two taps of a crossing in all
+// ZP planes are a few vector LDS reads and the
 // crossing's position and weights serve ZP planes.  Every ray visits every
 // line: the tap index is clamped into the three zero pads on each side, where
 // both taps are zero exactly when the crossing misses the line (the same sums
@@ -169,6 +170,20 @@ struct alignas(ZP * sizeof(T) >= 16 ? 16 : ZP * sizeof(T)) VecZ {
 };
 
 constexpr int kLdsBytes = 139264;   // 136 KiB per work-group (one work-group per compute unit)
+
+// LDS layout of ZP interleaved planes in 16-byte slices: the planes
+// s*SW .. s*SW+SW-1 of position e sit in slice array s (element s*NP + e).  A
+// lane's 16-byte read at position e and its neighbours' at e+1, e+2, ... then
+// fall in consecutive bank groups; one 32-byte vector per position would use
+// every other group and conflict two ways (measured: FP64 projection 13% and
+// FP32 backprojection of 8 planes 17% faster at 256^3 / 256 angles).
+template <typename T, int ZP>
+struct Sliced {
+  static constexpr int SW = ZP * (int)sizeof(T) > 16 ? 16 / (int)sizeof(T) : ZP;   // planes per slice
+  static constexpr int NS = ZP / SW;                                                 // slices
+  using Slice = VecZ<T, SW>;
+  static constexpr int NP = kLdsBytes / (NS * (int)sizeof(Slice));                  // positions
+};
 constexpr int kProjAngles = 32, kProjAnglesPerThread = 8;
 
 template <typename T, int ZP>
@@ -177,8 +192,9 @@ project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__
                    const AngleParams *__restrict__ ap, const int *__restrict__ aorder, int n_row_angles,
                    int n_angles, int nx, int ny, int nz, int ns, int n_groups_rows, int n_groups, int n_work)
 {
-  constexpr int NV = kLdsBytes / sizeof(VecZ<T, ZP>);
-  __shared__ VecZ<T, ZP> lds[NV];
+  using S = Sliced<T, ZP>;
+  constexpr int NV = S::NP, SW = S::SW, NS = S::NS;
+  __shared__ typename S::Slice lds[NS * NV];
   const int b = blockIdx.x;
   const int per_xcd = (n_work + 7) / 8;
   const int t = (b % 8) * per_xcd + b / 8;
@@ -227,10 +243,13 @@ project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__
     const int n_el = rc * LP;
     const size_t off0 = (size_t)c0 * LP;
     for (int e = threadIdx.x; e < n_el; e += 1024) {
-      VecZ<T, ZP> v;
 #pragma unroll
-      for (int q = 0; q < ZP; ++q) v.v[q] = sp[q][off0 + e];
-      lds[e] = v;
+      for (int sl = 0; sl < NS; ++sl) {
+        typename S::Slice v;
+#pragma unroll
+        for (int q = 0; q < SW; ++q) v.v[q] = sp[sl * SW + q][off0 + e];
+        lds[sl * NV + e] = v;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -245,9 +264,13 @@ project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__
           const int i0 = min(max((int)(u >> 32), -3), nm + 1) + kLinePadL;
           const T f = (T)(unsigned)(u & 0xffffffffLL) * T(2.3283064365386963e-10);
           const T e = T(1) - f;
-          const VecZ<T, ZP> v0 = lds[r * LP + i0], v1 = lds[r * LP + i0 + 1];
 #pragma unroll
-          for (int q = 0; q < ZP; ++q) acc[m][q] = fma(f, v1.v[q], fma(e, v0.v[q], acc[m][q]));
+          for (int sl = 0; sl < NS; ++sl) {
+            const typename S::Slice v0 = lds[sl * NV + r * LP + i0], v1 = lds[sl * NV + r * LP + i0 + 1];
+#pragma unroll
+            for (int q = 0; q < SW; ++q)
+              acc[m][sl * SW + q] = fma(f, v1.v[q], fma(e, v0.v[q], acc[m][sl * SW + q]));
+          }
           u += UR;
         }
         U[m] = u;
@@ -260,9 +283,13 @@ project_lds_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__
           const int i0 = (int)fmin(fmax(fl, -3.0), (double)(nm + 1)) + kLinePadL;
           const T f = (T)(u - fl);
           const T e = T(1) - f;
-          const VecZ<T, ZP> v0 = lds[r * LP + i0], v1 = lds[r * LP + i0 + 1];
 #pragma unroll
-          for (int q = 0; q < ZP; ++q) acc[m][q] = fma(f, v1.v[q], fma(e, v0.v[q], acc[m][q]));
+          for (int sl = 0; sl < NS; ++sl) {
+            const typename S::Slice v0 = lds[sl * NV + r * LP + i0], v1 = lds[sl * NV + r * LP + i0 + 1];
+#pragma unroll
+            for (int q = 0; q < SW; ++q)
+              acc[m][sl * SW + q] = fma(f, v1.v[q], fma(e, v0.v[q], acc[m][sl * SW + q]));
+          }
         }
       }
     }
@@ -460,8 +487,10 @@ backproject_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const AngleP
 // work-group owns a 64 x 64 voxel tile in ZP consecutive planes (8 in FP32, 4
 // in FP64); thread (i, kk) accumulates voxels (i, kk + 16 v), v = 0..3, in the
 // ZP planes.  Chunks of angles are staged into LDS with the planes' rows interleaved
-// ([angle][padded bin] of ZP-vectors), so the two taps of a voxel in all ZP
-// planes are a few vector LDS reads; the bin position and weights are computed
+// ([angle][padded bin] of ZP-vectors in 16-byte slices: FP32 8 planes as two
+// arrays of 4-vectors, 17% faster at 256^3 / 256 angles than one 32-byte vector
+// per bin, whose reads conflict two ways; FP64 likewise 5%), so the two taps of a
+// voxel in all ZP planes are a few vector LDS reads; the bin position and weights are computed
 // once per voxel and angle.  Same arithmetic and order as backproject_kernel
 // (angles in order, two FMAs per plane).
 // ---------------------------------------------------------------------------
@@ -471,8 +500,9 @@ backproject_lds_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const An
                        int n_angles, int nx, int ny, int nz, int ns, const T *__restrict__ kap, int tiles_x,
                        int tiles_y, int n_work)
 {
-  constexpr int NV = kLdsBytes / sizeof(VecZ<T, ZP>);
-  __shared__ VecZ<T, ZP> lds[NV];
+  using S = Sliced<T, ZP>;
+  constexpr int NV = S::NP, SW = S::SW, NS = S::NS;
+  __shared__ typename S::Slice lds[NS * NV];
   const int b = blockIdx.x;
   const int per_xcd = (n_work + 7) / 8;
   const int tw = (b % 8) * per_xcd + b / 8;
@@ -500,15 +530,18 @@ backproject_lds_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const An
     for (int e = threadIdx.x; e < ac * RS; e += 1024) {
       const int al = e / RS, jj = e - al * RS;
       const size_t row = (size_t)(a0 + al) * nz;
-      VecZ<T, ZP> v;
 #pragma unroll
-      for (int q = 0; q < ZP; ++q) v.v[q] = gpad[(row + zc[q]) * RS + jj];
-      lds[e] = v;
+      for (int sl = 0; sl < NS; ++sl) {
+        typename S::Slice v;
+#pragma unroll
+        for (int q = 0; q < SW; ++q) v.v[q] = gpad[(row + zc[sl * SW + q]) * RS + jj];
+        lds[sl * NV + e] = v;
+      }
     }
     __syncthreads();
     for (int al = 0; al < ac; ++al) {
       const AngleParams &P = ap[a0 + al];
-      const VecZ<T, ZP> *L = lds + al * RS;
+      const typename S::Slice *L = lds + al * RS;
       if (sizeof(T) == 4) {
         const long long T0 = P.b0_fix + (long long)i * P.bi_fix + (long long)k0 * P.bk_fix;
         const long long BK16 = 16 * P.bk_fix;
@@ -520,9 +553,13 @@ backproject_lds_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const An
           const T f = (T)(unsigned)(Tv & 0xffffffffLL) * T(2.3283064365386963e-10);
           const T w0 = wa * fmax(T(1) - f * ih, T(0));
           const T w1 = wa * fmax(T(1) - (T(1) - f) * ih, T(0));
-          const VecZ<T, ZP> v0 = L[j0], v1 = L[j0 + 1];
 #pragma unroll
-          for (int q = 0; q < ZP; ++q) acc[v][q] = fma(w1, v1.v[q], fma(w0, v0.v[q], acc[v][q]));
+          for (int sl = 0; sl < NS; ++sl) {
+            const typename S::Slice v0 = L[sl * NV + j0], v1 = L[sl * NV + j0 + 1];
+#pragma unroll
+            for (int q = 0; q < SW; ++q)
+              acc[v][sl * SW + q] = fma(w1, v1.v[q], fma(w0, v0.v[q], acc[v][sl * SW + q]));
+          }
         }
       } else {
         const T ih = (T)P.inv_hw, wa = (T)P.w;
@@ -535,9 +572,13 @@ backproject_lds_kernel(const T *__restrict__ gpad, T *__restrict__ vol, const An
           // a clamped bin reads two pads, so the weights do not matter there
           const T w0 = wa * fmax(T(1) - f * ih, T(0));
           const T w1 = wa * fmax(T(1) - (T(1) - f) * ih, T(0));
-          const VecZ<T, ZP> v0 = L[j0], v1 = L[j0 + 1];
 #pragma unroll
-          for (int q = 0; q < ZP; ++q) acc[v][q] = fma(w1, v1.v[q], fma(w0, v0.v[q], acc[v][q]));
+          for (int sl = 0; sl < NS; ++sl) {
+            const typename S::Slice v0 = L[sl * NV + j0], v1 = L[sl * NV + j0 + 1];
+#pragma unroll
+            for (int q = 0; q < SW; ++q)
+              acc[v][sl * SW + q] = fma(w1, v1.v[q], fma(w0, v0.v[q], acc[v][sl * SW + q]));
+          }
         }
       }
     }
