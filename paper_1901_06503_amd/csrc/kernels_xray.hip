@@ -708,29 +708,38 @@ residual_ramp_kernel(const T *g, const T *__restrict__ G, const uint8_t *__restr
   }
 }
 
-// Rows of up to 2048 bins: several rows per 256-thread work-group, each row
-// in LDS with ns + 8 zeros on both sides so that every tap reads without a
-// bounds test; thread t of a row computes the 8 outputs j = t + m tpr (lanes
-// read consecutive LDS words).  Same residual, mask and FP64 partial as
-// residual_ramp_kernel; the partial of a row is summed in thread order.
+// Rows of up to 2048 bins, register windows: thread t of a row computes the 8
+// adjacent outputs j = 8t..8t+7.  For the odd taps n = 1, 3, ... the values
+// r_{j-n} and r_{j+n} of its 8 outputs form two windows of 8 that move by two
+// positions per tap, so each tap loads 4 new values (ring slots fixed by the tap
+// modulo 4) instead of 16.  The row sits in LDS with a zero pad of P (a multiple
+// of 8, at least ns + 8) on both sides and one spare word after every 8 positions
+// (position e at word e + e/8), so that the lanes' reads, 8 positions apart, fall
+// in distinct banks.  Each output's sum runs over the taps in order (centre tap,
+// then n = 1, 3, ... with the left value added to the right), as in
+// residual_ramp_kernel, with the same residual and mask; the row's FP64
+// partial is summed in bin order.  At 256^3 / 256 angles: 0.14 ms FP32, 0.31 ms
+// FP64, against 0.29 / 0.56 ms for 8 outputs per thread strided across the row
+// (16 LDS reads per tap).
 template <typename T>
 __global__ void __launch_bounds__(256)
-residual_ramp8_kernel(const T *g, const T *__restrict__ G, const uint8_t *__restrict__ mask,
-                      const T *__restrict__ taps, T *y, int ns, int rows, int y_stride, int y_off,
-                      double *row_partials)
+residual_ramp_win_kernel(const T *g, const T *__restrict__ G, const uint8_t *__restrict__ mask,
+                         const T *__restrict__ taps, T *y, int ns, int rows, int y_stride, int y_off,
+                         double *row_partials)
 {
   extern __shared__ unsigned char smem_raw[];
   T *lr = reinterpret_cast<T *>(smem_raw);
   __shared__ double red[256];
   const int tpr = (ns + 7) / 8;              // threads per row
   const int rpb = 256 / tpr;                 // rows per work-group
-  const int P = ns + 8;                      // zeros on each side
-  const int W = 2 * P + ns;
+  const int P = ((ns + 8) + 7) / 8 * 8;      // zeros on each side, a multiple of 8
+  const int W = 2 * P + ns;                  // positions of a row
+  const int WP = W + W / 8 + 1;              // words of a row
   const int rl = threadIdx.x / tpr, jt = threadIdx.x - rl * tpr;
   const bool in_group = rl < rpb;
   const size_t row = (size_t)blockIdx.x * rpb + (in_group ? rl : 0);
   const bool act = in_group && row < (size_t)rows;
-  T *R = lr + (in_group ? rl : 0) * W;
+  T *R = lr + (in_group ? rl : 0) * WP;
   if (in_group) {
     const size_t base = row * (size_t)ns;
     for (int e = jt; e < W; e += tpr) {
@@ -741,36 +750,77 @@ residual_ramp8_kernel(const T *g, const T *__restrict__ G, const uint8_t *__rest
         if (G) v -= G[base + j];
         if (mask && !mask[base + j]) v = T(0);
       }
-      R[e] = v;
+      R[e + (e >> 3)] = v;
     }
   }
   __syncthreads();
-  const T *c = R + P + jt;                   // c[m tpr] = r_{jt + m tpr}
-  T acc[8];
+  // word of position P + 8 jt + d for d in [-16, 24): 9 (P/8 + jt) + d + floor(d / 8)
+  const T *cb = R + 9 * (P / 8 + jt);
+  T acc[8], cc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) cc[k] = cb[k];
   if (taps) {
     const T t0 = taps[0];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) acc[m] = t0 * c[m * tpr];
-    for (int n = 1; n < ns; n += 2) {
-      const T tn = taps[n];
+    for (int k = 0; k < 8; ++k) acc[k] = t0 * cc[k];
+    // ring slots: left value at position P + 8 jt + d (d = k - n) in Lr[d mod 8],
+    // right value at P + 8 jt + d (d = k + n) in Rr[d mod 8]
+    T Lr[8], Rr[8];
 #pragma unroll
-      for (int m = 0; m < 8; ++m) acc[m] = fma(tn, c[m * tpr - n] + c[m * tpr + n], acc[m]);
+    for (int k = 0; k < 8; ++k) {
+      const int dl = k - 1, dr = k + 1;      // the windows of n = 1
+      Lr[(dl + 8) % 8] = cb[dl + (dl < 0 ? -1 : 0)];
+      Rr[dr % 8] = cb[dr + (dr >= 8 ? 1 : 0)];
     }
+    const T *lp = cb, *rp = cb;              // move by -9 / +9 words every 4 taps
+    const int nt = ns / 2;                   // odd taps n = 1, 3, ..., < ns
+    int s = 0;
+    auto tap = [&](auto phase) {
+      constexpr int I = decltype(phase)::value;   // s mod 4
+      const T tn = taps[2 * s + 1];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int dl = k - (2 * I + 1), dr = k + (2 * I + 1);
+        acc[k] = fma(tn, Lr[((dl % 8) + 8) % 8] + Rr[((dr % 8) + 8) % 8], acc[k]);
+      }
+      // next tap's new values: left d = -(2 I + 3), -(2 I + 2); right d = 2 I + 9, 2 I + 10
+      // (relative to the pointers, which move by one block of 8 every 4 taps)
+      constexpr int dl0 = -(2 * I + 3), dl1 = -(2 * I + 2), dr0 = 2 * I + 9, dr1 = 2 * I + 10;
+      constexpr int wl0 = dl0 + (dl0 >= 0 ? dl0 / 8 : -((-dl0 + 7) / 8));
+      constexpr int wl1 = dl1 + (dl1 >= 0 ? dl1 / 8 : -((-dl1 + 7) / 8));
+      constexpr int wr0 = dr0 + dr0 / 8, wr1 = dr1 + dr1 / 8;
+      Lr[((dl0 % 8) + 8) % 8] = lp[wl0];
+      Lr[((dl1 % 8) + 8) % 8] = lp[wl1];
+      Rr[dr0 % 8] = rp[wr0];
+      Rr[dr1 % 8] = rp[wr1];
+      ++s;
+    };
+    for (; s + 4 <= nt;) {
+      tap(std::integral_constant<int, 0>{});
+      tap(std::integral_constant<int, 1>{});
+      tap(std::integral_constant<int, 2>{});
+      tap(std::integral_constant<int, 3>{});
+      lp -= 9;
+      rp += 9;
+    }
+    if (s < nt) tap(std::integral_constant<int, 0>{});
+    if (s < nt) tap(std::integral_constant<int, 1>{});
+    if (s < nt) tap(std::integral_constant<int, 2>{});
   } else {
 #pragma unroll
-    for (int m = 0; m < 8; ++m) acc[m] = c[m * tpr];
+    for (int k = 0; k < 8; ++k) acc[k] = cc[k];
   }
   double part = 0.0;
   if (act) {
     const size_t base = row * (size_t)ns;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int j = jt + m * tpr;
+    for (int k = 0; k < 8; ++k) {
+      const int j = 8 * jt + k;
       if (j >= ns) break;
-      T a = acc[m];
+      T a = acc[k];
       if (mask && !mask[base + j]) a = T(0);
       y[row * (size_t)y_stride + y_off + j] = a;
-      part += (double)c[m * tpr] * (double)a;
+      part += (double)cc[k] * (double)a;
     }
   }
   if (!row_partials) return;
@@ -789,10 +839,11 @@ hipError_t launch_residual_ramp(int rows, int ns, const T *g, const T *G, const 
 {
   if (ns <= 2048) {
     const int tpr = (ns + 7) / 8, rpb = 256 / tpr;
-    const size_t shmem = (size_t)rpb * (3 * ns + 16) * sizeof(T);
     const unsigned grid = (unsigned)((rows + rpb - 1) / rpb);
-    residual_ramp8_kernel<T><<<grid, 256, shmem, s>>>(g, G, mask, taps, y, ns, rows, y_stride, y_off,
-                                                      row_partials);
+    const int P = ((ns + 8) + 7) / 8 * 8, W = 2 * P + ns;
+    const size_t shmem = (size_t)rpb * (W + W / 8 + 1) * sizeof(T);
+    residual_ramp_win_kernel<T><<<grid, 256, shmem, s>>>(g, G, mask, taps, y, ns, rows, y_stride, y_off,
+                                                         row_partials);
     return hipGetLastError();
   }
   const size_t shmem = (size_t)ns * sizeof(T);
