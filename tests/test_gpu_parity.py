@@ -173,8 +173,11 @@ def test_project_backproject_work_decompositions(oracle, dtype, layout):
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])
-@pytest.mark.parametrize("ns", [1, 2, 48, 257, 700])
+@pytest.mark.parametrize("ns", [1, 2, 9, 16, 48, 257, 700, 2047, 2048, 2049])
 def test_ramp(oracle, dtype, ns):
+    """Rows of up to 2048 bins take the register-window kernel (several rows per
+    work-group below 129 bins; one row of 256 threads at 2041..2048), longer rows
+    the one-row fallback."""
     k = make_case((5, 8, 8), 4, n_angles=7, ns=ns)
     g = oracle_geom(oracle, k)
     r = rounded(k["rng"].standard_normal(g.data_shape), dtype)
