@@ -151,7 +151,7 @@ project_kernel(const T *__restrict__ padN, const T *__restrict__ padT, T *__rest
 
 // ---------------------------------------------------------------------------
 // Projector with the planes staged in LDS.  A 1024-thread work-group owns ZP
-// consecutive planes (the launch uses 4), one orientation (rays marching rows
+// consecutive planes (the launch uses 8 in FP32, 4 in FP64), one orientation (rays marching rows
 // read the padded planes, rays marching columns the padded transposes), 32
 // angles of that orientation and 256 detector bins; thread (bin j, quarter s) marches the rays
 // of angles 8s..8s+7.  The marched lines are staged chunk by chunk into LDS
@@ -370,13 +370,24 @@ hipError_t launch_project(const Dims &d, int n_angles, int ns, const AngleParams
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int lp_max = (d.nx > d.ny ? d.nx : d.ny) + kLinePadL + kLinePadR;
-  // four planes per work-group: eight (in FP32) measured 14% slower at 256^3 / 256
-  // angles (half the work-groups, half the lines per LDS chunk)
-  if (d.nz >= 4 && lp_max <= kLdsBytes / (int)(4 * sizeof(T)) && xray_lds_enabled()) {
+  // planes per work-group: eight in FP32 from 8 planes on (the crossing's position
+  // and weights serve 8 planes; with the planes in 16-byte LDS slices 5% faster than
+  // four at 256^3 / 256 angles, where one 32-byte vector per position was 14%
+  // slower), else four (FP64: 8 planes of accumulators would not fit the registers)
+  const int zp = (sizeof(T) == 4 && d.nz >= 8 && lp_max <= kLdsBytes / (int)(8 * sizeof(T))) ? 8 : 4;
+  if (d.nz >= 4 && lp_max <= kLdsBytes / (int)(zp * sizeof(T)) && xray_lds_enabled()) {
     const int gr = (n_row_angles + kProjAngles - 1) / kProjAngles;
     const int gc = (n_angles - n_row_angles + kProjAngles - 1) / kProjAngles;
-    const long n_work = (long)(gr + gc) * ((d.nz + 3) / 4) * ((ns + 255) / 256);
+    const long n_work = (long)(gr + gc) * ((d.nz + zp - 1) / zp) * ((ns + 255) / 256);
     const long grid = (n_work + 7) / 8 * 8;
+    if constexpr (sizeof(T) == 4) {
+      if (zp == 8) {
+        project_lds_kernel<T, 8><<<(unsigned)grid, 1024, 0, s>>>(padN, padT, g, ap, aorder, n_row_angles,
+                                                                 n_angles, d.nx, d.ny, d.nz, ns, gr, gr + gc,
+                                                                 (int)n_work);
+        return hipGetLastError();
+      }
+    }
     project_lds_kernel<T, 4><<<(unsigned)grid, 1024, 0, s>>>(padN, padT, g, ap, aorder, n_row_angles, n_angles,
                                                              d.nx, d.ny, d.nz, ns, gr, gr + gc, (int)n_work);
     return hipGetLastError();
