@@ -128,6 +128,18 @@ def test_wave_pairs_mid_size_chunking(oracle, shape, dtype, launch):
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])
+def test_stencil_shape_of_one_step_and_naive_plans(dtype):
+    """ffpat_plan_stencil_shape for the other two stencil kernels: the one-step
+    kernel's 64 x 8 tile with one plane per work-group on a 48^3 grid (about 2048
+    groups would need fewer), and zeros for the unblocked kernel."""
+    k = make_case((48, 48, 48), 6)
+    with gpu_plan(k, dtype, variant="single") as P:
+        assert P.steps_per_pass == 1 and P.stencil_shape == (64, 8, 1)
+    with gpu_plan(k, dtype, variant="naive") as P:
+        assert P.stencil_shape == (0, 0, 0)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("ds_ratio,ns_extra", [(1.0, 0), (0.83, 7), (1.3, -5)])
 def test_project_backproject(oracle, shape, dtype, ds_ratio, ns_extra):
