@@ -8,6 +8,8 @@ import ctypes
 import math
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -107,6 +109,23 @@ def test_null_plan_is_rejected(lib):
     assert lib.ffpat_plan_steps_per_pass(None, ctypes.byref(i32)) == -1
     assert lib.ffpat_plan_stencil_shape(None, ctypes.byref(i32), None, None) == -1
     assert lib.ffpat_plan_destroy(None) == 0
+
+
+def test_plain_c_caller_builds_links_and_runs(lib, tmp_path):
+    # the boundary is C: a C99 program compiled with -pedantic against the header links
+    # the library and gets the documented statuses from the calls that need no device
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    from paper_1901_06503_amd import _lib
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    exe = str(tmp_path / "abi_consumer")
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I" + os.path.dirname(HEADER),
+                    os.path.join(ROOT, "tests", "abi_consumer.c"), "-L" + libdir, "-lffpat",
+                    "-Wl,-rpath," + libdir, "-o", exe], check=True)
+    run = subprocess.run([exe], capture_output=True, text=True)
+    assert run.returncode == 0, run.stdout + run.stderr
+    assert run.stdout.count("ok ") == 9
 
 
 def test_python_binding_fails_loudly_without_library(tmp_path, monkeypatch):
