@@ -574,13 +574,25 @@ int ensure_objective_capacity(ffpat_plan *P, int n, hipStream_t s)
 {
   if (n <= P->obj_cap) return FFPAT_OK;
   const int cap = n > 1024 ? n : 1024;
+  // The captured iteration holds the buffer and its capacity as kernel arguments:
+  // it is captured again after the buffer moves.
+  if (P->g_iter.exec) {
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)hipGraphExecDestroy(P->g_iter.exec);
+    P->g_iter.exec = nullptr;
+  }
   if (P->obj) {
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipFree(P->obj));
     P->obj = nullptr;
     P->obj_cap = 0;
   }
-  HIP_TRY(hipMalloc(&P->obj, sizeof(double) * (size_t)cap));
+  const hipError_t e = hipMalloc(&P->obj, sizeof(double) * (size_t)cap);
+  if (e != hipSuccess) {
+    P->obj = nullptr;
+    (void)hipGetLastError();   // handled here: later launch checks must not see it
+    return fail(FFPAT_ENOMEM, "hipMalloc of %d objective values failed: %s", cap, hipGetErrorString(e));
+  }
   P->obj_cap = cap;
   return FFPAT_OK;
 }
@@ -714,7 +726,11 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
 
   ffpat_plan *P = new (std::nothrow) ffpat_plan();
   if (!P) return fail(FFPAT_ENOMEM, "host allocation failed");
-  HIP_TRY(hipGetDevice(&P->device));
+  hipError_t e = hipGetDevice(&P->device);
+  if (e != hipSuccess) {
+    delete P;
+    return hip_fail(e, "hipGetDevice");
+  }
   P->d = r.d;
   P->dtype = r.dtype;
   P->esz = r.dtype == FFPAT_F64 ? 8 : 4;
@@ -735,10 +751,12 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
   P->rows = r.n_angles * r.d.nz;
   P->lay = layout(r);
 
-  hipError_t e = hipMalloc(&P->base, P->lay.total);
+  e = hipMalloc(&P->base, P->lay.total);
   if (e != hipSuccess) {
+    const size_t total = P->lay.total;
     delete P;
-    return fail(FFPAT_ENOMEM, "hipMalloc(%zu) failed: %s", P->lay.total, hipGetErrorString(e));
+    (void)hipGetLastError();   // handled here: later launch checks must not see it
+    return fail(FFPAT_ENOMEM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
   }
   auto cleanup = [&](int code) {
     (void)hipStreamSynchronize(s);

@@ -56,6 +56,24 @@ def test_graph_replay_equals_eager(dtype):
         assert torch.equal(rg.h, re.h)
 
 
+def test_longer_run_after_a_captured_one_records_its_objective():
+    # 3 iterations capture the iteration graph with the plan's first objective buffer
+    # (1024 values); 1100 iterations with the same G and iterate buffer move it.  The
+    # graph must be captured again: results, history and step equal eager launches.
+    import paper_1901_06503_amd as ff
+    dx, angles, c, h, rng = _inputs(24, 12, 67)
+    with ff.Plan(c, dx, 0.5, angles, use_graphs=True) as Pg, ff.Plan(c, dx, 0.5, angles, use_graphs=False) as Pe:
+        G = _data(Pe, h, rng)
+        hg, he = torch.zeros_like(h), torch.zeros_like(h)
+        for n_iter, plan_step in ((3, False), (1100, True)):
+            rg = Pg.reconstruct(G, 1e-3, n_iter, h0=hg, use_plan_step=plan_step)
+            re = Pe.reconstruct(G, 1e-3, n_iter, h0=he, use_plan_step=plan_step)
+            assert rg.step == re.step
+            assert torch.equal(rg.h, re.h)
+            assert np.array_equal(rg.objective, re.objective)
+            assert np.all(np.isfinite(rg.objective)) and rg.objective[-1] <= rg.objective[0]
+
+
 def test_enqueue_report_equals_reconstruct():
     import paper_1901_06503_amd as ff
     dx, angles, c, h, rng = _inputs(32, 16, 62)
