@@ -36,7 +36,9 @@
  * Argument errors are reported before anything is enqueued.  HIP runtime
  * failures map to FFPAT_EHIP.  ffpat_last_error() gives a thread-local text
  * for the last failure.  A plan is not thread-safe; distinct plans may be
- * used concurrently on distinct streams.
+ * used concurrently on distinct streams.  Every call on a plan uses the
+ * plan's workspace: calls on one plan enqueued on different streams must be
+ * ordered by the caller (events), or they race on the device.
  */
 #ifndef FFPAT_H
 #define FFPAT_H
@@ -56,7 +58,7 @@ typedef enum {
   FFPAT_EHIP = -4,       /* HIP runtime error (text in ffpat_last_error) */
   FFPAT_EDIVERGED = -5,  /* non-finite objective or norm during reconstruction */
   FFPAT_EDTYPE = -6,     /* unknown precision */
-  FFPAT_EBUSY = -7       /* operation not allowed while the plan is in use */
+  FFPAT_EBUSY = -7       /* reserved (not returned by this version) */
 } ffpat_status;
 
 typedef enum { FFPAT_F32 = 0, FFPAT_F64 = 1 } ffpat_dtype;
@@ -76,7 +78,7 @@ typedef struct {
   int32_t ns;             /* detector bins per row; 0 selects nx */
   double ds;              /* detector spacing; 0 selects dx */
   int32_t dtype;          /* ffpat_dtype of every field; reductions are always FP64 */
-  uint32_t flags;         /* FFPAT_PLAN_* */
+  uint32_t flags;         /* FFPAT_PLAN_*; other bits: EINVAL */
 } ffpat_geom;
 
 /* Plan flags */
@@ -104,7 +106,7 @@ typedef struct {
   int32_t n_iter;           /* K >= 0 iterations */
   int32_t n_power;          /* power-iteration steps (0 selects 20) */
   uint32_t flags;           /* FFPAT_POSITIVITY | FFPAT_PRECOND | FFPAT_REG_GRAD | FFPAT_USE_PLAN_STEP |
-                               FFPAT_TWO_STEP; REG_GRAD excludes POSITIVITY */
+                               FFPAT_TWO_STEP; REG_GRAD excludes POSITIVITY; other bits: EINVAL */
   const uint8_t *support;   /* device [nz][ny][nx] mask chi_V (nonzero = inside), or NULL */
   const uint8_t *det_mask;  /* device [n_angles][nz][ns] mask chi_M (nonzero = measured), or NULL */
   double *objective;        /* host array of n_iter values J_k = 1/2<Lambda r_k, r_k> + lambda R(h_k), or NULL */

@@ -190,6 +190,8 @@ int resolve(const ffpat_geom *g, Resolved *r)
   r->ds = ds;
   r->T = g->T;
   r->cfl = cfl;
+  const uint32_t known = FFPAT_PLAN_NAIVE_STENCIL | FFPAT_PLAN_NO_GRAPHS | FFPAT_PLAN_SINGLE_STEP | FFPAT_PLAN_TWO_STEP;
+  if (g->flags & ~known) return fail(FFPAT_EINVAL, "unknown plan flags 0x%x", (unsigned)(g->flags & ~known));
   if ((g->flags & FFPAT_PLAN_SINGLE_STEP) && (g->flags & FFPAT_PLAN_TWO_STEP))
     return fail(FFPAT_EINVAL, "FFPAT_PLAN_SINGLE_STEP and FFPAT_PLAN_TWO_STEP exclude each other");
   r->flags = g->flags;
@@ -986,6 +988,8 @@ static int check_fb_args(ffpat_plan *plan, const void *G_dev, const ffpat_fb_par
   if (!std::isfinite(params->step)) return fail(FFPAT_EINVAL, "step must be finite");
   if (params->cg_maxit < 0 || params->cg_maxit > 100000) return fail(FFPAT_EINVAL, "cg_maxit must be in [0, 100000]");
   if (!(params->cg_tol >= 0) || !std::isfinite(params->cg_tol)) return fail(FFPAT_EINVAL, "cg_tol must be >= 0");
+  const uint32_t known = FFPAT_POSITIVITY | FFPAT_PRECOND | FFPAT_REG_GRAD | FFPAT_USE_PLAN_STEP | FFPAT_TWO_STEP;
+  if (params->flags & ~known) return fail(FFPAT_EINVAL, "unknown flags 0x%x", (unsigned)(params->flags & ~known));
   if ((params->flags & FFPAT_TWO_STEP) && params->det_mask)
     return fail(FFPAT_EINVAL, "FFPAT_TWO_STEP works on volumes: det_mask must be NULL");
   if ((params->flags & FFPAT_REG_GRAD) && (params->flags & FFPAT_POSITIVITY))

@@ -89,6 +89,20 @@ def test_gradient_regulariser_rejects_positivity():
             P.reconstruct(to_dev(G, F64), 1e-3, 1, reg="grad", positivity=True)
 
 
+def test_unknown_reconstruction_flags_are_rejected():
+    import ctypes
+    from paper_1901_06503_amd import _lib
+    g, c, h, G, P = _case((4, 10, 12), 104, 5, F64)
+    with P:
+        Gd, hd = to_dev(G, F64), to_dev(np.zeros_like(h), F64)
+        prm = P._fb_params(Gd, 1e-3, 1, 0.0, 2, True, True, None, None, hd, False, None)
+        prm.flags |= 1 << 10
+        rc = P._lib.ffpat_reconstruct(P._h, ctypes.c_void_p(Gd.data_ptr()), ctypes.byref(prm),
+                                      ctypes.c_void_p(hd.data_ptr()), None, None)
+        assert rc == _lib.EINVAL and b"unknown flags" in P._lib.ffpat_last_error()
+        assert not hd.any()
+
+
 @pytest.mark.parametrize("dtype", [F64, F32])
 def test_landweber_algorithm7(oracle, dtype):
     g, c, h, G, P = _case((8, 22, 26), 105, 12, dtype)
