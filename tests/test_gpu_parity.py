@@ -268,6 +268,30 @@ def test_edge_two_steps_and_tiny_grid(oracle, dtype):
         assert rel_l2(to_np(P.wave_adjoint(to_dev(h, dtype))), oracle.wave_T(g, c, h)) <= TOL_WAVE[dtype]
 
 
+THIN = [(6, 7, 1), (6, 1, 9), (1, 1, 1), (5, 1, 1), (1, 1, 8)]   # (nz, ny, nx)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("shape", THIN)
+def test_edge_grids_one_voxel_wide(oracle, shape, dtype, variant):
+    """Grids one voxel wide in x and/or y (and a single voxel): every stencil
+    neighbour but the centre lies outside, where the field is zero; n_t = 5 (first
+    step, pairs, a single-step tail); one detector bin per row when nx = 1."""
+    _case_tag(shape, dtype, variant)
+    dx = synth.grid_spacing(12)
+    rng = np.random.default_rng(71)
+    k = dict(shape=shape, dx=dx, ds=dx, ns=shape[2], T=0.35, cfl=0.3, c=1.0 + 0.1 * rng.standard_normal(shape),
+             h=rng.standard_normal(shape), angles=np.array([0.0, 0.7, math.pi / 2, 2.4]), rng=rng)
+    g = oracle_geom(oracle, k)
+    c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
+    d = rounded(rng.standard_normal(g.data_shape), dtype)
+    with gpu_plan(k, dtype, variant=variant) as P:
+        assert P.nt == 5
+        assert rel_l2(to_np(P.forward(to_dev(h, dtype))), oracle.forward(g, c, h)) <= TOL_WAVE[dtype]
+        assert rel_l2(to_np(P.adjoint(to_dev(d, dtype))), oracle.adjoint(g, c, d)) <= TOL_WAVE[dtype]
+
+
 @pytest.mark.parametrize("variant", ["pairs", "single"])
 @pytest.mark.parametrize("nt", [1, 2, 3, 4, 5, 6, 7])
 def test_every_step_count(oracle, nt, variant):
