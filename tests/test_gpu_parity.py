@@ -292,6 +292,26 @@ def test_edge_grids_one_voxel_wide(oracle, shape, dtype, variant):
         assert rel_l2(to_np(P.adjoint(to_dev(d, dtype))), oracle.adjoint(g, c, d)) <= TOL_WAVE[dtype]
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_edge_most_planes(oracle, dtype, variant):
+    """nz = 65535, the most planes the boundary accepts (the unblocked stencil and the
+    projector's plane copies launch one grid layer per plane)."""
+    shape = (65535, 2, 3)
+    _case_tag(shape, dtype, variant)
+    dx = synth.grid_spacing(12)
+    rng = np.random.default_rng(73)
+    k = dict(shape=shape, dx=dx, ds=dx, ns=3, T=0.35, cfl=0.3, c=1.0 + 0.1 * rng.standard_normal(shape),
+             h=rng.standard_normal(shape), angles=np.array([0.0, 0.7, math.pi / 2, 2.4]), rng=rng)
+    g = oracle_geom(oracle, k)
+    c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
+    d = rounded(rng.standard_normal(g.data_shape), dtype)
+    with gpu_plan(k, dtype, variant=variant) as P:
+        assert P.nt == 7
+        assert rel_l2(to_np(P.forward(to_dev(h, dtype))), oracle.forward(g, c, h)) <= TOL_WAVE[dtype]
+        assert rel_l2(to_np(P.adjoint(to_dev(d, dtype))), oracle.adjoint(g, c, d)) <= TOL_WAVE[dtype]
+
+
 @pytest.mark.parametrize("variant", ["pairs", "single"])
 @pytest.mark.parametrize("nt", [1, 2, 3, 4, 5, 6, 7])
 def test_every_step_count(oracle, nt, variant):
