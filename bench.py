@@ -39,7 +39,9 @@ def parse():
     ap.add_argument("--stencil", default="auto", choices=["auto", "single", "pairs"],
                     help="--mode wave: leapfrog steps per stencil pass (auto: the plan's choice)")
     ap.add_argument("--seed", type=int, default=3001)
-    ap.add_argument("--mode", default="fb", choices=["fb", "wave", "copy", "serve", "precision", "paper2d"],
+    ap.add_argument("--blocks", type=int, default=0,
+                    help="--mode stream: work-groups per launch (0: the best of 2048, 4096, 8192, 16384)")
+    ap.add_argument("--mode", default="fb", choices=["fb", "wave", "copy", "stream", "serve", "precision", "paper2d"],
                     help="fb: the benchmark; wave: only W_T applications (for counter runs); "
                          "copy: a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--reps", type=int, default=2, help="applications in --mode wave / copies in --mode copy")
@@ -273,6 +275,94 @@ def run_copy_only(args):
                       "reps": args.reps, "GBps_read_plus_write": 8 * n / s / 1e9}))
 
 
+def probe_library():
+    """libffpat_probe.so (streaming-ceiling kernels), or None if it is not built."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1901_06503_amd", "libffpat_probe.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    lib.ffpat_probe_stream.restype = ctypes.c_int
+    lib.ffpat_probe_stream.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 5 + [ctypes.c_size_t, ctypes.c_int,
+                                                                              ctypes.c_void_p]
+    return lib
+
+
+def probe_stream_us(torch, lib, pattern, fields, blocks, reps):
+    """Average duration (us, HIP events on the current stream) of `reps` launches of a
+    streaming pattern over `fields` (five FP32 tensors of one size), rotating the fields
+    so that each launch reads what the previous one wrote."""
+    import ctypes
+    stream = torch.cuda.current_stream()
+    count = fields[0].numel()
+
+    def launch(r):
+        if pattern == 0:
+            ptrs = [fields[(r + i) % 5].data_ptr() for i in range(5)]
+        else:
+            ptrs = [fields[r % 2].data_ptr(), None, None, fields[(r + 1) % 2].data_ptr(), None]
+        rc = lib.ffpat_probe_stream(pattern, *ptrs, count, blocks, ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"ffpat_probe_stream returned {rc}")
+
+    for r in range(3):
+        launch(r)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for r in range(reps):
+        launch(r)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def run_stream(args):
+    """Streaming ceilings (libffpat_probe.so): the two-step stencil's streams (three
+    fields read, two written) and a copy, over FP32 fields of n^3 points (256 and 384,
+    or --n), rotating the five fields so that each launch reads what the previous one
+    wrote, as the leapfrog does.  The best of four launch widths per pattern and size
+    (or --blocks)."""
+    import torch
+    lib = probe_library()
+    if lib is None:
+        raise SystemExit("libffpat_probe.so is missing: build it with `python -m paper_1901_06503_amd.build`")
+    reps = max(args.reps, 10)
+    for n in ([args.n] if args.n else [256, 384]):
+        count = n ** 3
+        f = [torch.zeros(count, dtype=torch.float32, device="cuda") for _ in range(5)]
+        out = {"mode": "stream", "n": n, "bytes_per_field": 4 * count, "reps": reps}
+        for pattern, name, words in ((0, "read3_write2", 5), (1, "read1_write1", 2)):
+            best = None
+            for blocks in ([args.blocks] if args.blocks > 0 else [2048, 4096, 8192, 16384]):
+                us = probe_stream_us(torch, lib, pattern, f, blocks, reps)
+                if best is None or us < best[0]:
+                    best = (us, blocks)
+            out[name] = {"us_per_launch": best[0], "blocks": best[1],
+                         "TBps": words * 4 * count / (best[0] * 1e-6) / 1e12}
+            log(f"stream n={n} {name}: {best[0]:.2f} us, {out[name]['TBps']:.3f} TB/s")
+        print(json.dumps(out))
+        del f
+        torch.cuda.empty_cache()
+
+
+def stream_ceiling(torch, bytes_per_launch, achieved):
+    """The two-step stencil's streams at the workload's field size (three fields read,
+    two written, bytes_per_launch in all) in a plain streaming kernel: what a kernel
+    with these streams can reach on this device, and the stencil's share of it."""
+    lib = probe_library()
+    if lib is None:
+        return None
+    count = bytes_per_launch // 5 // 4
+    f = [torch.zeros(count, dtype=torch.float32, device="cuda") for _ in range(5)]
+    us, blocks = min((probe_stream_us(torch, lib, 0, f, b, 20), b) for b in (8192, 16384))
+    del f
+    torch.cuda.empty_cache()
+    gbps = bytes_per_launch / (us * 1e-6) / 1e9
+    return {"kernel": "read3_write2", "achieved": gbps, "unit": "GB/s", "us_per_launch": us, "blocks": blocks,
+            "frac": achieved / gbps}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -401,6 +491,8 @@ def main():
         return run_wave_only(args)
     if args.mode == "copy":
         return run_copy_only(args)
+    if args.mode == "stream":
+        return run_stream(args)
     if args.mode == "serve":
         return run_serve(args)
     if args.mode == "precision":
@@ -430,6 +522,8 @@ def main():
     gpt = N ** 3 * plan.nt / roof["t_wave"] / 1e9
     log(f"{roof['kernel']} {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s; "
         f"W_T {roof['t_wave'] * 1e3:.2f} ms, {gpt:.1f} Gpt-updates/s")
+    ceiling = stream_ceiling(torch, bytes_per_launch, achieved) if roof["kernel"] == "wave_step2_blocked" else None
+    log(f"streaming ceiling of the same streams: {ceiling}")
 
     fp64 = None
     G_keep = G.cpu() if args.cpu_baseline else None
@@ -492,7 +586,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": roof["kernel"], "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": t_launch * 1e6},
+                     "avg_launch_us": t_launch * 1e6, "stream_ceiling": ceiling},
         "cpu_baseline": cpu,
         "serving": serve,
         "objective_last": float(out.objective[-1]) if len(out.objective) else None,

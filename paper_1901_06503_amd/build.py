@@ -1,4 +1,5 @@
-"""Builds libffpat.so (HIP, gfx950) in-tree from csrc/*.hip.
+"""Builds libffpat.so (HIP, gfx950) in-tree from csrc/*.hip, and beside it
+libffpat_probe.so (the streaming-ceiling kernels the benchmark times).
 
 Usage: python -m paper_1901_06503_amd.build  [--jobs N]
 """
@@ -19,6 +20,8 @@ LIB = os.path.join(HERE, "libffpat.so")
 ARCH = "gfx950"
 
 SOURCES = ["kernels_wave.hip", "kernels_xray.hip", "kernels_fb.hip", "plan.hip"]
+PROBE_LIB = os.path.join(HERE, "libffpat_probe.so")
+PROBE_SOURCES = ["stream_probe.hip"]
 
 # Packed FP32 instructions are disabled on purpose: the compiler forms them from
 # ordinary float code, and some of their forms have produced silently wrong
@@ -44,19 +47,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 4, verbose: bool = False) -> str:
-    """Compiles every source (always, also when a library exists) and links libffpat.so."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib: str):
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC"] + objs + ["-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(jobs: int = 4, verbose: bool = False) -> str:
+    """Compiles every source (always, also when a library exists) and links
+    libffpat.so and libffpat_probe.so."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        objs = list(ex.map(_compile, SOURCES + PROBE_SOURCES))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], PROBE_LIB)
     if verbose:
         print(f"built {LIB}")
+        print(f"built {PROBE_LIB}")
     return LIB
 
 

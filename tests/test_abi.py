@@ -128,6 +128,21 @@ def test_plain_c_caller_builds_links_and_runs(lib, tmp_path):
     assert run.stdout.count("ok ") == 9
 
 
+def test_stream_probe_library_rejects_bad_arguments_before_launching(lib):
+    # the streaming-ceiling kernels the benchmark times live in their own library
+    from paper_1901_06503_amd import build
+    probe = ctypes.CDLL(build.PROBE_LIB)
+    f = probe.ffpat_probe_stream
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 5 + [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    p16 = ctypes.c_void_p(0x1000)
+    assert f(0, p16, None, p16, p16, p16, 1024, 64, None) == -1          # b missing
+    assert f(1, p16, None, None, None, None, 1022, 64, None) == -1       # not a multiple of 4
+    assert f(1, ctypes.c_void_p(0x1004), None, None, p16, None, 1024, 64, None) == -1   # misaligned
+    assert f(1, p16, None, None, p16, None, 1024, 0, None) == -1         # no work-groups
+    assert f(2, p16, p16, p16, p16, p16, 1024, 64, None) == -1           # unknown pattern
+
+
 def test_python_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     from paper_1901_06503_amd import _lib
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
