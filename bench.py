@@ -322,16 +322,17 @@ def run_stream(args):
     fields read, two written) and a copy, over FP32 fields of n^3 points (256 and 384,
     or --n), rotating the five fields so that each launch reads what the previous one
     wrote, as the leapfrog does.  The best of four launch widths per pattern and size
-    (or --blocks)."""
+    (or --blocks).  --dtype float64: fields of the same bytes as n^3 FP64 points."""
     import torch
     lib = probe_library()
     if lib is None:
         raise SystemExit("libffpat_probe.so is missing: build it with `python -m paper_1901_06503_amd.build`")
     reps = max(args.reps, 10)
+    words_per_point = 2 if args.dtype == "float64" else 1
     for n in ([args.n] if args.n else [256, 384]):
-        count = n ** 3
+        count = n ** 3 * words_per_point
         f = [torch.zeros(count, dtype=torch.float32, device="cuda") for _ in range(5)]
-        out = {"mode": "stream", "n": n, "bytes_per_field": 4 * count, "reps": reps}
+        out = {"mode": "stream", "n": n, "dtype": args.dtype, "bytes_per_field": 4 * count, "reps": reps}
         for pattern, name, words in ((0, "read3_write2", 5), (1, "read1_write1", 2)):
             best = None
             for blocks in ([args.blocks] if args.blocks > 0 else [2048, 4096, 8192, 16384]):
