@@ -241,6 +241,31 @@ wave_step_blocked(const T *__restrict__ p, const T *prev, T *out, const T *__res
 // Inputs and outputs are four distinct buffers (neighbouring groups read the
 // inputs in their halos while this group writes).  Requires plane bytes < 2^31.
 // ---------------------------------------------------------------------------
+// Two adjacent FP32 points along x as one 8-byte element (the two-step kernel's FP32
+// form for even nx): loads, stores and LDS accesses move 8 bytes per lane.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// x-direction terms of the stencil at element c: s1 = p(x-1) + p(x+1), s2 = p(x-2) +
+// p(x+2).  One point per element: the neighbouring elements.  Two points per element
+// (x = 2j, 2j+1): the neighbours lie in elements j-1, j and j+1.
+template <typename T>
+struct StencilX {
+  static __device__ __forceinline__ void terms(const T *c, T &s1, T &s2)
+  {
+    s1 = c[-1] + c[1];
+    s2 = c[-2] + c[2];
+  }
+};
+template <>
+struct StencilX<f32x2> {
+  static __device__ __forceinline__ void terms(const f32x2 *c, f32x2 &s1, f32x2 &s2)
+  {
+    const f32x2 l = c[-1], m = c[0], r = c[1];
+    s1 = f32x2{l.y + m.y, m.x + r.x};
+    s2 = f32x2{l.x + r.x, l.y + r.y};
+  }
+};
+
 template <typename T>
 __device__ __forceinline__ T ldb(const T *base, unsigned boff)
 {
@@ -424,8 +449,10 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
     for (int m = 0; m < PPT; ++m) {
       if (!ev[m]) continue;
       const T *c = &lk[B % NLK][(ey[m] + 2) * KX + ex[m]];
-      T s1 = (c[-1] + c[1]) + (c[-KX] + c[KX]);
-      T s2 = (c[-2] + c[2]) + (c[-2 * KX] + c[2 * KX]);
+      T s1, s2;
+      StencilX<T>::terms(c, s1, s2);
+      s1 = s1 + (c[-KX] + c[KX]);
+      s2 = s2 + (c[-2 * KX] + c[2 * KX]);
       if (NDIM == 3) {
         s1 += w[m][Sm1] + w[m][Sp1];
         s2 += w[m][Sm2] + w[m][Sp2];
@@ -450,8 +477,10 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
       for (int m = 0; m < PPT; ++m) {
         if (!inter[m]) continue;
         const T *c = &lq[Sm2][ey[m] * KX + ex[m]];
-        T s1 = (c[-1] + c[1]) + (c[-KX] + c[KX]);
-        T s2 = (c[-2] + c[2]) + (c[-2 * KX] + c[2 * KX]);
+        T s1, s2;
+        StencilX<T>::terms(c, s1, s2);
+        s1 = s1 + (c[-KX] + c[KX]);
+        s2 = s2 + (c[-2 * KX] + c[2 * KX]);
         if (NDIM == 3) {
           s1 += r1[m][Sm3] + r1[m][Sm1];
           s2 += r1[m][Sm4] + r1[m][S0];
@@ -500,6 +529,7 @@ struct BlockedConfig {
   int zchunk2 = 0;   // two-step kernel: planes per work-group (0: from the grid size)
   int threads2 = 512; // two-step kernel: work-group size (256, 512 or 1024)
   int bx2 = 0;       // two-step kernel: tile width (0: chosen per grid; 64, or 128 in FP32 3D)
+  int x2 = -1;       // two-step kernel, FP32 3D, even nx: pairs of x-adjacent points per lane (-1: by the rule)
 };
 
 static BlockedConfig blocked_config(const Dims &d, size_t esz)
@@ -518,6 +548,7 @@ static BlockedConfig blocked_config(const Dims &d, size_t esz)
     if (const char *e = getenv("FFPAT_STENCIL2_RY")) c.ry2 = atoi(e);
     if (const char *e = getenv("FFPAT_STENCIL2_ZCHUNK")) c.zchunk2 = atoi(e);
     if (const char *e = getenv("FFPAT_STENCIL2_BX")) c.bx2 = atoi(e) == 128 ? 128 : (atoi(e) == 64 ? 64 : 0);
+    if (const char *e = getenv("FFPAT_STENCIL2_X2")) c.x2 = atoi(e) ? 1 : 0;
     if (const char *e = getenv("FFPAT_STENCIL2_THREADS")) {
       const int v = atoi(e);
       c.threads2 = v == 1024 ? 1024 : (v == 256 ? 256 : 512);
@@ -679,11 +710,48 @@ static auto visit_pair(PairVariant v, F &&f)
   }
 }
 
+// FP32 3D with even nx, where the 128 x 16 tile is chosen: the two-step kernel over
+// pairs of x-adjacent points, each pair one 8-byte element (the FP64 kernel's shape:
+// 64 x 16 elements, 512 threads, the p(k) plane double-buffered for one barrier per
+// plane).  The grid it sees has nx / 2 columns.  FFPAT_STENCIL2_X2 = 0 or 1 forces
+// the choice (1: every even nx).
+using PairX2 = PairTag<3, 4, 512, 64>;
+
+template <typename T>
+static bool pair_x2(const Dims &d, const BlockedConfig &cfg)
+{
+  if constexpr (sizeof(T) != 4) {
+    return false;
+  } else {
+    if (d.ndim != 3 || d.nx % 2 != 0 || cfg.x2 == 0) return false;
+    return cfg.x2 == 1 || pair_x_pairs(pair_wide_preferred<T>(d, cfg), d.nx);
+  }
+}
+
+static Dims x2_dims(const Dims &d)
+{
+  Dims e = d;
+  e.nx = d.nx / 2;
+  return e;
+}
+
 template <typename T>
 hipError_t launch_wave_pair(const Dims &d, const T *pm1, const T *pk, T *q_out, T *o_out, const T *kap,
                             hipStream_t s)
 {
   const BlockedConfig cfg = blocked_config(d, sizeof(T));
+  if constexpr (sizeof(T) == 4) {
+    if (pair_x2<T>(d, cfg)) {
+      const Dims e = x2_dims(d);
+      const PairShape p = pair_shape<f32x2, PairX2::ndim, PairX2::ry, PairX2::nth, PairX2::bx>(e, cfg);
+      const int grid = ((p.n_tiles + 7) / 8) * 8;
+      wave_step2_blocked<f32x2, PairX2::ndim, PairX2::ry, PairX2::nth, PairX2::bx><<<grid, PairX2::nth, 0, s>>>(
+          reinterpret_cast<const f32x2 *>(pm1), reinterpret_cast<const f32x2 *>(pk),
+          reinterpret_cast<f32x2 *>(q_out), reinterpret_cast<f32x2 *>(o_out), reinterpret_cast<const f32x2 *>(kap),
+          e.nx, e.ny, e.nz, p.zchunk, p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
+      return hipGetLastError();
+    }
+  }
   return visit_pair<T>(pair_variant<T>(d, cfg), [&](auto tag) {
     using Tag = decltype(tag);
     const PairShape p = pair_shape<T, Tag::ndim, Tag::ry, Tag::nth, Tag::bx>(d, cfg);
@@ -698,6 +766,15 @@ template <typename T>
 void wave_pair_shape(const Dims &d, int *tile_x, int *tile_y, int *zchunk)
 {
   const BlockedConfig cfg = blocked_config(d, sizeof(T));
+  if constexpr (sizeof(T) == 4) {
+    if (pair_x2<T>(d, cfg)) {
+      const PairShape p = pair_shape<f32x2, PairX2::ndim, PairX2::ry, PairX2::nth, PairX2::bx>(x2_dims(d), cfg);
+      *tile_x = 2 * p.bx;   // in points
+      *tile_y = p.by;
+      *zchunk = p.zchunk;
+      return;
+    }
+  }
   const PairShape p = visit_pair<T>(pair_variant<T>(d, cfg), [&](auto tag) {
     using Tag = decltype(tag);
     return pair_shape<T, Tag::ndim, Tag::ry, Tag::nth, Tag::bx>(d, cfg);

@@ -86,6 +86,17 @@ inline int pair_zchunk(int nz, long xy, long resident, int per_cu, int zmax)
   return best;
 }
 
+// Longest z-chunk the rule may pick: 64 planes where a compute unit holds one group
+// (FP64, and the FP32 128 x 16 tile), whose groups run in rounds; 32 where it holds
+// two (the FP32 64 x 16 tile, which takes the longest chunk).  Measured on MI355X,
+// 128 x 16 FP32 at 384^3, us per leapfrog step: 28 planes (the longest up to 32
+// by the estimate) 149.0, 40 147.7, 48 150.4, 55 134.2, 64 143.6; the estimate
+// ranks 55 first (7 chunks x 72 tiles: two nearly full rounds).
+inline int pair_zmax(bool f64, int per_cu)
+{
+  return (f64 || per_cu == 1) ? 64 : 32;
+}
+
 // Launch shape of the two-step kernel with a bx x by tile on a grid.
 struct PairShape {
   int bx, by;              // tile
@@ -105,7 +116,7 @@ inline PairShape pair_shape_for(int nx, int ny, int nz, int bx, int by, int per_
   p.per_cu = per_cu;
   p.cus = cus;
   if (zchunk <= 0)
-    zchunk = pair_zchunk(nz, (long)p.tiles_x * p.tiles_y, (long)cus * per_cu, per_cu, f64 ? 64 : 32);
+    zchunk = pair_zchunk(nz, (long)p.tiles_x * p.tiles_y, (long)cus * per_cu, per_cu, pair_zmax(f64, per_cu));
   if (zchunk > nz) zchunk = nz;
   p.zchunk = zchunk;
   p.n_tiles = p.tiles_x * p.tiles_y * ((nz + zchunk - 1) / zchunk);
@@ -141,6 +152,22 @@ inline double pair_cost(const PairShape &p, double t_shared, double t_alone)
 inline bool pair_wide_better(const PairShape &narrow, const PairShape &wide)
 {
   return pair_cost(wide, 0.9, 0.9) < pair_cost(narrow, 1.0, 0.55);
+}
+
+// FP32 3D: whether the two-step kernel runs over pairs of x-adjacent points, each
+// pair one 8-byte element: the FP64 kernel's shape (64 x 16 elements = the 128 x 16
+// tile in points, 512 threads, one group per compute unit, the p(k) plane
+// double-buffered for one barrier per plane) with half the memory and LDS
+// instructions per byte of the one-point form.  Wherever the 128 x 16 tile is chosen
+// and nx is even (the elements then end at the grid's edge).  Measured on MI355X, us
+// per leapfrog step (pairs / one point per lane, both with the chunk rule above):
+// 224^3 26.4 / 26.5, 256^3 41.3 / 42.3, 288^3 72.1 / 74.0, 384^3 131.6 / 134.3,
+// 448^3 228.4 / 236.8 (the 64 x 16 tile: 233.9), 512^3 314.9 / 319.0, 640^3
+// 612.1 / 624.9.  Where the 64 x 16 tile is chosen it is slower (128^3 11.9 / 9.5,
+// 192^3 21.3 / 19.6, 320^3 91.4 / 85.4).
+inline bool pair_x_pairs(bool wide, int nx)
+{
+  return wide && nx % 2 == 0;
 }
 
 }  // namespace ffpat

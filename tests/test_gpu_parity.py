@@ -107,9 +107,13 @@ def test_wave_and_transpose(oracle, shape, dtype, variant):
 # rounds x (planes + halo) estimate, FP32 128 x 16 with 7 chunks of 14 (last 13,
 # 504 groups), FP64 64 x 16 with 5 chunks of 20 (last 17, 720 groups).
 # Short solves (T = 0.04: n_t 8 to 22) keep the oracle quick.
+# (shape, dtype, (tile x in points, tile y, planes per group) on 256 compute units).
+# FP32 grids from 224^3 with even nx run over pairs of x-adjacent points per lane
+# (224^3, 96 x 250 x 250, 257 x 380 x 382), odd nx one point per lane.
 MID_SIZES = [((160, 160, 160), F32, (64, 16, 10)), ((224, 224, 224), F32, (128, 16, 25)),
              ((192, 192, 192), F64, (64, 16, 28)), ((96, 250, 250), F32, (128, 16, 12)),
-             ((97, 380, 383), F32, (128, 16, 14)), ((97, 380, 383), F64, (64, 16, 20))]
+             ((97, 380, 383), F32, (128, 16, 33)), ((97, 380, 383), F64, (64, 16, 20)),
+             ((257, 380, 383), F32, (128, 16, 37)), ((257, 380, 382), F32, (128, 16, 37))]
 
 
 def _compute_units():
@@ -117,7 +121,8 @@ def _compute_units():
 
 
 @pytest.mark.parametrize("shape,dtype,launch", MID_SIZES,
-                         ids=["f32-160", "f32-224", "f64-192", "f32-wide-ragged", "f32-rounds", "f64-rounds"])
+                         ids=["f32-160", "f32-224", "f64-192", "f32-wide-ragged", "f32-odd-nx", "f64-rounds",
+                              "f32-rounds", "f32-pairs-rounds"])
 def test_wave_pairs_mid_size_chunking(oracle, shape, dtype, launch):
     _case_tag(shape, dtype, "pairs-auto")
     k = make_case(shape, 5, T=0.04)
@@ -134,6 +139,27 @@ def test_wave_pairs_mid_size_chunking(oracle, shape, dtype, launch):
         assert rel_l2(p, oracle.wave(g, c, h)) <= TOL_WAVE[dtype]
         q = to_np(P.wave_adjoint(to_dev(h, dtype)))
         assert rel_l2(q, oracle.wave_T(g, c, h)) <= TOL_WAVE[dtype]
+
+
+@pytest.mark.parametrize("nt", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("shape", [(40, 250, 250), (64, 130, 254)])
+def test_pairs_of_points_every_step_count(oracle, shape, nt):
+    """FP32 grids with even nx where the 128 x 16 tile is chosen run over pairs of
+    x-adjacent points per lane: ragged x (125 and 127 pairs over 64-pair tiles) and y
+    tails, several z-chunks, odd and even step counts."""
+    _case_tag(shape, F32, f"pairs-of-points nt={nt}")
+    k = make_case(shape, 17, n_angles=5)
+    cmax = float(rounded(k["c"], F32).max())
+    k["T"] = (nt - 0.5) * k["cfl"] * k["dx"] / cmax
+    g = oracle_geom(oracle, k)
+    c, h = rounded(k["c"], F32), rounded(k["h"], F32)
+    import paper_1901_06503_amd as ff
+    with ff.Plan(to_dev(c, F32), k["dx"], k["T"], k["angles"], cfl=k["cfl"]) as P:
+        assert P.nt == nt and P.steps_per_pass == 2
+        if _compute_units() == 256:
+            assert P.stencil_shape == (128, 16, 8)
+        assert rel_l2(to_np(P.wave(to_dev(h, F32))), oracle.wave(g, c, h)) <= TOL_WAVE[F32]
+        assert rel_l2(to_np(P.wave_adjoint(to_dev(h, F32))), oracle.wave_T(g, c, h)) <= TOL_WAVE[F32]
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])

@@ -38,13 +38,14 @@ def pair(exe, nz, ny, nx, f64):
     return _run(exe, "pair", nx, ny, nz, 8 if f64 else 4, 256, 1 if f64 else 2, 1)
 
 
-# (nz, ny, nx): (tile width, planes per group) on 256 compute units
+# (nz, ny, nx): (tile width in points, planes per group, pairs of x-adjacent points
+# per lane) on 256 compute units
 PAIR_FP32 = {
-    (128, 128, 128): (64, 8), (160, 160, 160): (64, 10), (192, 192, 192): (64, 14),
-    (224, 224, 224): (128, 25), (256, 256, 256): (128, 32), (288, 288, 288): (128, 32),
-    (320, 320, 320): (64, 32), (384, 384, 384): (128, 28), (448, 448, 448): (64, 32),
-    (512, 512, 512): (128, 32), (640, 640, 640): (128, 32),
-    (96, 250, 250): (128, 12), (97, 380, 383): (128, 14),
+    (128, 128, 128): (64, 8, 0), (160, 160, 160): (64, 10, 0), (192, 192, 192): (64, 14, 0),
+    (224, 224, 224): (128, 25, 1), (256, 256, 256): (128, 32, 1), (288, 288, 288): (128, 32, 1),
+    (320, 320, 320): (64, 32, 0), (384, 384, 384): (128, 55, 1), (448, 448, 448): (128, 50, 1),
+    (512, 512, 512): (128, 64, 1), (640, 640, 640): (128, 64, 1),
+    (96, 250, 250): (128, 12, 1), (97, 380, 383): (128, 33, 0),   # odd nx: one point per lane
 }
 PAIR_FP64 = {
     (128, 128, 128): 8, (160, 160, 160): 20, (192, 192, 192): 28, (224, 224, 224): 56,
@@ -55,14 +56,14 @@ PAIR_FP64 = {
 
 @pytest.mark.parametrize("shape", sorted(PAIR_FP32))
 def test_two_step_fp32_tile_and_chunk(cli, shape):
-    bx, by, zc, groups = pair(cli, *shape, f64=False)
-    assert (bx, zc) == PAIR_FP32[shape] and by == 16
+    bx, by, zc, groups, pairs = pair(cli, *shape, f64=False)
+    assert (bx, zc, pairs) == PAIR_FP32[shape] and by == 16
 
 
 @pytest.mark.parametrize("shape", sorted(PAIR_FP64))
 def test_two_step_fp64_chunk(cli, shape):
-    bx, by, zc, groups = pair(cli, *shape, f64=True)
-    assert (bx, by, zc) == (64, 16, PAIR_FP64[shape])
+    bx, by, zc, groups, pairs = pair(cli, *shape, f64=True)
+    assert (bx, by, zc, pairs) == (64, 16, PAIR_FP64[shape], 0)
 
 
 @pytest.mark.parametrize("n", [128, 160, 192, 224, 256])
@@ -70,7 +71,7 @@ def test_two_step_fills_one_round_where_it_can(cli, n):
     """Below the point where the longest chunk is needed, the groups fit in one round
     of resident groups and the chunk is the shortest that does (8 planes at least)."""
     for f64 in (False, True):
-        bx, by, zc, groups = pair(cli, n, n, n, f64)
+        bx, by, zc, groups, _ = pair(cli, n, n, n, f64)
         resident = 256 * (1 if (f64 or bx == 128) else 2)
         assert groups <= resident
         if zc > 8:
@@ -81,7 +82,7 @@ def test_two_step_fills_one_round_where_it_can(cli, n):
 def test_two_step_handles_thin_grids(cli):
     """Fewer planes than the minimum chunk: one chunk of all planes."""
     for nz in (1, 3, 7):
-        bx, by, zc, groups = pair(cli, nz, 200, 300, f64=False)
+        bx, by, zc, groups, _ = pair(cli, nz, 200, 300, f64=False)
         assert zc == nz
 
 
