@@ -146,7 +146,10 @@ inline double pair_cost(const PairShape &p, double t_shared, double t_alone)
 // 640^3 (us per step, wide / narrow: 224^3 24.8 / 26.4, 256^3 42.3 / 47.0, 288^3
 // 74.8 / 78.3, 384^3 152.1 / 160.5 (28 planes per group), 512^3 347 / 391, 640^3
 // 690 / 746; narrow / wide where narrow is kept: 128^3 9.8 / 11.3, 192^3 18.4 /
-// 20.5, 320^3 91.4 / 101.9, 448^3 248 / 254).  A 64 x 32 tile with 1024 threads was
+// 20.5, 320^3 91.4 / 101.9, 448^3 248 / 254; these with chunks of at most 32 planes).
+// With up to 64 planes for the wide tile (pair_zmax) the estimate also takes it at
+// 448^3 (50 planes): 236.8 us per step with one point per lane against 233.9 for the
+// narrow tile, 228.4 with pairs of points per lane (even nx, pair_x_pairs).  A 64 x 32 tile with 1024 threads was
 // 3-6% faster at 160^3 and 192^3 but 4-6% slower at 224^3 and 448^3 and is not a
 // candidate.
 inline bool pair_wide_better(const PairShape &narrow, const PairShape &wide)

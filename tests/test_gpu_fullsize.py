@@ -57,7 +57,8 @@ def test_c256_forward_adjoint_samples(c256, dtype):
     print(f"[fullsize] 256^3 forward/adjoint {dtype}", flush=True)
     with ff.Plan(to_dev(case.c, dtype), case.dx, case.T, case.angles) as P:
         # the benchmark's kernels: two steps per pass; on 256 compute units the FP32
-        # plan takes 128 x 16 tiles, FP64 64 x 16, one z-chunk round each
+        # plan takes 128 x 16 tiles (pairs of x-adjacent points per lane), FP64 64 x 16,
+        # one z-chunk round each
         assert P.steps_per_pass == 2
         if torch.cuda.get_device_properties(0).multi_processor_count == 256:
             assert P.stencil_shape == ((128, 16, 32) if dtype == torch.float32 else (64, 16, 64))

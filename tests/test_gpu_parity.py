@@ -103,13 +103,14 @@ def test_wave_and_transpose(oracle, shape, dtype, variant):
 # FP32 160^3 64 x 16, 16 chunks of 10 planes; FP32 224^3 128 x 16, 9 chunks of 25
 # (last 24); FP64 192^3 64 x 16, 7 of 28 (last 24); FP32 96 x 250 x 250 (nz, ny, nx)
 # 128 x 16 with ragged x and y tails (122 columns, 10 rows), 8 chunks of 12.
-# 97 x 380 x 383 needs more than one round of groups: the chunk comes from the
-# rounds x (planes + halo) estimate, FP32 128 x 16 with 7 chunks of 14 (last 13,
-# 504 groups), FP64 64 x 16 with 5 chunks of 20 (last 17, 720 groups).
+# 97 x 380 x 383: FP32 128 x 16 with 3 chunks of 33 (last 31) in one round, FP64
+# 64 x 16 with 5 chunks of 20 (last 17, 720 groups: the chunk comes from the
+# rounds x (planes + halo) estimate).  257 x 380 x 383 and x 382: FP32 128 x 16 with
+# 7 chunks of 37 (last 35, 504 groups, two rounds).
+# FP32 grids with even nx where the 128 x 16 tile is chosen run over pairs of
+# x-adjacent points per lane (224^3, 96 x 250 x 250, 257 x 380 x 382), odd nx with
+# one point per lane (97 and 257 x 380 x 383).
 # Short solves (T = 0.04: n_t 8 to 22) keep the oracle quick.
-# (shape, dtype, (tile x in points, tile y, planes per group) on 256 compute units).
-# FP32 grids from 224^3 with even nx run over pairs of x-adjacent points per lane
-# (224^3, 96 x 250 x 250, 257 x 380 x 382), odd nx one point per lane.
 MID_SIZES = [((160, 160, 160), F32, (64, 16, 10)), ((224, 224, 224), F32, (128, 16, 25)),
              ((192, 192, 192), F64, (64, 16, 28)), ((96, 250, 250), F32, (128, 16, 12)),
              ((97, 380, 383), F32, (128, 16, 33)), ((97, 380, 383), F64, (64, 16, 20)),
