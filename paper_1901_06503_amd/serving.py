@@ -21,9 +21,9 @@ policy:
 
 On the 120-job trace (grids 64^3..256^3, 50 iterations each, FP32) at 4 jobs/s,
 above the device's capacity for the mix, "shortest" with concurrency 2 beat the
-serial baseline in throughput (+4%), median latency (-31%) and 99th percentile
-(-14%); "fill" gained about 3%, 12% and 9%.  Below capacity (2 jobs/s) "shortest" cuts
-the median by a quarter but its 99th percentile is 17% above serial; "fill"
+serial baseline in throughput (+5%), median latency (-35%) and 99th percentile
+(-15%); "fill" gained about 3%, 14% and 10%.  Below capacity (2 jobs/s) "shortest" cuts
+the median by almost a third but its 99th percentile is 16% above serial; "fill"
 keeps arrival order and the serial tail.  Most of the work is in the 192^3 and 256^3 jobs, whose kernels
 fill the device by themselves, which bounds what overlap can gain.
 
