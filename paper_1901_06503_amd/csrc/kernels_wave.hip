@@ -21,6 +21,7 @@
 
 #include <atomic>
 #include <cfloat>
+#include <cstdint>
 #include <cstdlib>
 
 namespace ffpat {
@@ -741,7 +742,12 @@ hipError_t launch_wave_pair(const Dims &d, const T *pm1, const T *pk, T *q_out, 
 {
   const BlockedConfig cfg = blocked_config(d, sizeof(T));
   if constexpr (sizeof(T) == 4) {
-    if (pair_x2<T>(d, cfg)) {
+    // 8-byte elements need 8-byte aligned fields (a caller's buffer may start at any
+    // float); otherwise one point per lane, with the same tile and chunk
+    const bool aligned = ((reinterpret_cast<uintptr_t>(pm1) | reinterpret_cast<uintptr_t>(pk) |
+                           reinterpret_cast<uintptr_t>(q_out) | reinterpret_cast<uintptr_t>(o_out) |
+                           reinterpret_cast<uintptr_t>(kap)) & 7) == 0;
+    if (aligned && pair_x2<T>(d, cfg)) {
       const Dims e = x2_dims(d);
       const PairShape p = pair_shape<f32x2, PairX2::ndim, PairX2::ry, PairX2::nth, PairX2::bx>(e, cfg);
       const int grid = ((p.n_tiles + 7) / 8) * 8;

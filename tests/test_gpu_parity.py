@@ -163,6 +163,34 @@ def test_pairs_of_points_every_step_count(oracle, shape, nt):
         assert rel_l2(to_np(P.wave_adjoint(to_dev(h, F32))), oracle.wave_T(g, c, h)) <= TOL_WAVE[F32]
 
 
+def test_pairs_of_points_with_buffers_at_odd_float_offsets(oracle):
+    """The pairs-of-points form moves 8 bytes per lane; caller buffers that start at
+    an odd float (contiguous views one float into an allocation) take the one-point
+    form.  Forward with n_t = 5 reads the input as p(k-1) in its first pair and writes
+    the output in its last; the adjoint writes its output in the last single step."""
+    shape = (40, 250, 250)
+    _case_tag(shape, F32, "pairs-of-points odd offsets")
+    k = make_case(shape, 19, n_angles=5)
+    cmax = float(rounded(k["c"], F32).max())
+    k["T"] = 4.5 * k["cfl"] * k["dx"] / cmax
+    g = oracle_geom(oracle, k)
+    c, h = rounded(k["c"], F32), rounded(k["h"], F32)
+    n = h.size
+    import paper_1901_06503_amd as ff
+    with ff.Plan(to_dev(c, F32), k["dx"], k["T"], k["angles"], cfl=k["cfl"]) as P:
+        assert P.nt == 5 and P.steps_per_pass == 2
+        hin = torch.zeros(n + 1, dtype=F32, device="cuda")[1:].view(shape)
+        hin.copy_(to_dev(h, F32))
+        out = torch.zeros(n + 1, dtype=F32, device="cuda")[1:].view(shape)
+        assert hin.data_ptr() % 8 == 4 and out.data_ptr() % 8 == 4
+        P.wave(hin, out=out)
+        assert rel_l2(to_np(out), oracle.wave(g, c, h)) <= TOL_WAVE[F32]
+        P.wave_adjoint(hin, out=out)
+        assert rel_l2(to_np(out), oracle.wave_T(g, c, h)) <= TOL_WAVE[F32]
+        # the same on aligned buffers (pairs of points)
+        assert rel_l2(to_np(P.wave(to_dev(h, F32))), oracle.wave(g, c, h)) <= TOL_WAVE[F32]
+
+
 @pytest.mark.parametrize("dtype", [F64, F32])
 def test_stencil_shape_of_one_step_and_naive_plans(dtype):
     """ffpat_plan_stencil_shape for the other two stencil kernels: the one-step
