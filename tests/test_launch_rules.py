@@ -6,7 +6,9 @@ feeds them the runtime's figures.  A small C++ driver compiled here with g++ run
 the same header on the host.  Expected shapes are for MI355X (256 compute units;
 two 64 x 16 FP32 groups per unit, one 128 x 16 FP32 group, one FP64 group): the
 picks that were measured fastest among the candidates swept on that device, and the
-ones the GPU tests assert through ffpat_plan_stencil_shape.
+ones the GPU tests assert through ffpat_plan_stencil_shape.  The driver also reports
+whether FP32 runs over pairs of x-adjacent points per lane (the 128 x 16 tile with even
+nx; the tile is then given in points and the group count is the pairs kernel's).
 """
 import os
 import shutil
