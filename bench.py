@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1, help="time the oracle on a bounded sample (1/0)")
     ap.add_argument("--naive-stencil", action="store_true")
     ap.add_argument("--n", type=int, default=0, help="--mode wave: grid edge instead of the recipe's")
+    ap.add_argument("--nz", type=int, default=0, help="--mode wave: planes (default: the grid edge)")
     ap.add_argument("--stencil", default="auto", choices=["auto", "single", "pairs"],
                     help="--mode wave: leapfrog steps per stencil pass (auto: the plan's choice)")
     ap.add_argument("--seed", type=int, default=3001)
@@ -231,12 +232,13 @@ def run_wave_only(args):
     dtype = torch.float32 if args.dtype == "float32" else torch.float64
     r = synth.RECIPES[args.recipe]
     n = args.n or r["n"]
+    nz = args.nz or n
     dx = synth.grid_spacing(n)
-    c = synth.sound_speed((n, n, n), dx, np.random.default_rng(args.seed), r["bumps"], r["amp"], r["clamp"])
+    c = synth.sound_speed((nz, n, n), dx, np.random.default_rng(args.seed), r["bumps"], r["amp"], r["clamp"])
     plan = ff.Plan(torch.from_numpy(c).to("cuda", dtype), dx, r["T"], synth.uniform_angles(r["n_angles"]),
                    naive_stencil=args.naive_stencil,
                    two_step_stencil={"auto": None, "single": False, "pairs": True}[args.stencil])
-    h = torch.randn((n, n, n), dtype=dtype, device="cuda")
+    h = torch.randn((nz, n, n), dtype=dtype, device="cuda")
     out = torch.empty_like(h)
     plan.wave(h, out=out)
     torch.cuda.synchronize()
@@ -249,9 +251,9 @@ def run_wave_only(args):
     e1.synchronize()
     us = 1e3 * e0.elapsed_time(e1) / (args.reps * plan.nt)
     env = {k: v for k, v in os.environ.items() if k.startswith("FFPAT_")}
-    print(json.dumps({"mode": "wave", "n": n, "dtype": args.dtype, "nt": plan.nt, "reps": args.reps,
-                      "steps_per_pass": plan.steps_per_pass, "us_per_step": us,
-                      "gpt_updates_per_s": n ** 3 / us / 1e3, "env": env}), flush=True)
+    print(json.dumps({"mode": "wave", "n": n, "nz": nz, "dtype": args.dtype, "nt": plan.nt, "reps": args.reps,
+                      "steps_per_pass": plan.steps_per_pass, "stencil_shape": list(plan.stencil_shape),
+                      "us_per_step": us, "gpt_updates_per_s": nz * n * n / us / 1e3, "env": env}), flush=True)
 
 
 def run_copy_only(args):
