@@ -424,6 +424,33 @@ def test_reconstruct_matches_oracle(oracle, dtype):
     assert np.allclose(res.objective, obj_ref, rtol=tol, atol=0)
 
 
+def test_pairs_of_points_reconstruction_in_graphs(oracle):
+    """Algorithm 8 in FP32 on a grid where the plan takes the pairs-of-points form,
+    its power iteration and FB iterations replayed from captured graphs."""
+    shape = (40, 250, 250)
+    _case_tag(shape, F32, "pairs-of-points reconstruct")
+    k = make_case(shape, 23, n_angles=6)
+    cmax = float(rounded(k["c"], F32).max())
+    k["T"] = 6.5 * k["cfl"] * k["dx"] / cmax
+    k["h"] = np.abs(k["h"])
+    g = oracle_geom(oracle, k)
+    c = rounded(k["c"], F32)
+    clean = oracle.forward(g, c, rounded(k["h"], F32))
+    G = rounded(clean + 0.01 * np.mean(clean) * k["rng"].standard_normal(clean.shape), F32)
+    lam, K = 1e-3, 4
+    h_ref, obj_ref, s_ref = oracle.fb(g, c, G, lam, step=0.0, n_iter=K, n_power=6,
+                                      flags=oracle.POSITIVITY | oracle.PRECOND)
+    import paper_1901_06503_amd as ff
+    with ff.Plan(to_dev(c, F32), k["dx"], k["T"], k["angles"], cfl=k["cfl"]) as P:
+        assert P.nt == 7 and P.steps_per_pass == 2
+        if _compute_units() == 256:
+            assert P.stencil_shape == (128, 16, 8)
+        res = P.reconstruct(to_dev(G, F32), lam, K, step=0.0, n_power=6)
+    assert res.step == pytest.approx(s_ref, rel=1e-4)
+    assert rel_l2(to_np(res.h), h_ref) <= 1e-4
+    assert np.allclose(res.objective, obj_ref, rtol=1e-4, atol=0)
+
+
 @pytest.mark.parametrize("dtype", [F64, F32])
 def test_reconstruct_masks_and_fixed_step(oracle, dtype):
     k, g, c, G = _fb_case(oracle, (12, 21, 34), 9, 11, dtype)
