@@ -181,10 +181,11 @@ class Plan:
         """vol = X^-1 G = X^T Lambda G (filtered backprojection per plane)."""
         return self._call(self._lib.ffpat_fbp, G, self.data_shape, out, self.shape, stream, "G")
 
-    def landweber(self, G, n_iter, step=0.0, n_power=20, det_mask=None, h0=None, stream=None) -> ReconResult:
+    def landweber(self, G, n_iter, step=0.0, n_power=20, det_mask=None, h0=None, use_plan_step=False,
+                  stream=None) -> ReconResult:
         """Algorithm 7, preconditioned Landweber: Algorithm 8 with R = 0 (no prox)."""
         return self.reconstruct(G, 0.0, n_iter, step=step, n_power=n_power, positivity=False, precond=True,
-                                det_mask=det_mask, h0=h0, stream=stream)
+                                det_mask=det_mask, h0=h0, use_plan_step=use_plan_step, stream=stream)
 
     def stripe_mask(self, a):
         """chi_M for M_theta = R minus [-a, a]: 1 where the detector coordinate |s| > a."""

@@ -175,6 +175,14 @@ int resolve(const ffpat_geom *g, Resolved *r)
   const double ds = g->ds == 0 ? g->dx : g->ds;
   if (!(ds > 0) || !std::isfinite(ds)) return fail(FFPAT_EINVAL, "ds must be finite and > 0");
   if (g->dtype != FFPAT_F32 && g->dtype != FFPAT_F64) return fail(FFPAT_EDTYPE, "unknown dtype %d", g->dtype);
+  // the projector addresses a padded plane (and its padded transpose) with 32-bit
+  // byte offsets from the plane's base
+  const size_t esz = g->dtype == FFPAT_F64 ? 8 : 4;
+  const size_t pad_plane_n = (size_t)g->ny * (size_t)(g->nx + kLinePadL + kLinePadR) * esz;
+  const size_t pad_plane_t = (size_t)g->nx * (size_t)(g->ny + kLinePadL + kLinePadR) * esz;
+  if (pad_plane_n >= ((size_t)1 << 32) || pad_plane_t >= ((size_t)1 << 32))
+    return fail(FFPAT_EINVAL, "an x-y plane of %d x %d %s values is too large for one projection pass "
+                "(padded plane of 2^32 bytes or more)", g->nx, g->ny, esz == 8 ? "FP64" : "FP32");
   const size_t nvox = (size_t)g->nx * g->ny * g->nz;
   const size_t ndat = (size_t)g->n_angles * g->nz * ns;
   if (nvox > ((size_t)1 << 33) || ndat > ((size_t)1 << 33)) return fail(FFPAT_EINVAL, "problem too large");

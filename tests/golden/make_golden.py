@@ -2,11 +2,14 @@
 oracle and the seeded input generators (no HIP code).
 
   python tests/golden/make_golden.py c128   # 128^3 reconstruction, 100 iterations
-  python tests/golden/make_golden.py c256   # 256^3 forward / adjoint / gradient samples
+  python tests/golden/make_golden.py c256   # 256^3 forward / adjoint / gradient
   python tests/golden/make_golden.py c384crop  # 64^3 window of the 384^3 workload, 200 iterations
 
-Each fixture is a small JSON text file: the recipe, seeds, sample indices and
-the oracle's values there.
+Each fixture is a JSON text file (the recipe, seeds, sample indices and the
+oracle's values there, scalars) and an .npz file beside it (arrays, loaded with
+numpy's default allow_pickle=False): norms of every row and column of the
+outputs, complete planes next to the z-chunk boundaries of the two-step stencil
+kernel at these sizes, the 32^3 gradient crop and the complete 64^3 window iterate.
 """
 from __future__ import annotations
 
@@ -24,6 +27,12 @@ import oracle  # noqa: E402
 import synth   # noqa: E402
 
 N_SAMPLES = 4096
+
+# z-planes stored whole at 256^3: the grid's first and last plane and both sides of
+# the 32- and 64-plane chunk boundaries (FP32 groups march 32 planes, FP64 64)
+C256_PLANES = (0, 31, 32, 63, 64, 255)
+# 128^3: groups of both precisions march 8 planes; one boundary in the middle
+C128_PLANES = (63, 64)
 
 
 def sample_indices(shape, seed, count=N_SAMPLES):
@@ -51,6 +60,18 @@ def simulate(case, g):
     return G.astype(np.float32).astype(np.float64)
 
 
+def line_norms(a):
+    """L2 norms of a 3D array along its last axis and along its middle axis: for a
+    volume [z][y][x] the norms of every x-row and every y-column of each plane, for
+    data [angle][z][s] those of every detector row and of every (z, s) over angles
+    (axis 0) instead of the middle axis."""
+    return np.sqrt(np.sum(a * a, axis=-1)), np.sqrt(np.sum(a * a, axis=-2))
+
+
+def data_norms(a):
+    return np.sqrt(np.sum(a * a, axis=-1)), np.sqrt(np.sum(a * a, axis=0))
+
+
 def make_c128(seed=2001):
     case = as_f32_values(synth.make_case("c128", seed))
     g = geometry(case)
@@ -60,10 +81,13 @@ def make_c128(seed=2001):
                              flags=oracle.POSITIVITY | oracle.PRECOND)
     idx = sample_indices(g.vol_shape, seed + 1)
     err = float(np.linalg.norm(h - case.h_true) / np.linalg.norm(case.h_true))
-    return {"recipe": "c128", "seed": seed, "sample_seed": seed + 1, "n_iter": case.n_iter, "n_power": case.n_power,
-            "lam": case.lam, "step": step, "objective": obj.tolist(), "h_norm": float(np.linalg.norm(h)),
-            "sample_index": idx.tolist(), "h_sample": h.ravel()[idx].tolist(),
-            "relative_error_vs_phantom": err, "oracle_seconds": time.time() - t0}
+    rows, cols = line_norms(h)
+    arrays = {"h_row_norms": rows, "h_col_norms": cols, "h_planes": h[list(C128_PLANES)]}
+    meta = {"recipe": "c128", "seed": seed, "sample_seed": seed + 1, "n_iter": case.n_iter,
+            "n_power": case.n_power, "lam": case.lam, "step": step, "objective": obj.tolist(),
+            "h_norm": float(np.linalg.norm(h)), "sample_index": idx.tolist(), "h_sample": h.ravel()[idx].tolist(),
+            "planes": list(C128_PLANES), "relative_error_vs_phantom": err, "oracle_seconds": time.time() - t0}
+    return meta, arrays
 
 
 def make_c256(seed=3001):
@@ -76,17 +100,31 @@ def make_c256(seed=3001):
     # gradient of 1/2 ||A h - d||^2 at h = h_true with d = data_rand (both synthetic inputs)
     grad = oracle.adjoint(g, case.c, fwd - data_rand)
     n = case.n
-    c0 = n // 2 - 8
-    crop = grad[c0:c0 + 16, c0:c0 + 16, c0:c0 + 16]
+    m = 32
+    c0 = n // 2 - m // 2
+    crop = grad[c0:c0 + m, c0:c0 + m, c0:c0 + m]
     fi = sample_indices(g.data_shape, seed + 2)
     ai = sample_indices(g.vol_shape, seed + 3)
-    return {"recipe": "c256", "seed": seed, "data_seed": seed + 10, "crop_origin": c0, "crop_size": 16,
+    planes = list(C256_PLANES)
+    f_rows, f_cols = data_norms(fwd)
+    a_rows, a_cols = line_norms(adj)
+    arrays = {
+        # complete planes, rounded to FP32 for size (relative rounding <= 2^-24)
+        "forward_planes": np.ascontiguousarray(fwd[:, planes, :].transpose(1, 0, 2)).astype(np.float32),
+        "adjoint_planes": adj[planes].astype(np.float32),
+        "forward_row_norms": f_rows, "forward_col_norms": f_cols,
+        "adjoint_row_norms": a_rows, "adjoint_col_norms": a_cols,
+        "gradient_crop": crop,
+    }
+    meta = {"recipe": "c256", "seed": seed, "data_seed": seed + 10, "crop_origin": c0, "crop_size": m,
+            "planes": planes,
             "forward_index": fi.tolist(), "forward_sample": fwd.ravel()[fi].tolist(),
             "forward_norm": float(np.linalg.norm(fwd)),
             "adjoint_index": ai.tolist(), "adjoint_sample": adj.ravel()[ai].tolist(),
             "adjoint_norm": float(np.linalg.norm(adj)),
-            "gradient_crop": crop.ravel().tolist(), "gradient_norm": float(np.linalg.norm(grad)),
+            "gradient_norm": float(np.linalg.norm(grad)),
             "oracle_seconds": time.time() - t0}
+    return meta, arrays
 
 
 def make_c384crop(seed=4001):
@@ -101,16 +139,18 @@ def make_c384crop(seed=4001):
                              flags=oracle.POSITIVITY | oracle.PRECOND)
     err = float(np.linalg.norm(h - case.h_true) / np.linalg.norm(case.h_true))
     idx = sample_indices(g.vol_shape, seed + 1, count=8192)
-    return {"recipe": "c384", "window": 64, "seed": seed, "sample_seed": seed + 1, "n_iter": case.n_iter,
+    meta = {"recipe": "c384", "window": 64, "seed": seed, "sample_seed": seed + 1, "n_iter": case.n_iter,
             "n_power": case.n_power, "lam": case.lam, "step": step, "objective": obj.tolist(),
             "h_norm": float(np.linalg.norm(h)), "sample_index": idx.tolist(), "h_sample": h.ravel()[idx].tolist(),
             "relative_error_vs_phantom": err, "oracle_seconds": time.time() - t0}
+    return meta, {"h": h}
 
 
 if __name__ == "__main__":
     which = sys.argv[1]
-    out = {"c128": make_c128, "c256": make_c256, "c384crop": make_c384crop}[which]()
+    meta, arrays = {"c128": make_c128, "c256": make_c256, "c384crop": make_c384crop}[which]()
     path = os.path.join(HERE, f"{which}_oracle.json")
     with open(path, "w") as f:
-        json.dump(out, f)
-    print(f"wrote {path} ({out['oracle_seconds']:.0f} s of oracle time)")
+        json.dump(meta, f)
+    np.savez_compressed(os.path.join(HERE, f"{which}_oracle.npz"), **arrays)
+    print(f"wrote {path} and its .npz ({meta['oracle_seconds']:.0f} s of oracle time)")

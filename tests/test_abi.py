@@ -90,6 +90,24 @@ def test_geometry_validation(lib, kw, status):
         assert lib.ffpat_last_error() != b""
 
 
+@pytest.mark.parametrize("nx,ny,dtype,status", [
+    (32768, 32768, 0, -1),          # padded FP32 plane 4.3e9 bytes: offsets would wrap
+    (32762, 32768, 0, -1),          # 32762 + 6 columns: exactly 2^32 bytes
+    (32761, 32768, 0, 0),           # just below
+    (23170, 23170, 1, -1),          # FP64: 23170 x 23176 x 8 > 2^32
+    (23000, 23000, 1, 0),
+    (1, 1 << 30, 0, -1),            # the transposed copy's lines are the long ones
+])
+def test_planes_too_large_for_32_bit_projector_offsets(lib, nx, ny, dtype, status):
+    """X (eq. Radon) addresses a padded plane with 32-bit byte offsets: geometries
+    whose padded plane reaches 2^32 bytes are rejected on the host."""
+    g, _a = _geom(nx=nx, ny=ny, nz=1, n_angles=4, ns=64, dtype=dtype)
+    out = ctypes.c_size_t()
+    assert lib.ffpat_workspace_bytes(ctypes.byref(g), ctypes.byref(out)) == status
+    if status:
+        assert b"2^32" in lib.ffpat_last_error()
+
+
 def test_plan_create_rejects_before_device_work(lib):
     # invalid geometry with a non-null dummy pointer: rejected on the host, nothing dereferenced
     g, _a = _geom(cfl=0.9)

@@ -24,25 +24,30 @@ F32, F64 = torch.float32, torch.float64
 TOL_FB = {F32: 1e-4, F64: 1e-10}
 
 
-def _case(shape, seed, n_angles, dtype, T=0.4, ndim=3):
+def _case(shape, seed, n_angles, dtype, T=0.4, ndim=3, ds_ratio=1.0):
     import oracle
     import paper_1901_06503_amd as ff
     nz, ny, nx = shape
     dx = synth.grid_spacing(max(nx, ny))
+    ds = ds_ratio * dx
+    ns = nx if ds_ratio == 1.0 else int(math.ceil(nx / ds_ratio)) + 4
     rng = np.random.default_rng(seed)
     c = rounded(synth.sound_speed(shape, dx, rng, 3, 0.2, (0.8, 1.2)), dtype)
     h = rounded(synth.gaussian_smooth(synth.balls(shape, dx, rng, 4), 1.0), dtype)
     angles = synth.uniform_angles(n_angles)
-    g = oracle.Geometry(nx=nx, ny=ny, nz=nz, dx=dx, T=T, angles=angles, ndim=ndim)
+    g = oracle.Geometry(nx=nx, ny=ny, nz=nz, dx=dx, T=T, angles=angles, ndim=ndim, ns=ns, ds=ds)
     G = oracle.forward(g, c, h)
     G = rounded(G + 0.02 * np.mean(G) * rng.standard_normal(G.shape), dtype)
-    P = ff.Plan(to_dev(c, dtype), dx, T, angles, ndim=ndim)
+    P = ff.Plan(to_dev(c, dtype), dx, T, angles, ndim=ndim, ns=ns, ds=ds)
     return g, c, h, G, P
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])
-def test_fbp(oracle, dtype):
-    g, c, h, G, P = _case((6, 33, 40), 101, 21, dtype)
+@pytest.mark.parametrize("ds_ratio", [1.0, 0.83, 1.3])
+def test_fbp(oracle, dtype, ds_ratio):
+    """X^-1 = X^* Lambda; off-grid detector spacings check the filter's scale with
+    the multi-bin (0.83 dx) and two-tap (1.3 dx) backprojection."""
+    g, c, h, G, P = _case((6, 33, 40), 101, 21, dtype, ds_ratio=ds_ratio)
     with P:
         out = to_np(P.fbp(to_dev(G, dtype)))
     assert rel_l2(out, oracle.fbp(g, G)) <= (1e-12 if dtype == F64 else 2e-6)
@@ -113,6 +118,49 @@ def test_landweber_algorithm7(oracle, dtype):
     assert rel_l2(to_np(res.h), h_ref) <= tol
     assert np.allclose(res.objective, obj_ref, rtol=tol, atol=0)
     assert np.all(np.diff(res.objective) < 0)                 # the data misfit decreases
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_landweber_converges_linearly(oracle, dtype):
+    """Algorithm 7 is the linear iteration e_{k+1} = (I - s H) e_k for the error e_k
+    against the least-squares solution, H = A^T Lambda A (Sec. 3.1).  On a tiny grid
+    the dense H comes from the oracle.  H is singular there (few angles), so the
+    error is taken on the span of the eigenvectors with eigenvalue >= mu = L / 4,
+    where the least-squares solution is unique and H commutes with the projection:
+    each GPU iteration shrinks that error by at least rho = max |1 - s lambda| over
+    those eigenvalues (about 3/4 with s from the power iteration), and after K
+    iterations it equals (I - s H)^K e_0 from the dense spectrum."""
+    import paper_1901_06503_amd as ff
+    from test_oracle_fb import dense
+    g = oracle.Geometry(nx=6, ny=6, nz=4, dx=0.1, T=0.25, angles=synth.uniform_angles(6), ns=8)
+    rng = np.random.default_rng(21)
+    c = rounded(rng.uniform(0.85, 1.15, size=g.vol_shape), dtype)
+    A = dense(lambda f: oracle.forward(g, c, f), g.vol_shape)
+    Lam = dense(lambda d: oracle.ramp(g, d), g.data_shape)
+    H = A.T @ Lam @ A
+    lam, U = np.linalg.eigh(0.5 * (H + H.T))
+    G = rounded(rng.normal(size=g.data_shape), dtype)
+    b = A.T @ Lam @ G.ravel()
+    keep = lam >= 0.25 * lam.max()
+    Uk = U[:, keep]
+    h_ls = Uk @ ((Uk.T @ b) / lam[keep])          # least squares on the kept span
+    K = 24
+    with ff.Plan(to_dev(c, dtype), g.dx, g.T, g.angles, ns=g.ns) as P:
+        Gd = to_dev(G, dtype)
+        h = torch.zeros(P.shape, dtype=dtype, device="cuda")
+        s = P.landweber(Gd, 0, n_power=20, h0=h).step     # power iteration only
+        errs = [np.linalg.norm(Uk.T @ (to_np(h).ravel() - h_ls))]
+        for _ in range(K):
+            P.landweber(Gd, 1, h0=h, use_plan_step=True)
+            errs.append(np.linalg.norm(Uk.T @ (to_np(h).ravel() - h_ls)))
+    rho = np.max(np.abs(1.0 - s * lam[keep]))
+    assert 0.5 < rho < 0.9
+    ratios = np.array(errs[1:]) / np.array(errs[:-1])
+    slack = 1e-9 if dtype == F64 else 1e-3
+    assert np.all(ratios <= rho + slack)
+    pred = np.linalg.norm(((1.0 - s * lam[keep]) ** K) * (Uk.T @ (0.0 - h_ls)))
+    assert errs[-1] == pytest.approx(pred, rel=1e-8 if dtype == F64 else 1e-2)
+    assert errs[-1] <= rho ** K * errs[0] * (1 + slack)
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])

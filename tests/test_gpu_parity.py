@@ -28,10 +28,12 @@ SHAPES = [(23, 37, 70), (48, 48, 48), (9, 131, 67)]   # (nz, ny, nx)
 def tol_xt(dtype, n_angles):
     """X^T sums n_angles terms per voxel (Sec. 3.1, X*).  In FP32 the rounding of a
     running sum of terms with random signs leaves a relative error of about
-    u sqrt(n / 6) (u = 2^-24); the bound is 4 u sqrt(n), never below TOL_X."""
+    u sqrt(n / 6) (u = 2^-24); the bound is 4 u sqrt(n), never below TOL_X and never
+    above the 1e-5 required of the FP32 operators (reached at 1750 angles; measured
+    5.9e-6 at 65535)."""
     if dtype == F64:
         return TOL_X[F64]
-    return max(TOL_X[F32], 4 * 2.0 ** -24 * math.sqrt(n_angles))
+    return min(TOL_WAVE[F32], max(TOL_X[F32], 4 * 2.0 ** -24 * math.sqrt(n_angles)))
 
 
 def make_case(shape, seed, n_angles=13, ns=None, ds_ratio=1.0, T=0.35, cfl=0.3):
@@ -259,12 +261,15 @@ def test_project_backproject_work_decompositions(oracle, dtype, layout):
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])
-@pytest.mark.parametrize("ns", [1, 2, 9, 16, 48, 257, 700, 2047, 2048, 2049, 8192])
-def test_ramp(oracle, dtype, ns):
+@pytest.mark.parametrize("ns,ds_ratio", [(1, 1.0), (2, 1.0), (9, 1.0), (16, 1.0), (48, 1.0), (257, 1.0), (700, 1.0),
+                                         (2047, 1.0), (2048, 1.0), (2049, 1.0), (8192, 1.0), (48, 0.83), (257, 1.3)])
+def test_ramp(oracle, dtype, ns, ds_ratio):
     """Rows of up to 2048 bins take the register-window kernel (several rows per
     work-group below 129 bins; one row of 256 threads at 2041..2048), longer rows
-    the one-row fallback, up to the largest accepted row (8192 bins)."""
-    k = make_case((5, 8, 8), 4, n_angles=7, ns=ns)
+    the one-row fallback, up to the largest accepted row (8192 bins).  Detector
+    spacings off the grid spacing check the filter's scale, pi / (N_angles dx^2)
+    for any ds."""
+    k = make_case((5, 8, 8), 4, n_angles=7, ns=ns, ds_ratio=ds_ratio)
     g = oracle_geom(oracle, k)
     r = rounded(k["rng"].standard_normal(g.data_shape), dtype)
     ref = oracle.ramp(g, r)
@@ -400,8 +405,8 @@ def test_two_dimensional_mode(oracle, dtype, variant):
 
 
 # ---------------------------------------------------------------- Algorithm 8
-def _fb_case(oracle, shape, n_angles, seed, dtype, eta=0.01):
-    k = make_case(shape, seed, n_angles=n_angles, T=0.5)
+def _fb_case(oracle, shape, n_angles, seed, dtype, eta=0.01, ds_ratio=1.0, ns_extra=0):
+    k = make_case(shape, seed, n_angles=n_angles, T=0.5, ds_ratio=ds_ratio, ns=shape[2] + ns_extra)
     k["h"] = np.abs(k["h"])
     g = oracle_geom(oracle, k)
     c = rounded(k["c"], dtype)
@@ -411,8 +416,12 @@ def _fb_case(oracle, shape, n_angles, seed, dtype, eta=0.01):
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])
-def test_reconstruct_matches_oracle(oracle, dtype):
-    k, g, c, G = _fb_case(oracle, (20, 26, 30), 16, 10, dtype)
+@pytest.mark.parametrize("ds_ratio,ns_extra", [(1.0, 0), (0.83, 7), (1.3, -5)])
+def test_reconstruct_matches_oracle(oracle, dtype, ds_ratio, ns_extra):
+    """Algorithm 8 with the ramp preconditioner; detector spacings 0.83 dx (footprints
+    over several bins) and 1.3 dx put the filter's scale and the multi-bin
+    backprojection inside the iteration and the power-iteration step."""
+    k, g, c, G = _fb_case(oracle, (20, 26, 30), 16, 10, dtype, ds_ratio=ds_ratio, ns_extra=ns_extra)
     lam, K = 1e-3, 5
     h_ref, obj_ref, s_ref = oracle.fb(g, c, G, lam, step=0.0, n_iter=K, n_power=20,
                                       flags=oracle.POSITIVITY | oracle.PRECOND)

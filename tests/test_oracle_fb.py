@@ -72,6 +72,29 @@ def test_fb_without_constraint_converges_to_normal_equations(oracle, problem):
     assert np.all(np.diff(obj) <= 1e-12 * abs(obj[0]))   # FB with s <= 1/L decreases the objective
 
 
+def test_landweber_converges_linearly_on_the_well_conditioned_span(oracle, problem):
+    """Algorithm 7 (Sec. 3.1) without regulariser or constraint is the linear iteration
+    e_{k+1} = (I - s H) e_k, H = A^T Lambda A.  On the span of the eigenvectors with
+    eigenvalue >= L / 4 (H is singular on this grid) the error shrinks every step by
+    at least rho = max |1 - s lambda| there, and equals (I - s H)^k e_0."""
+    g, c, H, A, Lam, G = (problem[k] for k in ("g", "c", "H", "A", "Lam", "G"))
+    lam, U = np.linalg.eigh(H)
+    keep = lam >= 0.25 * lam.max()
+    Uk = U[:, keep]
+    b = A.T @ Lam @ G.ravel()
+    h_ls = Uk @ ((Uk.T @ b) / lam[keep])
+    _, _, s = oracle.fb(g, c, G, 0.0, step=0.0, n_iter=0, n_power=20, flags=oracle.PRECOND)
+    errs = []
+    for k in range(0, 21, 4):
+        h, _, _ = oracle.fb(g, c, G, 0.0, step=s, n_iter=k, flags=oracle.PRECOND)
+        errs.append(np.linalg.norm(Uk.T @ (h.ravel() - h_ls)))
+    rho = np.max(np.abs(1.0 - s * lam[keep]))
+    assert 0.5 < rho < 0.9
+    assert np.all(np.array(errs[1:]) <= rho ** 4 * np.array(errs[:-1]) * (1 + 1e-10))
+    pred = np.linalg.norm(((1.0 - s * lam[keep]) ** 20) * (Uk.T @ h_ls))
+    assert errs[-1] == pytest.approx(pred, rel=1e-9)
+
+
 def test_fb_with_positivity_satisfies_kkt(oracle, problem):
     g, c, H, A, Lam, G = (problem[k] for k in ("g", "c", "H", "A", "Lam", "G"))
     lam_max = np.linalg.eigvalsh(H).max()
@@ -179,6 +202,25 @@ def test_fbp_inverts_the_xray_transform_on_smooth_objects(oracle):
     inner = np.hypot(*np.meshgrid(synth.axis(n, dx), synth.axis(n, dx))) < 1.0
     for z in range(2):
         assert rel_l2(rec[z][inner], vol[z][inner]) < 0.05
+
+
+@pytest.mark.parametrize("ratio", [0.83, 1.3])
+def test_fbp_inverts_with_off_grid_detector_spacing(oracle, ratio):
+    """X^-1 = X^* Lambda with detector bins ds = ratio * dx (0.83: footprints wider
+    than one bin, several taps per voxel; 1.3: at most two); the scale of the
+    inverse does not depend on ds."""
+    n = 64
+    dx = synth.grid_spacing(n)
+    ds = ratio * dx
+    ns = int(math.ceil(n * dx / ds)) + 8
+    g = oracle.Geometry(nx=n, ny=n, nz=2, dx=dx, T=0.1, angles=synth.uniform_angles(96), ns=ns, ds=ds)
+    vol = synth.gaussian_blob(g.vol_shape, dx, (-0.15, 0.2, 0.0), 4 * dx)
+    rec = oracle.fbp(g, oracle.project(g, vol))
+    inner = np.hypot(*np.meshgrid(synth.axis(n, dx), synth.axis(n, dx))) < 1.0
+    for z in range(2):
+        r, v = rec[z][inner], vol[z][inner]
+        assert np.vdot(r, v) / np.vdot(r, r) == pytest.approx(1.0, abs=0.02)
+        assert rel_l2(r, v) < 0.08
 
 
 @pytest.fixture(scope="module")
