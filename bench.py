@@ -59,8 +59,12 @@ def parse():
     ap.add_argument("--concurrency", type=int, default=2,
                     help="--mode serve, policy shortest: jobs advancing at a time")
     ap.add_argument("--serial", type=int, default=1, help="--mode serve: also run the serial baseline (1/0)")
-    ap.add_argument("--serve-jobs", type=int, default=40,
-                    help="--mode fb: jobs in the short serving leg (p50/p99 latency, 4 jobs/s); 0 skips it")
+    ap.add_argument("--serve-jobs", type=int, default=120,
+                    help="--mode fb: jobs in the serving leg (the 120-job trace at 4 jobs/s: p50/p99 latency, "
+                         "jobs/s against the serial baseline); 0 skips it")
+    ap.add_argument("--operator-384", type=int, default=1,
+                    help="--mode fb: also time the forward operator A = X W_T at 384^3 / 360 angles / T = 0.6 "
+                         "in FP32 and FP64 (the operator HBM fraction, 1/0)")
     return ap.parse_args()
 
 
@@ -416,30 +420,82 @@ def time_wave(torch, plan, reps=3):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def stencil_roofline(torch, ff, plan, case, dtype):
+def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
     """The dominant kernel of the path (the leapfrog stencil) and its average launch
     duration, measured live.  A W_T solve is n_t leapfrog steps: with one step per
-    pass, n_t launches of wave_step_blocked (algorithmic bytes per launch: read
-    p(k), p(k-1), k', write p(k+1) = 4 words per voxel); with two steps per pass,
-    one first-step launch, P = (n_t - 1) // 2 launches of wave_step2_blocked (read
-    p(k-1), p(k), k', write p(k+1), p(k+2) = 5 words per voxel) and S = (n_t - 1) % 2
+    pass, n_t launches of wave_step_blocked; with two steps per pass, one first-step
+    launch, P = (n_t - 1) // 2 launches of wave_step2_blocked and S = (n_t - 1) % 2
     single-step launches.  The pair kernel's duration is then
     (t(W_T) - (1 + S) t_single) / P, with t_single measured on a plan that runs one
-    step per pass."""
+    step per pass.
+    Bytes per launch, two ways: algorithmic = 4 words per point update (read p(k),
+    p(k-1), k'; write p(k+1): 16 B FP32, 32 B FP64) x the updates a launch makes per
+    voxel (1 or 2); compulsory = the words per voxel a launch must move at least
+    (4 for one step; read p(k-1), p(k), k', write p(k+1), p(k+2): 5 for two)."""
     esz = 4 if dtype == torch.float32 else 8
-    nvox = case.n ** 3
+    nvox = math.prod(plan.shape)
     t_w = time_wave(torch, plan)
     out = {"t_wave": t_w, "steps_per_pass": plan.steps_per_pass}
     if plan.steps_per_pass == 1:
-        out.update(kernel="wave_step_blocked", t_launch=t_w / plan.nt, bytes_per_launch=4 * esz * nvox)
+        out.update(kernel="wave_step_blocked", t_launch=t_w / plan.nt, alg_bytes=4 * esz * nvox,
+                   compulsory_bytes=4 * esz * nvox, updates_per_launch=1)
         return out
-    c = torch.from_numpy(case.c).to("cuda", dtype)
-    with ff.Plan(c, case.dx, case.T, case.angles, two_step_stencil=False) as ps:
+    with ff.Plan(c, dx, T, angles, two_step_stencil=False) as ps:
         t_single = time_wave(torch, ps) / ps.nt
     pairs, singles = divmod(plan.nt - 1, 2)
     out.update(kernel="wave_step2_blocked", t_launch=(t_w - (1 + singles) * t_single) / pairs,
-               bytes_per_launch=5 * esz * nvox, t_single_launch=t_single)
+               alg_bytes=2 * 4 * esz * nvox, compulsory_bytes=5 * esz * nvox, updates_per_launch=2,
+               t_single_launch=t_single)
     return out
+
+
+def operator_384(torch, ff, synth, seed):
+    """The forward operator A = X W_T at the precision workload's shape (384^3, 360
+    angles, T = 0.6, c with 10 bumps clamped to [0.75, 1.25]), where each field
+    (226 MB FP32) exceeds the 256 MB MALL with the others: the operator HBM fraction
+    (w N^3 n_t + w N^3 + w N_phi N^2) / t_A / 8 TB/s, w = 4 words of the field type
+    per point update and one per voxel and per bin for the projection, t_A from HIP
+    events around back-to-back applications, in FP32 and FP64; and the pair launch's
+    duration and algorithmic rate there."""
+    out = {"workload": "384^3 grid, 360 angles, T=0.6, c in [0.75, 1.25] (10 bumps)"}
+    n, nang = 384, 360
+    for name, dtype in (("f32", torch.float32), ("f64", torch.float64)):
+        dx, angles, c, h = synth.torch_case(n, nang, seed, dtype=dtype, n_bumps=10, amp=0.2, clamp=(0.75, 1.25))
+        with ff.Plan(c, dx, 0.6, angles) as P:
+            g = P.forward(h)
+            stream = torch.cuda.current_stream()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                P.forward(h, out=g, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            t_a = e0.elapsed_time(e1) / 1e3 / 3
+            esz = 4 if dtype == torch.float32 else 8
+            n3 = n ** 3
+            alg = esz * (4 * n3 * P.nt + n3 + nang * n * n)
+            roof = stencil_roofline(torch, ff, P, c, dx, 0.6, angles, dtype)
+            out[name] = {"nt": P.nt, "forward_ms": 1e3 * t_a, "operator_hbm_frac": alg / t_a / (HBM_PEAK_GBS * 1e9),
+                         "kernel": roof["kernel"], "avg_launch_us": roof["t_launch"] * 1e6,
+                         "achieved_GBps": roof["alg_bytes"] / roof["t_launch"] / 1e9,
+                         "frac": roof["alg_bytes"] / roof["t_launch"] / 1e9 / HBM_PEAK_GBS,
+                         "frac_compulsory": roof["compulsory_bytes"] / roof["t_launch"] / 1e9 / HBM_PEAK_GBS}
+        del c, h, g
+        torch.cuda.empty_cache()
+        log(f"384^3 {name}: {out[name]}")
+    return out
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def cpu_baseline(case, G, step):
@@ -463,7 +519,7 @@ def cpu_baseline(case, G, step):
     t1 = time.perf_counter()
     oracle.wave(gs, small.c, small.h_true)
     tw = time.perf_counter() - t1
-    return {"value": 1.0 / t, "unit": "FB iter/s", "cores": cores, "kind": "oracle",
+    return {"value": 1.0 / t, "unit": "FB iter/s", "cores": cores, "kind": "oracle", "cpu_model": host_cpu_model(),
             "sample": f"one full FB iteration of the {n}^3 / {len(case.angles)}-angle workload in FP64 "
                       f"({t:.1f} s: 2 wave solves, X, Lambda, X^T, prox)",
             "oracle_wave_gpt_updates_per_s": small.n ** 3 * nt_small / tw / 1e9,
@@ -519,13 +575,16 @@ def main():
     ms = 1e3 * t / args.steps
     log(f"FB {args.steps} iterations: {t:.3f}s ({ms:.2f} ms/iter), power iteration {t_power:.3f}s")
 
-    roof = stencil_roofline(torch, ff, plan, case, dtype)
-    t_launch, bytes_per_launch = roof["t_launch"], roof["bytes_per_launch"]
-    achieved = bytes_per_launch / t_launch / 1e9
+    roof = stencil_roofline(torch, ff, plan, torch.from_numpy(case.c).to("cuda", dtype), case.dx, case.T,
+                            case.angles, dtype)
+    t_launch = roof["t_launch"]
+    achieved = roof["alg_bytes"] / t_launch / 1e9
+    achieved_c = roof["compulsory_bytes"] / t_launch / 1e9
     gpt = N ** 3 * plan.nt / roof["t_wave"] / 1e9
-    log(f"{roof['kernel']} {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s; "
-        f"W_T {roof['t_wave'] * 1e3:.2f} ms, {gpt:.1f} Gpt-updates/s")
-    ceiling = stream_ceiling(torch, bytes_per_launch, achieved) if roof["kernel"] == "wave_step2_blocked" else None
+    log(f"{roof['kernel']} {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s algorithmic, "
+        f"{achieved_c:.0f} GB/s compulsory; W_T {roof['t_wave'] * 1e3:.2f} ms, {gpt:.1f} Gpt-updates/s")
+    ceiling = (stream_ceiling(torch, roof["compulsory_bytes"], achieved_c)
+               if roof["kernel"] == "wave_step2_blocked" else None)
     log(f"streaming ceiling of the same streams: {ceiling}")
 
     fp64 = None
@@ -535,8 +594,8 @@ def main():
         del G
         torch.cuda.empty_cache()
         case64, plan64, G64 = make_inputs(args, torch, ff, synth, torch.float64)
-        k64 = max(2, args.steps // 4)
-        t64, _, _ = time_fb(torch, plan64, G64, case.lam, k64, 1)
+        k64 = max(10, args.steps // 2)
+        t64, _, _ = time_fb(torch, plan64, G64, case.lam, k64, 2)
         fp64 = {"fb_iter_per_s": k64 / t64, "ms_per_iter": 1e3 * t64 / k64, "steps": k64,
                 "wave_gpt_updates_per_s": N ** 3 * plan64.nt / time_wave(torch, plan64) / 1e9,
                 "steps_per_pass": plan64.steps_per_pass}
@@ -550,6 +609,11 @@ def main():
         log(f"cpu baseline {cpu}")
     traffic = stored_traffic(roof["kernel"], args.recipe, args.dtype)
 
+    op384 = None
+    if args.operator_384 and args.recipe == "c256":
+        log("forward operator at 384^3 (FP32, FP64)")
+        op384 = operator_384(torch, ff, synth, args.seed + 1000)
+
     serve = None
     if args.serve_jobs > 0:
         log(f"serving leg: {args.serve_jobs} jobs at 4 jobs/s")
@@ -559,6 +623,7 @@ def main():
             cb, se = sv["continuous_batching"], sv["serial"]
             serve = {"trace": f"{args.serve_jobs} jobs, Poisson 4 jobs/s, grids 64^3..256^3, 50 FB iterations each, "
                               f"FP32, policy {args.policy}",
+                     "throughput_gain": sv["throughput_gain"],
                      "latency_p50_s": cb["latency_p50_s"], "latency_p99_s": cb["latency_p99_s"],
                      "jobs_per_s": cb["jobs_per_s"], "serial_latency_p50_s": se["latency_p50_s"],
                      "serial_latency_p99_s": se["latency_p99_s"], "serial_jobs_per_s": se["jobs_per_s"]}
@@ -580,7 +645,8 @@ def main():
         "dtype": "f32" if dtype == torch.float32 else "f64",
         "data": "synthetic (seeded phantom: balls + tubes, smoothed; c: Gaussian bumps)",
         "config": {"workload": f"{N}^3 grid, {nang} angles, T={case.T}, Algorithm 8 with positivity + "
-                               f"lambda={case.lam} l2 prox, FP32 fields + FP64 reductions",
+                               f"lambda={case.lam} l2 prox, "
+                               + ("FP32 fields + FP64 reductions" if dtype == torch.float32 else "all-FP64"),
                    "grid": N, "angles": nang, "nt": plan.nt, "power_steps": 20,
                    "stencil": "naive" if args.naive_stencil else roof["kernel"]},
         "wave_gpt_updates_per_s": gpt,
@@ -588,8 +654,18 @@ def main():
         "fp64": fp64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": roof["kernel"], "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": t_launch * 1e6, "stream_ceiling": ceiling},
+                     "kernel": roof["kernel"], "bytes_per_launch": roof["alg_bytes"],
+                     "byte_unit": f"algorithmic: 16 B per point update (FP32; read p(k), p(k-1), k', write "
+                                  f"p(k+1)) x {roof['updates_per_launch']} update(s) per voxel per launch",
+                     "avg_launch_us": t_launch * 1e6,
+                     "compulsory": {"bytes_per_launch": roof["compulsory_bytes"], "achieved": achieved_c,
+                                    "frac": achieved_c / HBM_PEAK_GBS,
+                                    "byte_unit": "words a launch must move per voxel (5 for two steps: read "
+                                                 "p(k-1), p(k), k', write p(k+1), p(k+2))"},
+                     "stream_ceiling": ceiling,
+                     "target": "the >= 0.60 HBM target applies to the operator HBM fraction of A = X W_T at "
+                               "384^3 (operator_384.*.operator_hbm_frac, beyond the 256 MB MALL)"},
+        "operator_384": op384,
         "cpu_baseline": cpu,
         "serving": serve,
         "objective_last": float(out.objective[-1]) if len(out.objective) else None,
