@@ -197,6 +197,22 @@ int ffpat_reconstruct(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params
 int ffpat_fb_enqueue(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev,
                      void *stream);
 
+/* For callers that cannot allocate device memory while they run: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  The same
+ * work as ffpat_fb_enqueue on a plan created beforehand, but it allocates nothing
+ * (no hipMalloc or hipFree, no graph or stream of its own): every kernel is launched
+ * on `stream` directly, so a caller may record the whole sequence into a graph of its
+ * own, and the objective values J_k go to a static device array of the library
+ * (65536 FP64 values, 512 KiB per device, held until the process ends) instead of the
+ * plan's objective buffer.  params->n_iter above 65536: FFPAT_EINVAL before anything
+ * is enqueued; other arguments as ffpat_fb_enqueue.  ffpat_fb_report on the same plan
+ * completes the run and reads the values from that array.  Every call on a device
+ * shares the array, which keeps the last call's values: calls that overlap on one
+ * device (any plans, any streams) race, and a report must come before the next such
+ * call on the device. */
+int ffpat_fb_enqueue_noalloc(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev,
+                             void *stream);
+
 /* Completes an ffpat_fb_enqueue: synchronises `stream`, writes the step size
  * (step_used, may be NULL) and the first n objective values of the last
  * enqueued run (objective, host, may be NULL when n = 0), and returns

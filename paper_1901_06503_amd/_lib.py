@@ -73,6 +73,7 @@ SIGNATURES = {
     "ffpat_reconstruct": ([_P, _P, ctypes.POINTER(FbParams), _P, ctypes.POINTER(ctypes.c_double), _P],
                           ctypes.c_int),
     "ffpat_fb_enqueue": ([_P, _P, ctypes.POINTER(FbParams), _P, _P], ctypes.c_int),
+    "ffpat_fb_enqueue_noalloc": ([_P, _P, ctypes.POINTER(FbParams), _P, _P], ctypes.c_int),
     "ffpat_fb_report": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _P],
                         ctypes.c_int),
 }

@@ -22,10 +22,17 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace ffpat;
+
+// Objective history of ffpat_fb_enqueue_noalloc: a static device array, so that entry
+// point allocates nothing.  512 KiB per device, held until the process ends; shared by
+// every such call on the device (calls that overlap on one device race).
+constexpr int kNoAllocMaxIter = 65536;
+static __device__ __align__(256) double scratch[kNoAllocMaxIter];
 
 namespace {
 
@@ -121,6 +128,8 @@ struct ffpat_plan {
   unsigned char *base = nullptr;
   double *obj = nullptr;  // objective history (device), capacity obj_cap
   int obj_cap = 0;
+  double *run_obj = nullptr;  // where the iterations being enqueued write J_k: obj, or the
+  int run_obj_cap = 0;        // static history of ffpat_fb_enqueue_noalloc; read by fb_report
   bool has_step = false;
   bool two_tap = true;    // every footprint half-width m dx / ds <= 1 bin
   bool need_n = false;    // some angle marches rows (reads the padded plane)
@@ -536,7 +545,7 @@ int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, hi
     if (rc) return rc;
     HIP_TRY(launch_vol_residual<T>(V2, G, P->nvox, P->partials(), s));
     HIP_TRY(launch_reduce_to(P->partials(), kReduceBlocks, 1.0, sc + SC_DATA, s));
-    HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->obj, sc + SC_ITER, P->obj_cap,
+    HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->run_obj, sc + SC_ITER, P->run_obj_cap,
                              sc + SC_NONFINITE, s));
     HIP_TRY(launch_mul<T>(V2, static_cast<const T *>(P->kap()), V1, P->nvox, s));
     rc = wave_adjoint_from_scaled<T>(P, V1, V3, Pool<T>{P->vol(1), P->vol(4), P->vol(5)}, s);
@@ -546,7 +555,7 @@ int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, hi
     rc = data_residual<T>(P, h, G, prm->det_mask, precond, P->partials(), s);
     if (rc) return rc;
     HIP_TRY(launch_reduce_to(P->partials(), P->rows, 1.0, sc + SC_DATA, s));
-    HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->obj, sc + SC_ITER, P->obj_cap,
+    HIP_TRY(launch_objective(sc + SC_DATA, sc + SC_REG, prm->lambda, P->run_obj, sc + SC_ITER, P->run_obj_cap,
                              sc + SC_NONFINITE, s));
     rc = op_adjoint_padded<T>(P, V3, s);
     if (rc) return rc;
@@ -608,22 +617,35 @@ int ensure_objective_capacity(ffpat_plan *P, int n, hipStream_t s)
 }
 
 // Enqueues the step-size selection and n_iter iterations; no host synchronisation.
+// static_obj != nullptr: the objective values go to that device array (capacity
+// kNoAllocMaxIter) and every kernel is launched on `s` directly (no graph capture, no
+// allocation: the no-allocation entry point).
 template <typename T>
-int fb_enqueue(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, hipStream_t s)
+int fb_enqueue(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, hipStream_t s,
+               double *static_obj = nullptr)
 {
   const bool precond = prm->flags & FFPAT_PRECOND;
   const bool two_step = prm->flags & FFPAT_TWO_STEP;
   const int n_power = prm->n_power > 0 ? prm->n_power : 20;
+  const bool graphs = P->use_graphs && !static_obj;
   double *sc = P->scalars();
-  int rc = ensure_objective_capacity(P, prm->n_iter, s);
-  if (rc) return rc;
+  if (static_obj) {
+    P->run_obj = static_obj;
+    P->run_obj_cap = kNoAllocMaxIter;
+  } else {
+    int rc = ensure_objective_capacity(P, prm->n_iter, s);
+    if (rc) return rc;
+    P->run_obj = P->obj;
+    P->run_obj_cap = P->obj_cap;
+  }
+  int rc = FFPAT_OK;
   HIP_TRY(launch_set(sc + SC_NONFINITE, 0.0, s));
   HIP_TRY(launch_set(sc + SC_ITER, 0.0, s));
   if (prm->flags & FFPAT_USE_PLAN_STEP) {
     if (!P->has_step) return fail(FFPAT_EINVAL, "FFPAT_USE_PLAN_STEP but the plan holds no step yet");
   } else if (prm->step > 0) {
     HIP_TRY(launch_set(sc + SC_STEP, prm->step, s));
-  } else if (P->use_graphs) {
+  } else if (graphs) {
     const uint32_t key = prm->flags & (FFPAT_PRECOND | FFPAT_TWO_STEP);
     if (!P->g_power.matches(nullptr, nullptr, nullptr, prm->det_mask, key, 0.0, n_power, 0.0, 0)) {
       rc = capture_graph(P, P->g_power, [&](hipStream_t cs) {
@@ -639,7 +661,7 @@ int fb_enqueue(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, hipS
   }
   P->has_step = true;
   if (prm->n_iter <= 0) return FFPAT_OK;
-  if (P->use_graphs) {
+  if (graphs) {
     const uint32_t key = prm->flags & (FFPAT_PRECOND | FFPAT_POSITIVITY | FFPAT_REG_GRAD | FFPAT_TWO_STEP);
     const CgControl cc = cg_control<T>(prm);
     if (!P->g_iter.matches(G, h, prm->support, prm->det_mask, key, prm->lambda, 0, cc.tol, cc.maxit)) {
@@ -665,9 +687,9 @@ int fb_report(ffpat_plan *P, double *step_used, double *objective, int n, hipStr
   HIP_TRY(hipStreamSynchronize(s));
   const int done = (int)host_sc[SC_ITER];
   if (objective && n > 0) {
-    if (n > done || n > P->obj_cap)
+    if (n > done || n > P->run_obj_cap || !P->run_obj)
       return fail(FFPAT_EINVAL, "%d objective values requested, %d available", n, done);
-    HIP_TRY(hipMemcpyAsync(objective, P->obj, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(objective, P->run_obj, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
   if (step_used) *step_used = host_sc[SC_STEP];
@@ -695,6 +717,38 @@ int fbp_op(ffpat_plan *P, const T *G, T *vol, hipStream_t s)
 }
 
 bool is_f64(const ffpat_plan *P) { return P->dtype == FFPAT_F64; }
+
+// Device address of `scratch` (the objective history of ffpat_fb_enqueue_noalloc) on
+// each device, resolved once per device with that device current: every GPU holds its
+// own copy of the array at its own address, and in host code the array's name is not
+// a device address.
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Resolves the address for the current device `dev` if not done yet.
+int scratch_resolve(int dev)
+{
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(FFPAT_EINVAL, "device %d: the static history is kept for devices 0..%d", dev, kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return FFPAT_OK;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();   // reported here: later launch checks must not see it
+    return fail(FFPAT_EHIP, "hipGetSymbolAddress of the static objective history: %s", hipGetErrorString(e));
+  }
+  g_scratch_ptr[dev] = static_cast<double *>(p);
+  return FFPAT_OK;
+}
+
+double *scratch_address(int dev)
+{
+  if (dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
 
 #define CHECK_PLAN(P)                                               \
   do {                                                              \
@@ -741,6 +795,9 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
     delete P;
     return hip_fail(e, "hipGetDevice");
   }
+  // set-up of the no-allocation entry point on this device (a failure is reported by
+  // that entry point, which tries again; plan creation does not depend on it)
+  (void)scratch_resolve(P->device);
   P->d = r.d;
   P->dtype = r.dtype;
   P->esz = r.dtype == FFPAT_F64 ? 8 : 4;
@@ -1024,6 +1081,26 @@ int ffpat_fb_enqueue(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params 
   hipStream_t s = static_cast<hipStream_t>(stream);
   return DISPATCH(plan, fb_enqueue<float>(plan, (const float *)G_dev, params, (float *)h_dev, s),
                   fb_enqueue<double>(plan, (const double *)G_dev, params, (double *)h_dev, s));
+}
+
+int ffpat_fb_enqueue_noalloc(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev,
+                             void *stream)
+{
+  int rc = check_fb_args(plan, G_dev, params, h_dev);
+  if (rc) return rc;
+  if (params->n_iter > kNoAllocMaxIter)
+    return fail(FFPAT_EINVAL, "n_iter %d exceeds the %d objective values the static history of "
+                "ffpat_fb_enqueue_noalloc holds", params->n_iter, kNoAllocMaxIter);
+  DeviceGuard guard(plan->device);
+  double *history = scratch_address(plan->device);
+  if (!history) {
+    rc = scratch_resolve(plan->device);
+    if (rc) return rc;
+    history = scratch_address(plan->device);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return DISPATCH(plan, fb_enqueue<float>(plan, (const float *)G_dev, params, (float *)h_dev, s, history),
+                  fb_enqueue<double>(plan, (const double *)G_dev, params, (double *)h_dev, s, history));
 }
 
 int ffpat_fb_report(ffpat_plan *plan, double *step_used, double *objective, int32_t n, void *stream)
