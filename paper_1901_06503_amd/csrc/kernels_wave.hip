@@ -518,6 +518,357 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two leapfrog steps per pass, 3D, 8-byte elements (FP64, or FP32 as pairs of
+// x-adjacent points), 64 x 16 element tile, 512 threads: the arithmetic of
+// wave_step2_blocked (every sum in the same order, so the results are the same
+// bits) with points assigned to threads so that no lane-dependent branch sits
+// between the LDS reads of different points:
+//   slots 0 and 1: the tile's 1024 interior points, one 64-wide row per
+//     wavefront and slot (coalesced); they run stage 1 and stage 2 and keep the
+//     q and k' z-windows;
+//   slot 2: the 416 other points of the LDS region's rows 2..21 (the extended
+//     tile's 2-point halo and the two outer columns on each side), threads
+//     0..415; stage 1 only, so no q or k' windows;
+//   ring: rows 0, 1, 22, 23 of the p(k) plane (288 points), threads 0..287.
+// Stage 1 issues the LDS reads of all three slots before any arithmetic and
+// stage 2 those of both interior slots, so each stage waits for LDS once per
+// plane.  Stage 1 runs on every slot unconditionally; a point off the grid or
+// plane yields q = 0 by a select, the outer columns' values land in q columns
+// that stage 2 never reads, and threads without a halo point write theirs to a
+// spare LDS word and to q column 0.  The results are pinned in registers before
+// the global stores, so the compiler cannot sink a slot's LDS reads into them.
+// The stores are buffer stores whose range check drops the lanes off the grid and,
+// for planes outside the group's chunk, all lanes (a zero-size range): every plane
+// issues the same memory instructions on every path, so the compiler's wait
+// counts stay exact and the loads of plane zs + 2 remain in flight across the
+// barriers of planes zs and zs + 1 instead of being waited for together with the
+// stores that a branch may or may not have issued.  Prefetch and windows as in
+// wave_step2_blocked.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct NbrX;   // x neighbours read from LDS (the centre comes from registers)
+template <>
+struct NbrX<double> {
+  static constexpr int N = 4;   // c[-2], c[-1], c[1], c[2]
+  static __device__ __forceinline__ void load(const double *c, double *v)
+  {
+    v[0] = c[-2];
+    v[1] = c[-1];
+    v[2] = c[1];
+    v[3] = c[2];
+  }
+  static __device__ __forceinline__ void terms(const double *v, double, double &s1, double &s2)
+  {
+    s1 = v[1] + v[2];
+    s2 = v[0] + v[3];
+  }
+};
+template <>
+struct NbrX<f32x2> {
+  static constexpr int N = 2;   // elements j-1 and j+1 (points 2j-2, 2j-1 and 2j+2, 2j+3)
+  static __device__ __forceinline__ void load(const f32x2 *c, f32x2 *v)
+  {
+    v[0] = c[-1];
+    v[1] = c[1];
+  }
+  static __device__ __forceinline__ void terms(const f32x2 *v, f32x2 m, f32x2 &s1, f32x2 &s2)
+  {
+    const f32x2 l = v[0], r = v[1];
+    s1 = f32x2{l.y + m.y, m.x + r.x};
+    s2 = f32x2{l.x + r.x, l.y + r.y};
+  }
+};
+
+// An empty asm statement that passes N register values through at once: the loads
+// that produce them are all issued before it, the wait for them comes once, at it,
+// and the arithmetic on them after it.
+template <typename T, int N>
+struct LdsFence;
+template <typename T>
+struct LdsFence<T, 18> {
+  static __device__ __forceinline__ void all(T *v)
+  {
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),
+                 "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]),
+                 "+v"(v[14]), "+v"(v[15]), "+v"(v[16]), "+v"(v[17]));
+  }
+};
+template <typename T>
+struct LdsFence<T, 24> {
+  static __device__ __forceinline__ void all(T *v)
+  {
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),
+                 "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]),
+                 "+v"(v[14]), "+v"(v[15]), "+v"(v[16]), "+v"(v[17]), "+v"(v[18]), "+v"(v[19]), "+v"(v[20]),
+                 "+v"(v[21]), "+v"(v[22]), "+v"(v[23]));
+  }
+};
+
+// 8-byte store through a buffer resource of `bytes` bytes at `base`: lanes whose byte
+// offset is out of range (and all lanes when bytes = 0) write nothing.
+template <typename T>
+__device__ __forceinline__ void st_ranged(T *base, unsigned bytes, unsigned boff, T v)
+{
+  static_assert(sizeof(T) == 8, "8-byte elements");
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, boff, 0, 0);
+}
+
+// RESTRICT: the inputs and outputs are declared non-aliasing.  Without it (FP32
+// pairs) the compiler must keep each plane's prefetch loads ahead of the plane's
+// stores, i.e. where they are written; with it, it sinks them past the z loop's
+// exit tests to the next plane, which halves the prefetch distance: the FP32 pairs
+// kernel is 1% faster without, the FP64 kernel 7% faster with (without, it spills).
+template <typename T, bool RESTRICT>
+__global__ void __launch_bounds__(512, 1)
+wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> pm1,
+                 std::conditional_t<RESTRICT, const T *__restrict__, const T *> pk,
+                 std::conditional_t<RESTRICT, T *__restrict__, T *> q_out,
+                 std::conditional_t<RESTRICT, T *__restrict__, T *> o_out,
+                 std::conditional_t<RESTRICT, const T *__restrict__, const T *> kap, int nx, int ny, int nz,
+                 int zchunk, int tiles_x, int tiles_y, int n_tiles, int xy_fastest)
+{
+  constexpr int NTH = 512, BX = 64, BY = 16;
+  constexpr int EX = BX + 4, EY = BY + 4;    // stage-1 region (68 x 20)
+  constexpr int KX = BX + 8, KY = BY + 8;    // p(k) plane in LDS (72 x 24)
+  constexpr int NIN = BX * BY / NTH;         // interior slots per thread (2)
+  constexpr int NHALO = KX * EY - BX * BY;   // other points of LDS rows 2..KY-3 (416)
+  constexpr int NRING = 4 * KX;              // LDS rows 0, 1, KY-2, KY-1 (288)
+  constexpr int PPT = NIN + 1;
+  constexpr int NB = NbrX<T>::N + 4;         // LDS reads per point and stage
+  static_assert(BX * BY == NIN * NTH && NHALO <= NTH && NRING <= NTH, "slot layout");
+  __shared__ T lk[2][KY * KX + 1];           // p(k) plane, double-buffered by plane parity (+ a spare word)
+  __shared__ T lq[5][EY * KX];               // q planes, row pitch KX
+
+  const int b = blockIdx.x;
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int t = (b % 8) * per_xcd + b / 8;
+  if (t >= n_tiles) return;                  // whole group exits together
+  const int n_zc = (nz + zchunk - 1) / zchunk;
+  int zc, txy;
+  if (xy_fastest) {
+    const int n_xy = tiles_x * tiles_y;
+    txy = t % n_xy;
+    zc = t / n_xy;
+  } else {
+    zc = t % n_zc;
+    txy = t / n_zc;
+  }
+  const int x0 = (txy % tiles_x) * BX, y0 = (txy / tiles_x) * BY;
+  const int zbeg = zc * zchunk;
+  const int zend = min(nz, zbeg + zchunk);
+  const size_t plane = (size_t)nx * ny;
+  const int zstart = zbeg - 2;
+  const int tid = threadIdx.x;
+
+  // per slot: LDS index in the p(k) plane and in a q plane, in-grid flags, byte
+  // offset of the (clamped) grid position within a plane
+  int lofs[PPT], lwr[PPT], qofs[PPT];   // LDS read centre, write index, q-plane index
+  unsigned boff[PPT], soff[NIN];          // load offset (clamped); store offset (out of range off the grid)
+  bool ingw[PPT], ing[PPT];
+  const unsigned plane_bytes = (unsigned)(plane * sizeof(T));
+  T w[PPT][5], r1[NIN][5], kr[NIN][5];
+#pragma unroll
+  for (int m = 0; m < PPT; ++m) {
+    int ex, ey;
+    bool has = true;
+    if (m < NIN) {
+      const int i = tid + NTH * m;
+      ey = 2 + i / BX;
+      ex = 4 + i % BX;
+    } else if (tid < 4 * KX) {             // extended rows 0, 1, EY-2, EY-1, full width
+      const int r = tid / KX;
+      ey = r < 2 ? r : EY - 4 + r;
+      ex = tid - r * KX;
+    } else if (tid < NHALO) {              // rows 2..EY-3, columns 0..3 and KX-4..KX-1
+      const int j = tid - 4 * KX;
+      ey = 2 + j / 8;
+      const int cc = j % 8;
+      ex = cc < 4 ? cc : KX - 8 + cc;
+    } else {                               // no halo point: reads around an interior position
+      has = false;
+      ey = 2;
+      ex = 4;
+    }
+    lofs[m] = (ey + 2) * KX + ex;
+    lwr[m] = has ? lofs[m] : KY * KX;      // the spare word
+    qofs[m] = has ? ey * KX + ex : 0;      // q column 0: never read
+    const int gx = x0 - 4 + ex, gy = y0 - 2 + ey;
+    ingw[m] = has && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    ing[m] = ingw[m] && ex >= 2 && ex < EX + 2;   // a stage-1 point of the grid
+    boff[m] = (unsigned)((min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1)) * sizeof(T));
+    if (m < NIN) soff[m] = ing[m] ? boff[m] : 0xFFFFFFF0u;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) w[m][q] = T(0);
+#pragma unroll
+    for (int d = -2; d <= 1; ++d) {
+      const int zq = zstart + d;
+      if (zq >= 0 && zq < nz) {
+        const T v = ldb(pk + (size_t)zq * plane, boff[m]);
+        w[m][(d + 5) % 5] = ingw[m] ? v : T(0);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NIN; ++m)
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      r1[m][q] = T(0);
+      kr[m][q] = T(0);
+    }
+
+  // ring element of the p(k) plane owned by this thread
+  const bool has_ring = tid < NRING;
+  int rl;
+  unsigned roff;
+  bool rin;
+  {
+    const int hr = has_ring ? tid / KX : 0;
+    const int lr = hr < 2 ? hr : KY - 4 + hr;
+    const int lc = has_ring ? tid - hr * KX : 0;
+    rl = lr * KX + lc;
+    const int gx = x0 - 4 + lc, gy = y0 - 4 + lr;
+    rin = has_ring && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    roff = (unsigned)((min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1)) * sizeof(T));
+  }
+
+  T nw[2][PPT], npv[2][PPT], nkv[2][PPT], nring[2];
+  auto fetch = [&](auto buf, int zf) {
+    constexpr int B = decltype(buf)::value;
+    const int zw = min(max(zf + 2, 0), nz - 1);   // p(k) plane entering the window
+    const int zc2 = min(max(zf, 0), nz - 1);
+    const T *bw = pk + (size_t)zw * plane, *bp = pm1 + (size_t)zc2 * plane, *bk = kap + (size_t)zc2 * plane;
+    const T *br = pk + (size_t)zc2 * plane;
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+      nw[B][m] = ldb(bw, boff[m]);
+      npv[B][m] = ldb(bp, boff[m]);
+      nkv[B][m] = ldb(bk, boff[m]);
+    }
+    nring[B] = ldb(br, roff);
+  };
+  fetch(std::integral_constant<int, 0>{}, zstart);
+  fetch(std::integral_constant<int, 1>{}, zstart + 1);
+
+  auto step = [&](auto phase, int zs) {
+    constexpr int Q = decltype(phase)::value;
+    constexpr int P = Q % 5, B = Q % 2;
+    constexpr int Sm2 = (P + 3) % 5, Sm1 = (P + 4) % 5, S0 = P, Sp1 = (P + 1) % 5, Sp2 = (P + 2) % 5;
+    constexpr int Sm3 = (P + 2) % 5, Sm4 = (P + 1) % 5;
+    const int z = zs - 2;
+    const bool zs_in = zs >= 0 && zs < nz;
+    const bool zw_in = zs + 2 >= 0 && zs + 2 < nz;
+    T pv[PPT], kv[PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+      w[m][Sp2] = (ingw[m] && zw_in) ? nw[B][m] : T(0);
+      pv[m] = npv[B][m];
+      kv[m] = nkv[B][m];
+    }
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) lk[B][lwr[m]] = w[m][S0];
+    if (has_ring) lk[B][rl] = (rin && zs_in) ? nring[B] : T(0);
+    fetch(std::integral_constant<int, B>{}, zs + 2);
+    __syncthreads();
+    // stage 1: q(zs) on every slot; all LDS reads first
+    T nb[PPT][NB];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+      const T *c = &lk[B][lofs[m]];
+      NbrX<T>::load(c, nb[m]);
+      nb[m][NB - 4] = c[-KX];
+      nb[m][NB - 3] = c[KX];
+      nb[m][NB - 2] = c[-2 * KX];
+      nb[m][NB - 1] = c[2 * KX];
+    }
+    LdsFence<T, PPT * NB>::all(&nb[0][0]);   // every read issued before the first wait
+    T qv[PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+      const T c0 = w[m][S0];
+      T s1, s2;
+      NbrX<T>::terms(nb[m], c0, s1, s2);
+      s1 = s1 + (nb[m][NB - 4] + nb[m][NB - 3]);
+      s2 = s2 + (nb[m][NB - 2] + nb[m][NB - 1]);
+      s1 += w[m][Sm1] + w[m][Sp1];
+      s2 += w[m][Sm2] + w[m][Sp2];
+      const T S = T(16) * s1 - s2 - T(90) * c0;
+      const T qn = T(2) * c0 - pv[m] + kv[m] * S;
+      qv[m] = (ing[m] && zs_in) ? qn : T(0);
+    }
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) lq[S0][qofs[m]] = qv[m];
+#pragma unroll
+    for (int m = 0; m < NIN; ++m) {
+      r1[m][S0] = qv[m];
+      kr[m][S0] = kv[m];
+      asm volatile("" : : "v"(qv[m]));
+    }
+    {                                        // q(zs) where the plane belongs to this group's chunk
+      const bool own = zs >= zbeg && zs < zend;
+      T *q_pl = q_out + (size_t)min(max(zs, 0), nz - 1) * plane;
+#pragma unroll
+      for (int m = 0; m < NIN; ++m) st_ranged(q_pl, own ? plane_bytes : 0u, soff[m], qv[m]);
+    }
+    // stage 2: o(z) on the interior slots, z = zs - 2 (computed on every plane, stored
+    // from z = zbeg on; before that the q planes it reads are not yet written)
+    {
+      T nq[NIN][NB];
+#pragma unroll
+      for (int m = 0; m < NIN; ++m) {
+        const T *c = &lq[Sm2][qofs[m]];
+        NbrX<T>::load(c, nq[m]);
+        nq[m][NB - 4] = c[-KX];
+        nq[m][NB - 3] = c[KX];
+        nq[m][NB - 2] = c[-2 * KX];
+        nq[m][NB - 1] = c[2 * KX];
+      }
+      T *o_pl = o_out + (size_t)max(z, 0) * plane;
+      T ov[NIN];
+#pragma unroll
+      for (int m = 0; m < NIN; ++m) {
+        const T c0 = r1[m][Sm2];
+        T s1, s2;
+        NbrX<T>::terms(nq[m], c0, s1, s2);
+        s1 = s1 + (nq[m][NB - 4] + nq[m][NB - 3]);
+        s2 = s2 + (nq[m][NB - 2] + nq[m][NB - 1]);
+        s1 += r1[m][Sm3] + r1[m][Sm1];
+        s2 += r1[m][Sm4] + r1[m][S0];
+        const T S = T(16) * s1 - s2 - T(90) * c0;
+        ov[m] = T(2) * c0 - w[m][Sm2] + kr[m][Sm2] * S;
+        asm volatile("" : : "v"(ov[m]));
+      }
+#pragma unroll
+      for (int m = 0; m < NIN; ++m) st_ranged(o_pl, z >= zbeg ? plane_bytes : 0u, soff[m], ov[m]);
+    }
+  };
+
+  const int zlast = zend + 1;                // last stage-1 plane
+  for (int zb = zstart; zb <= zlast; zb += 10) {
+    step(std::integral_constant<int, 0>{}, zb);
+    if (zb + 1 > zlast) break;
+    step(std::integral_constant<int, 1>{}, zb + 1);
+    if (zb + 2 > zlast) break;
+    step(std::integral_constant<int, 2>{}, zb + 2);
+    if (zb + 3 > zlast) break;
+    step(std::integral_constant<int, 3>{}, zb + 3);
+    if (zb + 4 > zlast) break;
+    step(std::integral_constant<int, 4>{}, zb + 4);
+    if (zb + 5 > zlast) break;
+    step(std::integral_constant<int, 5>{}, zb + 5);
+    if (zb + 6 > zlast) break;
+    step(std::integral_constant<int, 6>{}, zb + 6);
+    if (zb + 7 > zlast) break;
+    step(std::integral_constant<int, 7>{}, zb + 7);
+    if (zb + 8 > zlast) break;
+    step(std::integral_constant<int, 8>{}, zb + 8);
+    if (zb + 9 > zlast) break;
+    step(std::integral_constant<int, 9>{}, zb + 9);
+  }
+}
+
 // Tunables of the blocked kernel (set once per process from the environment
 // for sweeps; the defaults are the measured best on MI355X).
 struct BlockedConfig {
@@ -531,6 +882,7 @@ struct BlockedConfig {
   int threads2 = 512; // two-step kernel: work-group size (256, 512 or 1024)
   int bx2 = 0;       // two-step kernel: tile width (0: chosen per grid; 64, or 128 in FP32 3D)
   int x2 = -1;       // two-step kernel, FP32 3D, even nx: pairs of x-adjacent points per lane (-1: by the rule)
+  int split = 1;     // two-step kernel, 8-byte elements, 64 x 16 tile, 512 threads: wave_step2_split (0: blocked)
 };
 
 static BlockedConfig blocked_config(const Dims &d, size_t esz)
@@ -550,6 +902,7 @@ static BlockedConfig blocked_config(const Dims &d, size_t esz)
     if (const char *e = getenv("FFPAT_STENCIL2_ZCHUNK")) c.zchunk2 = atoi(e);
     if (const char *e = getenv("FFPAT_STENCIL2_BX")) c.bx2 = atoi(e) == 128 ? 128 : (atoi(e) == 64 ? 64 : 0);
     if (const char *e = getenv("FFPAT_STENCIL2_X2")) c.x2 = atoi(e) ? 1 : 0;
+    if (const char *e = getenv("FFPAT_STENCIL2_SPLIT")) c.split = atoi(e) ? 1 : 0;
     if (const char *e = getenv("FFPAT_STENCIL2_THREADS")) {
       const int v = atoi(e);
       c.threads2 = v == 1024 ? 1024 : (v == 256 ? 256 : 512);
@@ -635,6 +988,19 @@ static int device_cus()
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 0;
   if (dev >= 0 && dev < kMaxDevices) cache[dev].store(cus, std::memory_order_relaxed);
   return cus;
+}
+
+// Launch shape of wave_step2_split (the 64 x 16 tile of 8-byte elements, 512 threads).
+template <typename T>
+static PairShape pair_shape_split(const Dims &d, const BlockedConfig &cfg)
+{
+  static const int occ = [] {
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wave_step2_split<T, std::is_same_v<T, double>>,
+                                                        512, 0) == hipSuccess ? n : 0;
+  }();
+  const int cus = device_cus();
+  return pair_shape_for(d.nx, d.ny, d.nz, 64, 16, occ > 0 ? occ : 1, cus > 0 ? cus : 256, true, cfg.zchunk2);
 }
 
 template <typename T, int NDIM, int RY, int NTH, int BX>
@@ -749,12 +1115,30 @@ hipError_t launch_wave_pair(const Dims &d, const T *pm1, const T *pk, T *q_out, 
                            reinterpret_cast<uintptr_t>(kap)) & 7) == 0;
     if (aligned && pair_x2<T>(d, cfg)) {
       const Dims e = x2_dims(d);
+      if (cfg.split) {
+        const PairShape p = pair_shape_split<f32x2>(e, cfg);
+        const int grid = ((p.n_tiles + 7) / 8) * 8;
+        wave_step2_split<f32x2, false><<<grid, 512, 0, s>>>(
+            reinterpret_cast<const f32x2 *>(pm1), reinterpret_cast<const f32x2 *>(pk),
+            reinterpret_cast<f32x2 *>(q_out), reinterpret_cast<f32x2 *>(o_out), reinterpret_cast<const f32x2 *>(kap),
+            e.nx, e.ny, e.nz, p.zchunk, p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
+        return hipGetLastError();
+      }
       const PairShape p = pair_shape<f32x2, PairX2::ndim, PairX2::ry, PairX2::nth, PairX2::bx>(e, cfg);
       const int grid = ((p.n_tiles + 7) / 8) * 8;
       wave_step2_blocked<f32x2, PairX2::ndim, PairX2::ry, PairX2::nth, PairX2::bx><<<grid, PairX2::nth, 0, s>>>(
           reinterpret_cast<const f32x2 *>(pm1), reinterpret_cast<const f32x2 *>(pk),
           reinterpret_cast<f32x2 *>(q_out), reinterpret_cast<f32x2 *>(o_out), reinterpret_cast<const f32x2 *>(kap),
           e.nx, e.ny, e.nz, p.zchunk, p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (sizeof(T) == 8) {
+    if (cfg.split && pair_variant<T>(d, cfg) == PAIR_RY4_T512) {
+      const PairShape p = pair_shape_split<T>(d, cfg);
+      const int grid = ((p.n_tiles + 7) / 8) * 8;
+      wave_step2_split<T, true><<<grid, 512, 0, s>>>(pm1, pk, q_out, o_out, kap, d.nx, d.ny, d.nz, p.zchunk,
+                                                     p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
       return hipGetLastError();
     }
   }
@@ -774,17 +1158,23 @@ void wave_pair_shape(const Dims &d, int *tile_x, int *tile_y, int *zchunk)
   const BlockedConfig cfg = blocked_config(d, sizeof(T));
   if constexpr (sizeof(T) == 4) {
     if (pair_x2<T>(d, cfg)) {
-      const PairShape p = pair_shape<f32x2, PairX2::ndim, PairX2::ry, PairX2::nth, PairX2::bx>(x2_dims(d), cfg);
+      const PairShape p = cfg.split ? pair_shape_split<f32x2>(x2_dims(d), cfg)
+                                    : pair_shape<f32x2, PairX2::ndim, PairX2::ry, PairX2::nth, PairX2::bx>(x2_dims(d), cfg);
       *tile_x = 2 * p.bx;   // in points
       *tile_y = p.by;
       *zchunk = p.zchunk;
       return;
     }
   }
-  const PairShape p = visit_pair<T>(pair_variant<T>(d, cfg), [&](auto tag) {
-    using Tag = decltype(tag);
-    return pair_shape<T, Tag::ndim, Tag::ry, Tag::nth, Tag::bx>(d, cfg);
-  });
+  PairShape p;
+  if (sizeof(T) == 8 && cfg.split && pair_variant<T>(d, cfg) == PAIR_RY4_T512) {
+    p = pair_shape_split<double>(d, cfg);
+  } else {
+    p = visit_pair<T>(pair_variant<T>(d, cfg), [&](auto tag) {
+      using Tag = decltype(tag);
+      return pair_shape<T, Tag::ndim, Tag::ry, Tag::nth, Tag::bx>(d, cfg);
+    });
+  }
   *tile_x = p.bx;
   *tile_y = p.by;
   *zchunk = p.zchunk;
