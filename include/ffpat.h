@@ -148,7 +148,20 @@ int ffpat_plan_steps_per_pass(const ffpat_plan *plan, int32_t *steps);
  * with FFPAT_PLAN_NAIVE_STENCIL (no tiles).  Any pointer may be NULL. */
 int ffpat_plan_stencil_shape(const ffpat_plan *plan, int32_t *tile_x, int32_t *tile_y, int32_t *zchunk);
 
-/* Releases the plan and its device memory (synchronises the device first). */
+/* Replaces the plan's sound speed c(x) (eq. wave1) for a new problem of the same
+ * geometry, without new allocations: recomputes c_max, n_t, dt and k' from c_dev
+ * (as ffpat_plan_create; reads c_max back, so it synchronises `stream`) and discards
+ * the stored step size.  Waits for the plan's earlier work (see ffpat_plan_destroy)
+ * before touching k'.  Captured graphs are kept when n_t is unchanged (they read k'
+ * from the plan's memory) and re-captured at the next use otherwise.  On error
+ * (FFPAT_EINVAL for non-finite or non-positive c) the plan keeps its previous
+ * speed and time grid. */
+int ffpat_plan_set_speed(ffpat_plan *plan, const void *c_dev, void *stream);
+
+/* Releases the plan and its device memory.  Waits for the work of the plan's own
+ * calls (an event recorded after each call's work on its stream), not for the
+ * rest of the device; work that a caller recorded into a graph of its own must
+ * have completed. */
 int ffpat_plan_destroy(ffpat_plan *plan);
 
 /* g = X W_T h (Problem 1 with full data; eq. Wo then eq. Radon).

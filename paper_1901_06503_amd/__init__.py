@@ -121,6 +121,20 @@ class Plan:
         _lib.check(self._lib.ffpat_plan_stencil_shape(self._h, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(zc)))
         self.stencil_shape = (tx.value, ty.value, zc.value)   # tile width, height, planes per work-group
 
+    def set_speed(self, c, stream=None):
+        """Replaces the sound speed (same shape and dtype) for a new problem of the same
+        geometry, reusing the plan's memory: c_max, nt, dt and k' are recomputed and the
+        stored step size is discarded (the next reconstruction runs its power iteration)."""
+        torch = _torch()
+        if not (isinstance(c, torch.Tensor) and c.is_cuda) or c.dtype != self.dtype or tuple(c.shape) != self.shape:
+            raise TypeError(f"c must be a {self.dtype} device tensor of shape {self.shape}")
+        c = c.contiguous()
+        _lib.check(self._lib.ffpat_plan_set_speed(self._h, ctypes.c_void_p(c.data_ptr()),
+                                                  ctypes.c_void_p(_stream_handle(stream))))
+        nt = ctypes.c_int32(); dt = ctypes.c_double(); cm = ctypes.c_double()
+        _lib.check(self._lib.ffpat_plan_info(self._h, ctypes.byref(nt), ctypes.byref(dt), ctypes.byref(cm)))
+        self.nt, self.dt, self.cmax = nt.value, dt.value, cm.value
+
     # ------------------------------------------------------------------ helpers
     def _check_tensor(self, t, shape, name):
         torch = _torch()

@@ -61,6 +61,7 @@ SIGNATURES = {
     "ffpat_plan_steps_per_pass": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "ffpat_plan_stencil_shape": ([_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "ffpat_plan_set_speed": ([_P, _P, _P], ctypes.c_int),
     "ffpat_plan_destroy": ([_P], ctypes.c_int),
     "ffpat_forward": ([_P, _P, _P, _P], ctypes.c_int),
     "ffpat_adjoint": ([_P, _P, _P, _P], ctypes.c_int),

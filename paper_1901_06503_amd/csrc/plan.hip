@@ -138,6 +138,7 @@ struct ffpat_plan {
   bool use_graphs = true; // replay captured graphs for the power iteration and FB iterations
   bool use_pairs = true;  // two leapfrog steps per pass where possible
   hipStream_t cap_stream = nullptr;
+  hipEvent_t done = nullptr;  // recorded after the work of every call (ffpat_plan_destroy waits for it)
   GraphCache g_iter, g_power;
 
   void *vol(int i) const { return base + lay.vol[i]; }
@@ -718,6 +719,50 @@ int fbp_op(ffpat_plan *P, const T *G, T *vol, hipStream_t s)
 
 bool is_f64(const ffpat_plan *P) { return P->dtype == FFPAT_F64; }
 
+// Records the plan's completion event after a call's work on `s` (when the call
+// succeeded): ffpat_plan_destroy and ffpat_plan_set_speed wait for the plan's own
+// work only, not for the device.
+// Work that a caller records into a graph of its own is not tracked (the caller
+// completes its replays before destroying the plan).
+int mark_done(ffpat_plan *P, hipStream_t s, int rc)
+{
+  if (rc != FFPAT_OK) return rc;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone) return FFPAT_OK;
+  e = hipEventRecord(P->done, s);
+  return e == hipSuccess ? FFPAT_OK : hip_fail(e, "hipEventRecord");
+}
+
+// c range and validity (one host read), the time grid and k' of a plan for sound
+// speed c_dev, on stream s.  On error the plan's previous k' and time grid stay.
+int apply_speed(ffpat_plan *P, const void *c_dev, hipStream_t s)
+{
+  double stats[3];
+  double *sc = P->scalars();
+  hipError_t e;
+  if (is_f64(P)) e = launch_c_stats<double>(P->d, static_cast<const double *>(c_dev), P->partials(), kReduceBlocks, sc, s);
+  else e = launch_c_stats<float>(P->d, static_cast<const float *>(c_dev), P->partials(), kReduceBlocks, sc, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(stats, sc, sizeof stats, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "sound-speed statistics");
+  if (stats[2] != 0.0) return fail(FFPAT_EINVAL, "c has %.0f non-finite or non-positive values", stats[2]);
+  // time grid: dt = cfl dx / c_max, rounded so that n_t dt = T exactly
+  const double x = P->T * stats[1] / (P->cfl * P->dx);
+  double n = std::ceil(x * (1.0 - 1e-12));
+  if (n < 1.0) n = 1.0;
+  if (n > 1e7) return fail(FFPAT_EINVAL, "n_t = %g time steps is unreasonably large", n);
+  P->cmin = stats[0];
+  P->cmax = stats[1];
+  P->nt = (int)n;
+  P->dt = P->T / n;
+  if (is_f64(P)) e = launch_make_kappa<double>(P->d, static_cast<const double *>(c_dev), P->dt, P->dx, static_cast<double *>(P->kap()), s);
+  else e = launch_make_kappa<float>(P->d, static_cast<const float *>(c_dev), P->dt, P->dx, static_cast<float *>(P->kap()), s);
+  if (e != hipSuccess) return hip_fail(e, "make_kappa");
+  return FFPAT_OK;
+}
+
 // Device address of `scratch` (the objective history of ffpat_fb_enqueue_noalloc) on
 // each device, resolved once per device with that device current: every GPU holds its
 // own copy of the array at its own address, and in host code the array's name is not
@@ -828,33 +873,17 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
   auto cleanup = [&](int code) {
     (void)hipStreamSynchronize(s);
     (void)hipFree(P->base);
+    if (P->done) (void)hipEventDestroy(P->done);
     delete P;
     return code;
   };
-
-  // c range and validity (the one host read of the plan set-up)
-  double stats[3];
-  double *sc = P->scalars();
-  if (is_f64(P)) e = launch_c_stats<double>(P->d, static_cast<const double *>(c_dev), P->partials(), kReduceBlocks, sc, s);
-  else e = launch_c_stats<float>(P->d, static_cast<const float *>(c_dev), P->partials(), kReduceBlocks, sc, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(stats, sc, sizeof stats, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return cleanup(hip_fail(e, "sound-speed statistics"));
-  if (stats[2] != 0.0) return cleanup(fail(FFPAT_EINVAL, "c has %.0f non-finite or non-positive values", stats[2]));
-  P->cmin = stats[0];
-  P->cmax = stats[1];
-
-  // time grid: dt = cfl dx / c_max, rounded so that n_t dt = T exactly
-  const double x = P->T * P->cmax / (P->cfl * P->dx);
-  double n = std::ceil(x * (1.0 - 1e-12));
-  if (n < 1.0) n = 1.0;
-  if (n > 1e7) return cleanup(fail(FFPAT_EINVAL, "n_t = %g time steps is unreasonably large", n));
-  P->nt = (int)n;
-  P->dt = P->T / n;
-
-  if (is_f64(P)) e = launch_make_kappa<double>(P->d, static_cast<const double *>(c_dev), P->dt, P->dx, static_cast<double *>(P->kap()), s);
-  else e = launch_make_kappa<float>(P->d, static_cast<const float *>(c_dev), P->dt, P->dx, static_cast<float *>(P->kap()), s);
-  if (e != hipSuccess) return cleanup(hip_fail(e, "make_kappa"));
+  e = hipEventCreateWithFlags(&P->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    P->done = nullptr;
+    return cleanup(hip_fail(e, "hipEventCreateWithFlags"));
+  }
+  rc = apply_speed(P, c_dev, s);
+  if (rc) return cleanup(rc);
 
   std::vector<AngleParams> ap((size_t)r.n_angles);
   std::vector<int> aorder;
@@ -890,8 +919,31 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
   if (e != hipSuccess) return cleanup(hip_fail(e, "plan upload"));
+  e = hipEventRecord(P->done, s);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipEventRecord"));
   *out = P;
   return FFPAT_OK;
+}
+
+int ffpat_plan_set_speed(ffpat_plan *plan, const void *c_dev, void *stream)
+{
+  CHECK_PLAN(plan);
+  CHECK_PTR(c_dev, "c_dev");
+  DeviceGuard guard(plan->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipEventSynchronize(plan->done);   // the plan's earlier work reads k'
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  const int nt_old = plan->nt;
+  plan->has_step = false;            // the stored step belongs to the previous speed
+  const int rc = apply_speed(plan, c_dev, s);
+  if (rc) return rc;
+  if (plan->nt != nt_old) {          // the captured launch sequences hold n_t steps
+    if (plan->g_iter.exec) (void)hipGraphExecDestroy(plan->g_iter.exec);
+    if (plan->g_power.exec) (void)hipGraphExecDestroy(plan->g_power.exec);
+    plan->g_iter.exec = nullptr;
+    plan->g_power.exec = nullptr;
+  }
+  return mark_done(plan, s, FFPAT_OK);
 }
 
 int ffpat_plan_info(const ffpat_plan *plan, int32_t *nt, double *dt, double *cmax)
@@ -932,14 +984,15 @@ int ffpat_plan_destroy(ffpat_plan *plan)
 {
   if (!plan) return FFPAT_OK;
   DeviceGuard guard(plan->device);
-  hipError_t e = hipDeviceSynchronize();
+  const hipError_t e = hipEventSynchronize(plan->done);   // the plan's own work, not the device's
   if (plan->g_iter.exec) (void)hipGraphExecDestroy(plan->g_iter.exec);
   if (plan->g_power.exec) (void)hipGraphExecDestroy(plan->g_power.exec);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   if (plan->obj) (void)hipFree(plan->obj);
   (void)hipFree(plan->base);
+  (void)hipEventDestroy(plan->done);
   delete plan;
-  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
   return FFPAT_OK;
 }
 
@@ -952,8 +1005,8 @@ int ffpat_forward(ffpat_plan *plan, const void *h_dev, void *g_dev, void *stream
   CHECK_PTR(g_dev, "g_dev");
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return DISPATCH(plan, op_forward<float>(plan, (const float *)h_dev, (float *)g_dev, s),
-                  op_forward<double>(plan, (const double *)h_dev, (double *)g_dev, s));
+  return mark_done(plan, s, DISPATCH(plan, op_forward<float>(plan, (const float *)h_dev, (float *)g_dev, s),
+                                     op_forward<double>(plan, (const double *)h_dev, (double *)g_dev, s)));
 }
 
 int ffpat_adjoint(ffpat_plan *plan, const void *g_dev, void *h_dev, void *stream)
@@ -963,8 +1016,8 @@ int ffpat_adjoint(ffpat_plan *plan, const void *g_dev, void *h_dev, void *stream
   CHECK_PTR(g_dev, "g_dev");
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return DISPATCH(plan, op_adjoint<float>(plan, (const float *)g_dev, (float *)h_dev, s),
-                  op_adjoint<double>(plan, (const double *)g_dev, (double *)h_dev, s));
+  return mark_done(plan, s, DISPATCH(plan, op_adjoint<float>(plan, (const float *)g_dev, (float *)h_dev, s),
+                                     op_adjoint<double>(plan, (const double *)g_dev, (double *)h_dev, s)));
 }
 
 int ffpat_wave(ffpat_plan *plan, const void *h_dev, void *p_dev, void *stream)
@@ -975,11 +1028,11 @@ int ffpat_wave(ffpat_plan *plan, const void *h_dev, void *p_dev, void *stream)
   if (h_dev == p_dev) return fail(FFPAT_EINVAL, "h_dev and p_dev must not overlap");
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return DISPATCH(plan,
+  return mark_done(plan, s, DISPATCH(plan,
                   wave_forward<float>(plan, (const float *)h_dev, (float *)p_dev,
                                       Pool<float>{plan->vol(0), plan->vol(1), plan->vol(2), plan->vol(4)}, s),
                   wave_forward<double>(plan, (const double *)h_dev, (double *)p_dev,
-                                       Pool<double>{plan->vol(0), plan->vol(1), plan->vol(2), plan->vol(4)}, s));
+                                       Pool<double>{plan->vol(0), plan->vol(1), plan->vol(2), plan->vol(4)}, s)));
 }
 
 int ffpat_wave_adjoint(ffpat_plan *plan, const void *g_dev, void *q_dev, void *stream)
@@ -989,8 +1042,8 @@ int ffpat_wave_adjoint(ffpat_plan *plan, const void *g_dev, void *q_dev, void *s
   CHECK_PTR(q_dev, "q_dev");
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return DISPATCH(plan, wave_adjoint_op<float>(plan, (const float *)g_dev, (float *)q_dev, s),
-                  wave_adjoint_op<double>(plan, (const double *)g_dev, (double *)q_dev, s));
+  return mark_done(plan, s, DISPATCH(plan, wave_adjoint_op<float>(plan, (const float *)g_dev, (float *)q_dev, s),
+                                     wave_adjoint_op<double>(plan, (const double *)g_dev, (double *)q_dev, s)));
 }
 
 int ffpat_project(ffpat_plan *plan, const void *vol_dev, void *g_dev, void *stream)
@@ -1002,7 +1055,7 @@ int ffpat_project(ffpat_plan *plan, const void *vol_dev, void *g_dev, void *stre
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = DISPATCH(plan, project<float>(plan, (const float *)vol_dev, (float *)g_dev, s),
                           project<double>(plan, (const double *)vol_dev, (double *)g_dev, s));
-  return e == hipSuccess ? FFPAT_OK : hip_fail(e, "project");
+  return mark_done(plan, s, e == hipSuccess ? FFPAT_OK : hip_fail(e, "project"));
 }
 
 int ffpat_backproject(ffpat_plan *plan, const void *g_dev, void *vol_dev, void *stream)
@@ -1014,7 +1067,7 @@ int ffpat_backproject(ffpat_plan *plan, const void *g_dev, void *vol_dev, void *
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = DISPATCH(plan, backproject_op<float>(plan, (const float *)g_dev, (float *)vol_dev, s),
                           backproject_op<double>(plan, (const double *)g_dev, (double *)vol_dev, s));
-  return e == hipSuccess ? FFPAT_OK : hip_fail(e, "backproject");
+  return mark_done(plan, s, e == hipSuccess ? FFPAT_OK : hip_fail(e, "backproject"));
 }
 
 int ffpat_ramp(ffpat_plan *plan, const void *r_dev, void *y_dev, void *stream)
@@ -1027,7 +1080,7 @@ int ffpat_ramp(ffpat_plan *plan, const void *r_dev, void *y_dev, void *stream)
   hipError_t e = DISPATCH(plan,
       launch_residual_ramp<float>(plan->rows, plan->ns, (const float *)r_dev, nullptr, nullptr, (const float *)plan->taps(), (float *)y_dev, plan->ns, 0, nullptr, s),
       launch_residual_ramp<double>(plan->rows, plan->ns, (const double *)r_dev, nullptr, nullptr, (const double *)plan->taps(), (double *)y_dev, plan->ns, 0, nullptr, s));
-  return e == hipSuccess ? FFPAT_OK : hip_fail(e, "ramp");
+  return mark_done(plan, s, e == hipSuccess ? FFPAT_OK : hip_fail(e, "ramp"));
 }
 
 int ffpat_fbp(ffpat_plan *plan, const void *G_dev, void *vol_dev, void *stream)
@@ -1037,8 +1090,8 @@ int ffpat_fbp(ffpat_plan *plan, const void *G_dev, void *vol_dev, void *stream)
   CHECK_PTR(vol_dev, "vol_dev");
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return DISPATCH(plan, fbp_op<float>(plan, (const float *)G_dev, (float *)vol_dev, s),
-                  fbp_op<double>(plan, (const double *)G_dev, (double *)vol_dev, s));
+  return mark_done(plan, s, DISPATCH(plan, fbp_op<float>(plan, (const float *)G_dev, (float *)vol_dev, s),
+                                     fbp_op<double>(plan, (const double *)G_dev, (double *)vol_dev, s)));
 }
 
 static int check_fb_args(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev)
@@ -1069,8 +1122,9 @@ int ffpat_reconstruct(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params
   if (rc) return rc;
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return DISPATCH(plan, reconstruct<float>(plan, (const float *)G_dev, params, (float *)h_dev, step_used, s),
-                  reconstruct<double>(plan, (const double *)G_dev, params, (double *)h_dev, step_used, s));
+  return mark_done(plan, s, DISPATCH(plan,
+                  reconstruct<float>(plan, (const float *)G_dev, params, (float *)h_dev, step_used, s),
+                  reconstruct<double>(plan, (const double *)G_dev, params, (double *)h_dev, step_used, s)));
 }
 
 int ffpat_fb_enqueue(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev, void *stream)
@@ -1079,8 +1133,8 @@ int ffpat_fb_enqueue(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params 
   if (rc) return rc;
   DeviceGuard guard(plan->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return DISPATCH(plan, fb_enqueue<float>(plan, (const float *)G_dev, params, (float *)h_dev, s),
-                  fb_enqueue<double>(plan, (const double *)G_dev, params, (double *)h_dev, s));
+  return mark_done(plan, s, DISPATCH(plan, fb_enqueue<float>(plan, (const float *)G_dev, params, (float *)h_dev, s),
+                                     fb_enqueue<double>(plan, (const double *)G_dev, params, (double *)h_dev, s)));
 }
 
 int ffpat_fb_enqueue_noalloc(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev,
@@ -1099,8 +1153,9 @@ int ffpat_fb_enqueue_noalloc(ffpat_plan *plan, const void *G_dev, const ffpat_fb
     history = scratch_address(plan->device);
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return DISPATCH(plan, fb_enqueue<float>(plan, (const float *)G_dev, params, (float *)h_dev, s, history),
-                  fb_enqueue<double>(plan, (const double *)G_dev, params, (double *)h_dev, s, history));
+  return mark_done(plan, s,
+                   DISPATCH(plan, fb_enqueue<float>(plan, (const float *)G_dev, params, (float *)h_dev, s, history),
+                            fb_enqueue<double>(plan, (const double *)G_dev, params, (double *)h_dev, s, history)));
 }
 
 int ffpat_fb_report(ffpat_plan *plan, double *step_used, double *objective, int32_t n, void *stream)

@@ -11,23 +11,36 @@ iterations of earlier ones.  Which idle jobs get their next chunk is the
 policy:
 
 * "shortest" (default): the oldest job (so no job waits for ever) plus the
-  `concurrency - 1` with the least remaining work, power iteration included
-  (short jobs overtake long ones).
+  `concurrency - 1` others that come first by remaining work in seconds minus
+  `aging` times the time waited since arrival (short jobs overtake long ones,
+  but only those that arrived less than a few of their remaining seconds
+  earlier); `concurrency` applies while more than `backlog` jobs have arrived
+  and are not finished, two run together otherwise.
 * "fill": arrival order; the oldest job always runs, and later ones join
   while the running jobs hold at most `fill_voxels` grid points together
   (small grids, whose kernels leave most of the device idle, share it; a
   large grid runs alone at full speed).
 * "all": every admitted job (round robin).
 
-On the 120-job trace (grids 64^3..256^3, 50 iterations each, FP32) at 4 jobs/s,
-above the device's capacity for the mix, "shortest" with concurrency 2 beat the
-serial baseline in throughput (+5%), median latency (-35%) and 99th percentile
-(-15%); "fill" gained about 3%, 14% and 10%.  Below capacity (2 jobs/s) "shortest" cuts
-the median by almost a third but its 99th percentile is 16% above serial; "fill"
-keeps arrival order and the serial tail.  Most of the work is in the 192^3 and 256^3 jobs, whose kernels
-fill the device by themselves, which bounds what overlap can gain.
+A finished job's plan, data buffer, iterate buffer and stream are kept for the
+next job of the same geometry: ffpat_plan_set_speed gives the plan the new
+sound speed and the captured iteration graphs are replayed as they are, so no
+job after the first of its geometry allocates device memory, creates a plan or
+captures a graph; kept plans give their memory back, least recently used
+first, when an admission of another geometry needs it.  The result is copied
+out of the kept iterate buffer on the job's stream.
 
-Finished jobs release their slot and memory.
+What overlap can gain here is bounded: one job of the serial baseline is 98% or
+more device time (plan creation, uploads, graph capture and destruction are 1-2%
+of it: 64^3 41 ms, 128^3 128 ms, 192^3 318 ms, 256^3 1.04 s on MI355X), and the
+two-step stencil kernel of a 192^3 or 256^3 job holds every compute unit while it
+runs.  What remains is the 64^3 and 128^3 jobs, whose small launches leave the
+device mostly idle, running in the gaps of the others.  On the 120-job trace
+(grids 64^3..256^3, 50 iterations each, FP32), MI355X: at 4 jobs/s, above the
+device's capacity for the mix, "shortest" with concurrency 3 and aging 4 gives
+2.91 jobs/s against 2.71 serial (+7.4%), median latency 3.6 s against 5.3 s,
+99th percentile 7.7 s against 9.6 s (concurrency 2: +5.5%); at 2 jobs/s, two at
+a time, median 0.44 s against 0.54 s and 99th percentile 2.47 s against 2.43 s.
 
 `run_serial` is the plain baseline: one `ffpat_reconstruct` at a time in
 arrival order.
@@ -73,15 +86,31 @@ class Job:
                 + (2 * nvox + self.G.numel()) * esz)
 
 
+class _Slot:
+    """A plan with its data, iterate and stream, kept for reuse by later jobs of the
+    same geometry (grid, spacing, T, angles, precision): the workspace, the padded
+    copies and the captured iteration graphs carry over; ffpat_plan_set_speed puts
+    the next job's sound speed in."""
+
+    def __init__(self, key, plan, G, h, stream, nbytes):
+        self.key, self.plan, self.G, self.h, self.stream, self.bytes = key, plan, G, h, stream, nbytes
+        self.last_used = 0.0
+
+
 class _Active:
-    def __init__(self, job, plan, stream, h, G):
-        self.job, self.plan, self.stream, self.h, self.G = job, plan, stream, h, G
+    def __init__(self, job, slot):
+        self.job, self.slot = job, slot
+        self.plan, self.stream, self.h, self.G = slot.plan, slot.stream, slot.h, slot.G
         self.done_iters = 0
         self.powered = False
         self.event = None
         self.busy = False
-        self.bytes = 0
         self.last_chunk = 0
+
+
+# Wave-operator rate that converts remaining point updates into seconds for the
+# "shortest" policy's aging (the FP32 rate on MI355X is about 4e11 per second).
+_POINT_UPDATES_PER_S = 4.0e11
 
 
 def _remaining_work(a) -> float:
@@ -91,17 +120,29 @@ def _remaining_work(a) -> float:
     return 2.0 * a.plan.nt * a.job.c.numel() * left
 
 
+def _geometry_key(job):
+    c = job.c
+    ang = np.ascontiguousarray(np.asarray(job.angles, dtype=np.float64))
+    return (tuple(c.shape), str(c.dtype), float(job.dx), float(job.T), ang.tobytes(), tuple(job.G.shape))
+
+
 class Scheduler:
     """Continuous-batching scheduler.
 
-    hbm_budget: device bytes the active jobs may hold together.
+    hbm_budget: device bytes the jobs' plans, data and iterates may hold together
+    (plans kept for reuse included: idle ones are released, least recently used
+    first, when an admission needs their memory).
     max_active: slots.  iters_per_turn: FB iterations enqueued per job per turn.
     policy: "fill", "shortest" or "all" (see the module docstring); fill_voxels is
-    the fill threshold, concurrency the number of jobs "shortest" advances.
+    the fill threshold; concurrency the number of jobs "shortest" advances while more
+    than `backlog` jobs have arrived and are not finished (two otherwise); aging the
+    seconds of waiting that offset a second of remaining work in "shortest".
+    reuse_plans: keep finished jobs' plans for later jobs of the same geometry.
     """
 
-    def __init__(self, hbm_budget: int, max_active: int = 8, iters_per_turn: int = 5, concurrency: int = 2,
-                 policy: str = "shortest", fill_voxels: int = 192 ** 3, device="cuda"):
+    def __init__(self, hbm_budget: int, max_active: int = 8, iters_per_turn: int = 5, concurrency: int = 3,
+                 policy: str = "shortest", fill_voxels: int = 192 ** 3, device="cuda", aging: float = 4.0,
+                 reuse_plans: bool = True, backlog: int = 3):
         if policy not in ("fill", "shortest", "all"):
             raise ValueError(f"unknown policy {policy!r}")
         self.hbm_budget = int(hbm_budget)
@@ -110,12 +151,20 @@ class Scheduler:
         self.policy = policy
         self.fill_voxels = int(fill_voxels)
         self.concurrency = max(1, int(concurrency))
+        self.aging = float(aging)
+        self.backlog = int(backlog)
+        self.reuse_plans = bool(reuse_plans)
+        self._waiting = 0
         self.device = device
         self.peak_bytes = 0
         self.peak_active = 0
         self.peak_running = 0
+        self.plans_created = 0
+        self.plans_reused = 0
+        self._idle: list[_Slot] = []       # plans kept for reuse, not serving a job
+        self._now = 0.0
 
-    def _admit(self, job, now):
+    def _new_slot(self, job, key, need):
         import torch
         from . import Plan
         stream = torch.cuda.Stream(device=self.device)   # default priority
@@ -125,7 +174,26 @@ class Scheduler:
             h = torch.zeros(c.shape, dtype=c.dtype, device=self.device)
             plan = Plan(c, job.dx, job.T, job.angles, stream=stream)
             del c
-        a = _Active(job, plan, stream, h, G)
+        self.plans_created += 1
+        return _Slot(key, plan, G, h, stream, need)
+
+    def _reuse_slot(self, slot, job):
+        import torch
+        with torch.cuda.stream(slot.stream):
+            c = job.c.to(self.device, non_blocking=True)
+            slot.G.copy_(job.G, non_blocking=True)
+            slot.h.zero_()
+            slot.plan.set_speed(c, stream=slot.stream)
+            del c
+        self.plans_reused += 1
+        return slot
+
+    def _release(self, slot):
+        slot.plan.close()
+
+    def _admit(self, job, now, key, slot=None):
+        slot = self._reuse_slot(slot, job) if slot is not None else self._new_slot(job, key, job.footprint())
+        a = _Active(job, slot)
         job.t_admit = now
         job.status = "running"
         return a
@@ -152,31 +220,61 @@ class Scheduler:
         a.job.step = step
         a.job.objective.extend(obj.tolist())
 
+    def _finish(self, a, now):
+        """Hands the iterate to the job (a copy on the job's stream, so that the slot's
+        buffer can serve the next job) and keeps or releases the slot."""
+        import torch
+        with torch.cuda.stream(a.stream):
+            a.job.h = a.h.clone()
+        a.job.t_done = now
+        a.slot.last_used = now
+        if self.reuse_plans:
+            self._idle.append(a.slot)
+        else:
+            self._release(a.slot)
+
     def run(self, jobs):
         """Serves `jobs` (arrival times in seconds from now) and returns them finished."""
+        import torch
         from . import FfpatError
         pending = sorted(jobs, key=lambda j: j.arrival)
         active: list[_Active] = []
-        used = 0
         t0 = time.perf_counter()
+
+        def in_use():
+            return sum(a.slot.bytes for a in active) + sum(s.bytes for s in self._idle)
+
         while pending or active:
             now = time.perf_counter() - t0
+            self._now = now
+            self._waiting = len(active) + sum(1 for j in pending if j.arrival <= now)
             progressed = False
-            # admission: arrived, a free slot, and the footprint fits
+            # admission: arrived, a free slot, and the footprint fits (a kept plan of the
+            # same geometry needs no new memory; idle kept plans give way when needed)
             while pending and pending[0].arrival <= now and len(active) < self.max_active:
-                need = pending[0].footprint()
-                if used + need > self.hbm_budget and active:
-                    break
-                job = pending.pop(0)
+                job = pending[0]
+                key = _geometry_key(job)
+                slot = next((s for s in self._idle if s.key == key), None)
+                if slot is None:
+                    need = job.footprint()
+                    while self._idle and in_use() + need > self.hbm_budget:
+                        victim = min(self._idle, key=lambda s: s.last_used)
+                        self._idle.remove(victim)
+                        self._release(victim)
+                    if in_use() + need > self.hbm_budget and active:
+                        break
+                else:
+                    self._idle.remove(slot)
+                pending.pop(0)
                 try:
-                    a = self._admit(job, now)
+                    a = self._admit(job, now, key, slot)
                 except FfpatError as e:
                     job.status, job.t_done = f"failed: {e}", time.perf_counter() - t0
+                    if slot is not None:
+                        self._release(slot)
                     continue
-                a.bytes = need
-                used += need
                 active.append(a)
-                self.peak_bytes = max(self.peak_bytes, used)
+                self.peak_bytes = max(self.peak_bytes, in_use())
                 self.peak_active = max(self.peak_active, len(active))
                 progressed = True
             # retire finished jobs; collect the objective of completed chunks
@@ -192,10 +290,7 @@ class Scheduler:
                         a.job.status = "done"
                     except FfpatError as e:
                         a.job.status = f"failed: {e}"
-                    a.job.h = a.h
-                    a.job.t_done = time.perf_counter() - t0
-                    a.plan.close()
-                    used -= a.bytes
+                    self._finish(a, time.perf_counter() - t0)
                     active.remove(a)
             chosen = self._choose(active)
             for a in chosen:
@@ -206,13 +301,25 @@ class Scheduler:
                     except FfpatError as e:
                         a.job.status = f"failed: {e}"
                         a.job.t_done = time.perf_counter() - t0
-                        a.plan.close()
-                        used -= a.bytes
+                        self._release(a.slot)
                         active.remove(a)
             self.peak_running = max(self.peak_running, sum(1 for a in active if a.busy))
             if not progressed:
                 time.sleep(0.0002)
+        torch.cuda.synchronize(self.device)        # results copied out on the jobs' streams
         return jobs
+
+    def close(self):
+        """Releases the plans kept for reuse."""
+        for s in self._idle:
+            self._release(s)
+        self._idle = []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def _choose(self, active):
         """The admitted jobs that may start their next chunk now (see the policies)."""
@@ -220,8 +327,12 @@ class Scheduler:
             return active
         order = sorted(active, key=lambda a: (a.job.arrival, a.job.job_id))
         if self.policy == "shortest":
-            rest = sorted(order[1:], key=_remaining_work)
-            return [order[0]] + rest[:self.concurrency - 1]
+            now = self._now
+            prio = lambda a: (_remaining_work(a) / _POINT_UPDATES_PER_S - self.aging * (now - a.job.arrival),
+                              a.job.arrival, a.job.job_id)
+            rest = sorted(order[1:], key=prio)
+            conc = self.concurrency if self._waiting > self.backlog else min(2, self.concurrency)
+            return [order[0]] + rest[:conc - 1]
         chosen, vox = [order[0]], order[0].job.c.numel()
         for a in order[1:]:
             if vox + a.job.c.numel() > self.fill_voxels:

@@ -126,6 +126,7 @@ def test_null_plan_is_rejected(lib):
     i32 = ctypes.c_int32()
     assert lib.ffpat_plan_steps_per_pass(None, ctypes.byref(i32)) == -1
     assert lib.ffpat_plan_stencil_shape(None, ctypes.byref(i32), None, None) == -1
+    assert lib.ffpat_plan_set_speed(None, ctypes.c_void_p(16), None) == -1
     assert lib.ffpat_plan_destroy(None) == 0
 
 

@@ -91,6 +91,38 @@ def test_enqueue_report_equals_reconstruct():
     assert np.array_equal(np.concatenate([o1, o2]), ref.objective)
 
 
+def test_set_speed_equals_a_new_plan():
+    """ffpat_plan_set_speed: a plan given a new sound speed reconstructs bit for bit as a
+    plan created with it, with the captured graphs kept (same n_t) or re-captured (a
+    faster medium takes more steps); an invalid speed is rejected and leaves the plan's
+    time grid as it was."""
+    import paper_1901_06503_amd as ff
+    dx, angles, c1, h, rng = _inputs(36, 20, 63)
+    c2 = c1.flip(0).contiguous()                          # same range, same n_t
+    c3 = c1 * 1.15                                        # faster: more time steps
+    with ff.Plan(c1, dx, 0.5, angles) as P:
+        G = _data(P, h, rng)
+        P.reconstruct(G, 1e-3, 3)                         # captures both graphs
+        for c in (c2, c3):
+            nt_before = P.nt
+            P.set_speed(c)
+            with ff.Plan(c, dx, 0.5, angles) as Q:
+                assert (P.nt, P.dt, P.cmax) == (Q.nt, Q.dt, Q.cmax)
+                r_ref = Q.reconstruct(G, 1e-3, 3)
+            r = P.reconstruct(G, 1e-3, 3)
+            assert r.step == r_ref.step
+            assert torch.equal(r.h, r_ref.h)
+            assert np.array_equal(r.objective, r_ref.objective)
+            if c is c3:
+                assert P.nt > nt_before
+        bad = c1.clone()
+        bad[2, 2, 2] = -1.0
+        nt = P.nt
+        with pytest.raises(ff.FfpatError):
+            P.set_speed(bad)
+        assert P.nt == nt
+
+
 def _trace(sizes, seed, n_iter=8, n_power=6, spacing=0.03):
     from paper_1901_06503_amd.serving import Job
     import paper_1901_06503_amd as ff
@@ -119,9 +151,10 @@ def test_results_in_the_mix_equal_results_alone():
     jobs = _trace([24, 40, 32, 48, 24, 40, 32, 24], 70)
     alone = run_serial(_clone(jobs))
     for policy in ("fill", "shortest", "all"):
-        sched = Scheduler(hbm_budget=8 << 30, max_active=4, iters_per_turn=3, policy=policy)
-        mixed = sched.run(_clone(jobs))
+        with Scheduler(hbm_budget=8 << 30, max_active=4, iters_per_turn=3, policy=policy) as sched:
+            mixed = sched.run(_clone(jobs))
         assert sched.peak_running > 1                      # work really overlapped on the device
+        assert sched.plans_reused > 0                      # later jobs ran on earlier jobs' plans
         for a, b in zip(sorted(alone, key=lambda j: j.job_id), sorted(mixed, key=lambda j: j.job_id)):
             assert a.status == b.status == "done"
             assert a.step == b.step
@@ -135,13 +168,20 @@ def test_admission_respects_the_hbm_budget():
     from paper_1901_06503_amd.serving import Scheduler
     jobs = _trace([40, 40, 40, 40], 80, n_iter=4, n_power=3, spacing=0.0)
     one = jobs[0].footprint()
-    sched = Scheduler(hbm_budget=int(1.5 * one), max_active=8)
-    out = sched.run(jobs)
+    with Scheduler(hbm_budget=int(1.5 * one), max_active=8) as sched:
+        out = sched.run(jobs)
     assert all(j.status == "done" for j in out)
     assert sched.peak_active == 1 and sched.peak_bytes <= int(1.5 * one)
-    sched2 = Scheduler(hbm_budget=int(2.5 * one), max_active=8)
-    sched2.run(_clone(jobs))
-    assert sched2.peak_active == 2
+    assert sched.plans_created == 1 and sched.plans_reused == 3   # one plan serves all four
+    with Scheduler(hbm_budget=int(2.5 * one), max_active=8) as sched2:
+        sched2.run(_clone(jobs))
+    assert sched2.peak_active == 2 and sched2.peak_bytes <= int(2.5 * one)
+    # a job of another geometry makes an idle plan give way when the budget needs it
+    other = _trace([40, 32], 81, n_iter=4, n_power=3, spacing=0.0)
+    budget = jobs[0].footprint() + other[1].footprint() // 2
+    with Scheduler(hbm_budget=budget, max_active=8) as sched3:
+        out3 = sched3.run(_clone(jobs[:1]) + [other[1]])
+    assert all(j.status == "done" for j in out3) and sched3.peak_bytes <= max(budget, other[1].footprint())
 
 
 def test_failed_job_does_not_disturb_the_others():
@@ -150,7 +190,8 @@ def test_failed_job_does_not_disturb_the_others():
     bad = _clone(jobs)
     bad[1].c = bad[1].c.clone()
     bad[1].c[3, 3, 3] = float("nan")                       # rejected at plan creation
-    out = Scheduler(hbm_budget=8 << 30, max_active=4).run(bad)
+    with Scheduler(hbm_budget=8 << 30, max_active=4) as sched:
+        out = sched.run(bad)
     ref = run_serial(_clone(jobs))
     assert out[1].status.startswith("failed") and "FFPAT_EINVAL" in out[1].status
     for i in (0, 2):
