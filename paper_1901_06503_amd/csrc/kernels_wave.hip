@@ -527,10 +527,12 @@ wave_step2_blocked(const T *__restrict__ pm1, const T *__restrict__ pk, T *__res
 //   slots 0 and 1: the tile's 1024 interior points, one 64-wide row per
 //     wavefront and slot (coalesced); they run stage 1 and stage 2 and keep the
 //     q and k' z-windows;
-//   slot 2: the 416 other points of the LDS region's rows 2..21 (the extended
-//     tile's 2-point halo and the two outer columns on each side), threads
-//     0..415; stage 1 only, so no q or k' windows;
-//   ring: rows 0, 1, 22, 23 of the p(k) plane (288 points), threads 0..287.
+//   slot 2: the other points of the LDS region's rows 2..21 (the extended tile's
+//     2-point halo and the two outer points on each side; 416 elements in FP64,
+//     336 pairs), stage 1 only, so no q or k' windows;
+//   ring: rows 0, 1, 22, 23 of the p(k) plane (288 elements, 272 pairs).
+// The x halos are counted in elements: pairs of points need half the elements
+// (and stage 1 half the halo columns) that single points do.
 // Stage 1 issues the LDS reads of all three slots before any arithmetic and
 // stage 2 those of both interior slots, so each stage waits for LDS once per
 // plane.  Stage 1 runs on every slot unconditionally; a point off the grid or
@@ -631,11 +633,15 @@ wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
                  int zchunk, int tiles_x, int tiles_y, int n_tiles, int xy_fastest)
 {
   constexpr int NTH = 512, BX = 64, BY = 16;
-  constexpr int EX = BX + 4, EY = BY + 4;    // stage-1 region (68 x 20)
-  constexpr int KX = BX + 8, KY = BY + 8;    // p(k) plane in LDS (72 x 24)
+  // x halos in elements: the p(k) plane needs 4 points on each side, stage 1 runs on
+  // 2 more points on each side than the tile: 4 and 2 elements in FP64, 2 and 1 for
+  // pairs of points
+  constexpr int XH = NbrX<T>::N == 2 ? 2 : 4, SH = XH / 2;
+  constexpr int EY = BY + 4;                 // stage-1 rows
+  constexpr int KX = BX + 2 * XH, KY = BY + 8;   // p(k) plane in LDS (FP64 72 x 24, pairs 68 x 24)
   constexpr int NIN = BX * BY / NTH;         // interior slots per thread (2)
-  constexpr int NHALO = KX * EY - BX * BY;   // other points of LDS rows 2..KY-3 (416)
-  constexpr int NRING = 4 * KX;              // LDS rows 0, 1, KY-2, KY-1 (288)
+  constexpr int NHALO = KX * EY - BX * BY;   // other points of LDS rows 2..KY-3 (FP64 416, pairs 336)
+  constexpr int NRING = 4 * KX;              // LDS rows 0, 1, KY-2, KY-1 (FP64 288, pairs 272)
   constexpr int PPT = NIN + 1;
   constexpr int NB = NbrX<T>::N + 4;         // LDS reads per point and stage
   static_assert(BX * BY == NIN * NTH && NHALO <= NTH && NRING <= NTH, "slot layout");
@@ -677,27 +683,27 @@ wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
     if (m < NIN) {
       const int i = tid + NTH * m;
       ey = 2 + i / BX;
-      ex = 4 + i % BX;
+      ex = XH + i % BX;
     } else if (tid < 4 * KX) {             // extended rows 0, 1, EY-2, EY-1, full width
       const int r = tid / KX;
       ey = r < 2 ? r : EY - 4 + r;
       ex = tid - r * KX;
-    } else if (tid < NHALO) {              // rows 2..EY-3, columns 0..3 and KX-4..KX-1
+    } else if (tid < NHALO) {              // rows 2..EY-3, columns 0..XH-1 and KX-XH..KX-1
       const int j = tid - 4 * KX;
-      ey = 2 + j / 8;
-      const int cc = j % 8;
-      ex = cc < 4 ? cc : KX - 8 + cc;
+      ey = 2 + j / (2 * XH);
+      const int cc = j % (2 * XH);
+      ex = cc < XH ? cc : KX - 2 * XH + cc;
     } else {                               // no halo point: reads around an interior position
       has = false;
       ey = 2;
-      ex = 4;
+      ex = XH;
     }
     lofs[m] = (ey + 2) * KX + ex;
     lwr[m] = has ? lofs[m] : KY * KX;      // the spare word
     qofs[m] = has ? ey * KX + ex : 0;      // q column 0: never read
-    const int gx = x0 - 4 + ex, gy = y0 - 2 + ey;
+    const int gx = x0 - XH + ex, gy = y0 - 2 + ey;
     ingw[m] = has && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    ing[m] = ingw[m] && ex >= 2 && ex < EX + 2;   // a stage-1 point of the grid
+    ing[m] = ingw[m] && ex >= XH - SH && ex < XH + BX + SH;   // a stage-1 point of the grid
     boff[m] = (unsigned)((min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1)) * sizeof(T));
     if (m < NIN) soff[m] = ing[m] ? boff[m] : 0xFFFFFFF0u;
 #pragma unroll
@@ -729,7 +735,7 @@ wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
     const int lr = hr < 2 ? hr : KY - 4 + hr;
     const int lc = has_ring ? tid - hr * KX : 0;
     rl = lr * KX + lc;
-    const int gx = x0 - 4 + lc, gy = y0 - 4 + lr;
+    const int gx = x0 - XH + lc, gy = y0 - 4 + lr;
     rin = has_ring && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     roff = (unsigned)((min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1)) * sizeof(T));
   }
