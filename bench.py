@@ -447,10 +447,22 @@ def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
     with ff.Plan(c, dx, T, angles, two_step_stencil=False) as ps:
         t_single = time_wave(torch, ps) / ps.nt
     pairs, singles = divmod(plan.nt - 1, 2)
-    out.update(kernel="wave_step2_blocked", t_launch=(t_w - (1 + singles) * t_single) / pairs,
+    out.update(kernel=pair_kernel_name(plan, dtype == torch.float64), t_launch=(t_w - (1 + singles) * t_single) / pairs,
                alg_bytes=2 * 4 * esz * nvox, compulsory_bytes=5 * esz * nvox, updates_per_launch=2,
                t_single_launch=t_single)
     return out
+
+
+def pair_kernel_name(plan, f64):
+    """The two-step kernel a plan's pair launches run: wave_step2_split for 8-byte
+    elements with the 64 x 16 element tile (FP64, and FP32 as pairs of x-adjacent
+    points, a 128-point-wide tile on a grid of even nx), else wave_step2_blocked."""
+    if os.environ.get("FFPAT_STENCIL2_SPLIT", "1") == "0":
+        return "wave_step2_blocked"
+    tx, ty, _ = plan.stencil_shape
+    if f64:
+        return "wave_step2_split" if (tx, ty) == (64, 16) else "wave_step2_blocked"
+    return "wave_step2_split" if tx == 128 and plan.shape[2] % 2 == 0 else "wave_step2_blocked"
 
 
 def operator_384(torch, ff, synth, seed):
@@ -588,7 +600,7 @@ def main():
     log(f"{roof['kernel']} {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s algorithmic, "
         f"{achieved_c:.0f} GB/s compulsory; W_T {roof['t_wave'] * 1e3:.2f} ms, {gpt:.1f} Gpt-updates/s")
     ceiling = (stream_ceiling(torch, roof["compulsory_bytes"], achieved_c)
-               if roof["kernel"] == "wave_step2_blocked" else None)
+               if roof["kernel"].startswith("wave_step2") else None)
     log(f"streaming ceiling of the same streams: {ceiling}")
 
     fp64 = None
