@@ -40,6 +40,16 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def build_sanitized(path: str) -> str:
+    """Compiles the oracle with AddressSanitizer and UndefinedBehaviorSanitizer (gcc,
+    -O1 -g, errors fatal) into `path`, for the CPU tests' sanitizer run; the process
+    that loads it preloads gcc's sanitizer runtimes."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-fopenmp", "-std=c99", "-D_DEFAULT_SOURCE", "-shared", "-fPIC",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+                           _SRC, "-o", path, "-lm"])
+    return path
+
+
 class _Geom(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("ndim", ctypes.c_int32), ("dx", ctypes.c_double), ("T", ctypes.c_double),
@@ -54,8 +64,11 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        path = os.environ.get("FFPAT_ORACLE_LIB")   # the sanitizer build, in the CPU tests' sanitizer run
+        if not path:
+            build()
+            path = _LIB
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         G = ctypes.POINTER(_Geom)
         for name, args, res in [

@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libffpat.so")
+# FFPAT_LIB_PATH selects another build of the same library (the CPU tests' sanitizer
+# build); by default the in-tree libffpat.so
+LIB_PATH = os.environ.get("FFPAT_LIB_PATH") or os.path.join(HERE, "libffpat.so")
 
 OK, EINVAL, ECFL, ENOMEM, EHIP, EDIVERGED, EDTYPE, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {OK: "FFPAT_OK", EINVAL: "FFPAT_EINVAL", ECFL: "FFPAT_ECFL", ENOMEM: "FFPAT_ENOMEM",

@@ -56,6 +56,35 @@ def _link(objs, lib: str):
     os.replace(tmp, lib)
 
 
+# Host-side sanitizer build for the CPU tests (no GPU needed): AddressSanitizer and
+# UndefinedBehaviorSanitizer on the host code only (each flag behind -Xarch_host), so
+# the argument checks, layouts and launch-shape rules of the C ABI run instrumented.
+# The library leaves the sanitizer runtime to the process (preloaded by the test).
+SAN_DIR = os.path.join(BUILD_DIR, "san")
+SAN_HOST_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(jobs: int = 4) -> str:
+    """Builds _build/san/libffpat.so with the host code under ASan and UBSan (-O1 -g)."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    flags = [f for f in HIP_FLAGS if f != "-O3"] + ["-O1", "-g"] + SAN_HOST_FLAGS
+
+    def one(src):
+        obj = os.path.join(SAN_DIR, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc()] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compiling {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        objs = list(ex.map(one, SOURCES))
+    lib = os.path.join(SAN_DIR, "libffpat.so")
+    _link(objs, lib)
+    return lib
+
+
 def build(jobs: int = 4, verbose: bool = False) -> str:
     """Compiles every source (always, also when a library exists) and links
     libffpat.so and libffpat_probe.so."""

@@ -26,8 +26,9 @@ def cli(tmp_path_factory):
     if gxx is None:
         pytest.skip("g++ not available")
     exe = str(tmp_path_factory.mktemp("rules") / "launch_rules_cli")
-    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Werror", "-I" + CSRC,
-                    os.path.join(HERE, "launch_rules_cli.cpp"), "-o", exe], check=True)
+    extra = os.environ.get("FFPAT_TEST_HOST_CFLAGS", "").split()   # the sanitizer run adds -fsanitize=...
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Werror", "-I" + CSRC] + extra +
+                   [os.path.join(HERE, "launch_rules_cli.cpp"), "-o", exe], check=True)
     return exe
 
 
