@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--naive-stencil", action="store_true")
     ap.add_argument("--n", type=int, default=0, help="--mode wave: grid edge instead of the recipe's")
     ap.add_argument("--nz", type=int, default=0, help="--mode wave: planes (default: the grid edge)")
-    ap.add_argument("--stencil", default="auto", choices=["auto", "single", "pairs"],
+    ap.add_argument("--stencil", default="auto", choices=["auto", "single", "pairs", "triples"],
                     help="--mode wave: leapfrog steps per stencil pass (auto: the plan's choice)")
     ap.add_argument("--seed", type=int, default=3001)
     ap.add_argument("--blocks", type=int, default=0,
@@ -245,7 +245,7 @@ def run_wave_only(args):
     c = synth.sound_speed((nz, n, n), dx, np.random.default_rng(args.seed), r["bumps"], r["amp"], r["clamp"])
     plan = ff.Plan(torch.from_numpy(c).to("cuda", dtype), dx, r["T"], synth.uniform_angles(r["n_angles"]),
                    naive_stencil=args.naive_stencil,
-                   two_step_stencil={"auto": None, "single": False, "pairs": True}[args.stencil])
+                   stencil_steps={"auto": None, "single": 1, "pairs": 2, "triples": 3}[args.stencil])
     h = torch.randn((nz, n, n), dtype=dtype, device="cuda")
     out = torch.empty_like(h)
     plan.wave(h, out=out)
@@ -426,37 +426,52 @@ def time_wave(torch, plan, reps=3):
 
 def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
     """The dominant kernel of the path (the leapfrog stencil) and its average launch
-    duration, measured live.  A W_T solve is n_t leapfrog steps: with one step per
-    pass, n_t launches of wave_step_blocked; with two steps per pass, one first-step
-    launch, P = (n_t - 1) // 2 launches of wave_step2_blocked and S = (n_t - 1) % 2
-    single-step launches.  The pair kernel's duration is then
-    (t(W_T) - (1 + S) t_single) / P, with t_single measured on a plan that runs one
-    step per pass.
+    duration, measured live.  A forward W_T solve is n_t leapfrog steps: with one step
+    per pass, n_t launches of wave_step_blocked; with k = 2 or 3 steps per pass, one
+    first-step launch, M = (n_t - 1) // k launches of the k-step kernel and a shorter
+    pass for the remaining (n_t - 1) % k steps (a single step, or a pair of steps in a
+    two-step launch).  The k-step kernel's duration is (t(W_T) - t_first - t_rest) / M,
+    with the single-step duration measured on a plan that runs one step per pass and
+    the pair duration, where needed, derived the same way on a two-step plan.
     Bytes per launch, two ways: algorithmic = 4 words per point update (read p(k),
     p(k-1), k'; write p(k+1): 16 B FP32, 32 B FP64) x the updates a launch makes per
-    voxel (1 or 2); compulsory = the words per voxel a launch must move at least
-    (4 for one step; read p(k-1), p(k), k', write p(k+1), p(k+2): 5 for two)."""
+    voxel (1, 2 or 3); compulsory = the words per voxel a launch must move at least
+    (4 for one step; read p(k-1), p(k), k', write the last two levels: 5 for two or
+    three steps)."""
     esz = 4 if dtype == torch.float32 else 8
     nvox = math.prod(plan.shape)
     t_w = time_wave(torch, plan)
-    out = {"t_wave": t_w, "steps_per_pass": plan.steps_per_pass}
-    if plan.steps_per_pass == 1:
+    k = plan.steps_per_pass
+    out = {"t_wave": t_w, "steps_per_pass": k}
+    if k == 1:
         out.update(kernel="wave_step_blocked", t_launch=t_w / plan.nt, alg_bytes=4 * esz * nvox,
                    compulsory_bytes=4 * esz * nvox, updates_per_launch=1)
         return out
-    with ff.Plan(c, dx, T, angles, two_step_stencil=False) as ps:
+    with ff.Plan(c, dx, T, angles, stencil_steps=1) as ps:
         t_single = time_wave(torch, ps) / ps.nt
-    pairs, singles = divmod(plan.nt - 1, 2)
-    out.update(kernel=pair_kernel_name(plan, dtype == torch.float64), t_launch=(t_w - (1 + singles) * t_single) / pairs,
-               alg_bytes=2 * 4 * esz * nvox, compulsory_bytes=5 * esz * nvox, updates_per_launch=2,
+    t_pair = None
+    if k == 3:
+        with ff.Plan(c, dx, T, angles, stencil_steps=2) as p2:
+            t_w2 = time_wave(torch, p2)
+            pairs2, singles2 = divmod(p2.nt - 1, 2)
+            t_pair = (t_w2 - (1 + singles2) * t_single) / pairs2
+    full, rest = divmod(plan.nt - 1, k)
+    t_rest = 0.0 if rest == 0 else (t_single if rest == 1 else t_pair)
+    out.update(kernel=multi_kernel_name(plan, dtype == torch.float64), t_launch=(t_w - t_single - t_rest) / full,
+               alg_bytes=k * 4 * esz * nvox, compulsory_bytes=5 * esz * nvox, updates_per_launch=k,
                t_single_launch=t_single)
+    if t_pair is not None:
+        out["t_pair_launch"] = t_pair
     return out
 
 
-def pair_kernel_name(plan, f64):
-    """The two-step kernel a plan's pair launches run: wave_step2_split for 8-byte
-    elements with the 64 x 16 element tile (FP64, and FP32 as pairs of x-adjacent
-    points, a 128-point-wide tile on a grid of even nx), else wave_step2_blocked."""
+def multi_kernel_name(plan, f64):
+    """The kernel a plan's multi-step launches run: wave_step3_split for three steps
+    per pass; for two, wave_step2_split with 8-byte elements and the 64 x 16 element
+    tile (FP64, and FP32 as pairs of x-adjacent points, a 128-point-wide tile on a
+    grid of even nx), else wave_step2_blocked."""
+    if plan.steps_per_pass == 3:
+        return "wave_step3_split"
     if os.environ.get("FFPAT_STENCIL2_SPLIT", "1") == "0":
         return "wave_step2_blocked"
     tx, ty, _ = plan.stencil_shape
@@ -471,8 +486,8 @@ def operator_384(torch, ff, synth, seed):
     (226 MB FP32) exceeds the 256 MB MALL with the others: the operator HBM fraction
     (w N^3 n_t + w N^3 + w N_phi N^2) / t_A / 8 TB/s, w = 4 words of the field type
     per point update and one per voxel and per bin for the projection, t_A from HIP
-    events around back-to-back applications, in FP32 and FP64; and the pair launch's
-    duration and algorithmic rate there."""
+    events around back-to-back applications, in FP32 and FP64; and the multi-step
+    launch's duration and algorithmic rate there."""
     out = {"workload": "384^3 grid, 360 angles, T=0.6, c in [0.75, 1.25] (10 bumps)"}
     n, nang = 384, 360
     for name, dtype in (("f32", torch.float32), ("f64", torch.float64)):
@@ -600,7 +615,7 @@ def main():
     log(f"{roof['kernel']} {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s algorithmic, "
         f"{achieved_c:.0f} GB/s compulsory; W_T {roof['t_wave'] * 1e3:.2f} ms, {gpt:.1f} Gpt-updates/s")
     ceiling = (stream_ceiling(torch, roof["compulsory_bytes"], achieved_c)
-               if roof["kernel"].startswith("wave_step2") else None)
+               if roof["kernel"] != "wave_step_blocked" else None)
     log(f"streaming ceiling of the same streams: {ceiling}")
 
     fp64 = None
@@ -676,8 +691,8 @@ def main():
                      "avg_launch_us": t_launch * 1e6,
                      "compulsory": {"bytes_per_launch": roof["compulsory_bytes"], "achieved": achieved_c,
                                     "frac": achieved_c / HBM_PEAK_GBS,
-                                    "byte_unit": "words a launch must move per voxel (5 for two steps: read "
-                                                 "p(k-1), p(k), k', write p(k+1), p(k+2))"},
+                                    "byte_unit": "words a launch must move per voxel (5 for two or three "
+                                                 "steps: read p(k-1), p(k), k', write the last two levels)"},
                      "stream_ceiling": ceiling,
                      "target": "the >= 0.60 HBM target applies to the operator HBM fraction of A = X W_T at "
                                "384^3 (operator_384.*.operator_hbm_frac, beyond the 256 MB MALL)"},

@@ -85,11 +85,16 @@ typedef struct {
 #define FFPAT_PLAN_NAIVE_STENCIL 1u   /* unblocked stencil kernel (for comparison) */
 #define FFPAT_PLAN_NO_GRAPHS 2u       /* launch every kernel eagerly instead of replaying captured graphs */
 #define FFPAT_PLAN_SINGLE_STEP 4u     /* one leapfrog step per stencil pass (no temporal blocking) */
-#define FFPAT_PLAN_TWO_STEP 8u        /* two leapfrog steps per stencil pass wherever the chain allows.
-                                         With neither of these two flags the plan chooses: two steps per
-                                         pass for grids of 128^3 voxels or more, where that kernel is
-                                         measured faster, one step otherwise.  Both: EINVAL.
-                                         Planes of 2^31 bytes or more always take one step per pass. */
+#define FFPAT_PLAN_TWO_STEP 8u        /* at most two leapfrog steps per stencil pass, two wherever the
+                                         chain allows */
+#define FFPAT_PLAN_THREE_STEP 32u     /* three leapfrog steps per stencil pass wherever the chain and the
+                                         grid allow (3D; FP32 with even nx where the 128 x 16 tile is
+                                         chosen, FP64), two otherwise.
+                                         With none of these three flags the plan chooses, by measurement:
+                                         one step per pass below 128^3 voxels; from 128^3 on two, or in
+                                         FP32 three where the three-step kernel applies.  More than one:
+                                         EINVAL.  Planes of 2^31 bytes or more always take one step per
+                                         pass. */
 
 /* Reconstruction flags (ffpat_fb_params.flags) */
 #define FFPAT_POSITIVITY 1u   /* R includes the indicator of h >= 0 (prox clamps at 0) */
@@ -136,9 +141,10 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
 int ffpat_plan_info(const ffpat_plan *plan, int32_t *nt, double *dt, double *cmax);
 
 /* Leapfrog steps per stencil pass that the plan's wave solves use (eq. leapfrog):
- * 2 when the temporally blocked kernel runs (see FFPAT_PLAN_TWO_STEP), else 1.
- * A W_T solve is one first-step pass, then pairs, then a single pass when the
- * remaining n_t - 1 steps are odd. */
+ * 3 or 2 when a temporally blocked kernel runs (see FFPAT_PLAN_THREE_STEP), else 1.
+ * A W_T solve is one first-step pass, then passes of that many steps, then a
+ * shorter pass for the remainder (the adjoint's last step, which divides by k',
+ * always alone). */
 int ffpat_plan_steps_per_pass(const ffpat_plan *plan, int32_t *steps);
 
 /* Launch shape of the plan's leapfrog stencil kernel (informational; the kernel

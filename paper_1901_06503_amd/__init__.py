@@ -73,17 +73,19 @@ class Plan:
     ds = 0: dx; ndim = 2: the z-invariant mode, every plane its own 2D problem).
     naive_stencil: the unblocked leapfrog kernel (for comparison).
     use_graphs: replay captured graphs in fb_enqueue / reconstruct.
-    two_step_stencil: None lets the plan choose one or two leapfrog steps per
-    stencil pass; True / False force two / one (FFPAT_PLAN_TWO_STEP / _SINGLE_STEP).
+    two_step_stencil: None lets the plan choose the leapfrog steps per stencil
+    pass; True / False force two / one (FFPAT_PLAN_TWO_STEP / _SINGLE_STEP).
+    stencil_steps: 1, 2 or 3 forces that many steps per pass where the grid allows
+    (FFPAT_PLAN_SINGLE_STEP / _TWO_STEP / _THREE_STEP); excludes two_step_stencil.
     stream: torch stream (or None: the current one) for the plan's set-up.
 
-    After creation: nt, dt, cmax (the time grid), steps_per_pass (1 or 2 leapfrog
+    After creation: nt, dt, cmax (the time grid), steps_per_pass (1, 2 or 3 leapfrog
     steps per stencil pass) and stencil_shape (tile width, tile height, z-planes per
     work-group of that stencil kernel on this device; zeros for the naive kernel).
     """
 
     def __init__(self, c, dx, T, angles, ns=0, ds=0.0, cfl=0.3, ndim=3, naive_stencil=False, use_graphs=True,
-                 two_step_stencil=None, stream=None):
+                 two_step_stencil=None, stream=None, stencil_steps=None):
         torch = _torch()
         if not (isinstance(c, torch.Tensor) and c.is_cuda):
             raise TypeError("c must be a device tensor")
@@ -96,8 +98,13 @@ class Plan:
         self.device = c.device
         nz, ny, nx = c.shape
         code = _lib.F64 if c.dtype == torch.float64 else _lib.F32
+        if stencil_steps is not None and two_step_stencil is not None:
+            raise ValueError("stencil_steps and two_step_stencil exclude each other")
+        steps_flag = ({None: 0, True: _lib.PLAN_TWO_STEP, False: _lib.PLAN_SINGLE_STEP}[two_step_stencil]
+                      if stencil_steps is None else
+                      {1: _lib.PLAN_SINGLE_STEP, 2: _lib.PLAN_TWO_STEP, 3: _lib.PLAN_THREE_STEP}[stencil_steps])
         flags = ((_lib.PLAN_NAIVE_STENCIL if naive_stencil else 0) | (0 if use_graphs else _lib.PLAN_NO_GRAPHS)
-                 | {None: 0, True: _lib.PLAN_TWO_STEP, False: _lib.PLAN_SINGLE_STEP}[two_step_stencil])
+                 | steps_flag)
         self._lib = _lib.load()
         g, self._angles = _make_geom(nx, ny, nz, dx, T, angles, ns, ds, cfl, ndim, code, flags)
         handle = ctypes.c_void_p()
@@ -116,7 +123,7 @@ class Plan:
         self.nt, self.dt, self.cmax = nt.value, dt.value, cm.value
         sp = ctypes.c_int32()
         _lib.check(self._lib.ffpat_plan_steps_per_pass(self._h, ctypes.byref(sp)))
-        self.steps_per_pass = sp.value          # 2: temporally blocked stencil kernel
+        self.steps_per_pass = sp.value          # 2 or 3: temporally blocked stencil kernel
         tx, ty, zc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _lib.check(self._lib.ffpat_plan_stencil_shape(self._h, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(zc)))
         self.stencil_shape = (tx.value, ty.value, zc.value)   # tile width, height, planes per work-group

@@ -23,6 +23,7 @@ PLAN_NAIVE_STENCIL = 1
 PLAN_NO_GRAPHS = 2
 PLAN_SINGLE_STEP = 4
 PLAN_TWO_STEP = 8
+PLAN_THREE_STEP = 32
 POSITIVITY = 1
 PRECOND = 2
 REG_GRAD = 4

@@ -67,11 +67,28 @@ hipError_t launch_wave_pair(const Dims &d, const T *pm1, const T *pk, T *q, T *o
 // current device for this grid.
 template <typename T>
 void wave_pair_shape(const Dims &d, int *tile_x, int *tile_y, int *zchunk);
+// Three leapfrog steps in one pass: r = p(k+2), o = p(k+3) from pm1 = p(k-1), pk =
+// p(k) (p(k+1) stays on chip).  All four buffers must be distinct.  *taken = false
+// (and nothing launched) where the grid, element size or buffer alignment has no
+// three-step kernel; the caller then takes smaller passes.
+template <typename T>
+hipError_t launch_wave_triple(const Dims &d, const T *pm1, const T *pk, T *r, T *o, const T *kap, hipStream_t s,
+                              bool *taken);
+// Tile and planes per work-group of launch_wave_triple for this grid (8-byte aligned
+// buffers); false where it takes no three-step pass.
+template <typename T>
+bool wave_triple_shape(const Dims &d, int *tile_x, int *tile_y, int *zchunk);
 // The same for the one-step blocked kernel (launch_wave_step with STENCIL_BLOCKED).
 void wave_step_shape(const Dims &d, size_t esz, int *tile_x, int *tile_y, int *zchunk);
 // Whether the two-step kernel is the faster choice for this grid and element size
 // (FFPAT_STENCIL_TB=0/1 in the environment overrides the rule).
 bool wave_pairs_preferred(const Dims &d, size_t esz);
+// Whether a three-step pass exists for this grid and element size (8-byte aligned
+// buffers), and whether it is the preferred choice (FFPAT_STENCIL3=0/1 in the
+// environment overrides the rule).
+template <typename T>
+bool wave_triples_available(const Dims &d);
+bool wave_triples_preferred(const Dims &d, size_t esz);
 // Whether the two-step kernel can address a plane of this grid (plane bytes < 2^31).
 bool wave_pairs_fit(const Dims &d, size_t esz);
 

@@ -137,6 +137,7 @@ struct ffpat_plan {
   int n_row_angles = 0;   // angles that march rows (listed first in aorder)
   bool use_graphs = true; // replay captured graphs for the power iteration and FB iterations
   bool use_pairs = true;  // two leapfrog steps per pass where possible
+  bool use_triples = false;  // three steps per pass where possible (implies use_pairs)
   hipStream_t cap_stream = nullptr;
   hipEvent_t done = nullptr;  // recorded after the work of every call (ffpat_plan_destroy waits for it)
   GraphCache g_iter, g_power;
@@ -208,10 +209,14 @@ int resolve(const ffpat_geom *g, Resolved *r)
   r->ds = ds;
   r->T = g->T;
   r->cfl = cfl;
-  const uint32_t known = FFPAT_PLAN_NAIVE_STENCIL | FFPAT_PLAN_NO_GRAPHS | FFPAT_PLAN_SINGLE_STEP | FFPAT_PLAN_TWO_STEP;
+  const uint32_t known = FFPAT_PLAN_NAIVE_STENCIL | FFPAT_PLAN_NO_GRAPHS | FFPAT_PLAN_SINGLE_STEP | FFPAT_PLAN_TWO_STEP |
+                         FFPAT_PLAN_THREE_STEP;
   if (g->flags & ~known) return fail(FFPAT_EINVAL, "unknown plan flags 0x%x", (unsigned)(g->flags & ~known));
-  if ((g->flags & FFPAT_PLAN_SINGLE_STEP) && (g->flags & FFPAT_PLAN_TWO_STEP))
-    return fail(FFPAT_EINVAL, "FFPAT_PLAN_SINGLE_STEP and FFPAT_PLAN_TWO_STEP exclude each other");
+  {
+    const uint32_t steps = g->flags & (FFPAT_PLAN_SINGLE_STEP | FFPAT_PLAN_TWO_STEP | FFPAT_PLAN_THREE_STEP);
+    if (steps & (steps - 1))
+      return fail(FFPAT_EINVAL, "FFPAT_PLAN_SINGLE_STEP, FFPAT_PLAN_TWO_STEP and FFPAT_PLAN_THREE_STEP exclude each other");
+  }
   r->flags = g->flags;
   return FFPAT_OK;
 }
@@ -320,7 +325,26 @@ int leapfrog_chain(ffpat_plan *P, const T *pm1, bool pm1_owned, T *pk, int steps
 {
   const T *kap = static_cast<const T *>(P->kap());
   while (steps > 0) {
-    const bool pair = P->use_pairs && steps >= 2 && !(div_last && steps == 2) && pool.n >= (steps == 2 ? 1 : 2);
+    // steps that may go into multi-step passes (a dividing last step runs alone)
+    const int multi = steps - (div_last ? 1 : 0);
+    if (P->use_triples && multi >= 3 && pool.n >= (steps == 3 ? 1 : 2)) {
+      T *a = pool.take();
+      T *b = (steps == 3) ? out : pool.take();
+      bool taken = false;
+      HIP_TRY(launch_wave_triple<T>(P->d, pm1, pk, a, b, kap, s, &taken));
+      if (taken) {
+        if (pm1_owned) pool.give(const_cast<T *>(pm1));
+        pool.give(pk);
+        pm1 = a;
+        pm1_owned = true;
+        pk = b;
+        steps -= 3;
+        continue;
+      }
+      if (b != out) pool.give(b);   // buffers the kernel cannot take (alignment): smaller passes
+      pool.give(a);
+    }
+    const bool pair = P->use_pairs && multi >= 2 && pool.n >= (steps == 2 ? 1 : 2);
     if (pair) {
       T *a = pool.take();
       T *b = (steps == 2) ? out : pool.take();
@@ -855,9 +879,15 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
   P->flags = r.flags;
   P->stencil = (r.flags & FFPAT_PLAN_NAIVE_STENCIL) ? STENCIL_NAIVE : STENCIL_BLOCKED;
   P->use_graphs = !(r.flags & FFPAT_PLAN_NO_GRAPHS);
-  P->use_pairs = P->stencil == STENCIL_BLOCKED && wave_pairs_fit(r.d, r.dtype == FFPAT_F64 ? 8 : 4) &&
-                 ((r.flags & FFPAT_PLAN_TWO_STEP) ||
-                  (!(r.flags & FFPAT_PLAN_SINGLE_STEP) && wave_pairs_preferred(r.d, r.dtype == FFPAT_F64 ? 8 : 4)));
+  {
+    const size_t esz = r.dtype == FFPAT_F64 ? 8 : 4;
+    const bool forced = r.flags & (FFPAT_PLAN_TWO_STEP | FFPAT_PLAN_THREE_STEP);
+    P->use_pairs = P->stencil == STENCIL_BLOCKED && wave_pairs_fit(r.d, esz) &&
+                   (forced || (!(r.flags & FFPAT_PLAN_SINGLE_STEP) && wave_pairs_preferred(r.d, esz)));
+    const bool triples = esz == 8 ? wave_triples_available<double>(r.d) : wave_triples_available<float>(r.d);
+    P->use_triples = P->use_pairs && triples &&
+                     ((r.flags & FFPAT_PLAN_THREE_STEP) || (!forced && wave_triples_preferred(r.d, esz)));
+  }
   P->nvox = r.d.nvox();
   P->ndat = (size_t)r.n_angles * r.d.nz * r.ns;
   P->rows = r.n_angles * r.d.nz;
@@ -959,7 +989,7 @@ int ffpat_plan_steps_per_pass(const ffpat_plan *plan, int32_t *steps)
 {
   CHECK_PLAN(plan);
   if (!steps) return fail(FFPAT_EINVAL, "steps is NULL");
-  *steps = plan->use_pairs ? 2 : 1;
+  *steps = plan->use_triples ? 3 : (plan->use_pairs ? 2 : 1);
   return FFPAT_OK;
 }
 
@@ -971,6 +1001,8 @@ int ffpat_plan_stencil_shape(const ffpat_plan *plan, int32_t *tile_x, int32_t *t
     DeviceGuard guard(plan->device);
     const size_t esz = plan->dtype == FFPAT_F64 ? 8 : 4;
     if (!plan->use_pairs) wave_step_shape(plan->d, esz, &tx, &ty, &zc);
+    else if (plan->use_triples && esz == 8) wave_triple_shape<double>(plan->d, &tx, &ty, &zc);
+    else if (plan->use_triples) wave_triple_shape<float>(plan->d, &tx, &ty, &zc);
     else if (esz == 8) wave_pair_shape<double>(plan->d, &tx, &ty, &zc);
     else wave_pair_shape<float>(plan->d, &tx, &ty, &zc);
   }

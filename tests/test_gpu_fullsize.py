@@ -99,10 +99,10 @@ def test_c256_forward_adjoint(c256, dtype):
     planes = gold["planes"]
     print(f"[fullsize] 256^3 forward/adjoint {dtype}", flush=True)
     with ff.Plan(to_dev(case.c, dtype), case.dx, case.T, case.angles) as P:
-        # the benchmark's kernels: two steps per pass; on 256 compute units the FP32
-        # plan takes 128 x 16 tiles (pairs of x-adjacent points per lane), FP64 64 x 16,
-        # one z-chunk round each: chunk boundaries at 32k (FP32) and 64k (FP64)
-        assert P.steps_per_pass == 2
+        # the benchmark's kernels: three steps per pass in FP32 (128 x 16 tiles, pairs of
+        # x-adjacent points per lane), two in FP64 (64 x 16); on 256 compute units one
+        # z-chunk round each: chunk boundaries at 32k (FP32) and 64k (FP64)
+        assert P.steps_per_pass == (3 if dtype == torch.float32 else 2)
         if torch.cuda.get_device_properties(0).multi_processor_count == 256:
             assert P.stencil_shape == ((128, 16, 32) if dtype == torch.float32 else (64, 16, 64))
         fwd = P.forward(to_dev(case.h_true, dtype))
@@ -164,7 +164,7 @@ def test_c384_full_size_adjoint_dot_test(dtype):
     print(f"[fullsize] 384^3 dot test {dtype}", flush=True)
     gen = torch.Generator(device="cuda").manual_seed(7)
     with ff.Plan(to_dev(case.c, dtype), case.dx, case.T, case.angles) as P:
-        assert P.steps_per_pass == 2
+        assert P.steps_per_pass == (3 if dtype == torch.float32 else 2)
         h = torch.randn(P.shape, dtype=dtype, device="cuda", generator=gen)
         g = torch.randn(P.data_shape, dtype=dtype, device="cuda", generator=gen)
         Ah = P.forward(h)
@@ -285,7 +285,7 @@ def test_c384_precision_fp32_vs_fp64_200_iterations():
     for name, dtype in (("f32", torch.float32), ("f64", torch.float64)):
         print(f"[fullsize] 384^3 precision workload, 200 iterations, {name}", flush=True)
         with ff.Plan(to_dev(case.c, dtype), case.dx, case.T, case.angles) as P:
-            assert P.nt == nt64 and P.steps_per_pass == 2
+            assert P.nt == nt64 and P.steps_per_pass == (3 if dtype == torch.float32 else 2)
             res = P.reconstruct(G64.to(dtype), case.lam, case.n_iter, step=0.0, n_power=case.n_power)
             recon[name] = res.h.double()
             steps[name] = res.step

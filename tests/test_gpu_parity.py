@@ -132,7 +132,7 @@ def test_wave_pairs_mid_size_chunking(oracle, shape, dtype, launch):
     g = oracle_geom(oracle, k)
     c, h = rounded(k["c"], dtype), rounded(k["h"], dtype)
     import paper_1901_06503_amd as ff
-    with ff.Plan(to_dev(c, dtype), k["dx"], k["T"], k["angles"], cfl=k["cfl"]) as P:
+    with ff.Plan(to_dev(c, dtype), k["dx"], k["T"], k["angles"], cfl=k["cfl"], stencil_steps=2) as P:
         assert P.steps_per_pass == 2 and P.nt >= 5
         if _compute_units() == 256:
             assert P.stencil_shape == launch
@@ -157,7 +157,7 @@ def test_pairs_of_points_every_step_count(oracle, shape, nt):
     g = oracle_geom(oracle, k)
     c, h = rounded(k["c"], F32), rounded(k["h"], F32)
     import paper_1901_06503_amd as ff
-    with ff.Plan(to_dev(c, F32), k["dx"], k["T"], k["angles"], cfl=k["cfl"]) as P:
+    with ff.Plan(to_dev(c, F32), k["dx"], k["T"], k["angles"], cfl=k["cfl"], stencil_steps=2) as P:
         assert P.nt == nt and P.steps_per_pass == 2
         if _compute_units() == 256:
             assert P.stencil_shape == (128, 16, 8)
@@ -180,7 +180,7 @@ def test_pairs_of_points_with_buffers_at_odd_float_offsets(oracle):
     c, h = rounded(k["c"], F32), rounded(k["h"], F32)
     n = h.size
     import paper_1901_06503_amd as ff
-    with ff.Plan(to_dev(c, F32), k["dx"], k["T"], k["angles"], cfl=k["cfl"]) as P:
+    with ff.Plan(to_dev(c, F32), k["dx"], k["T"], k["angles"], cfl=k["cfl"], stencil_steps=2) as P:
         assert P.nt == 5 and P.steps_per_pass == 2
         hin = torch.zeros(n + 1, dtype=F32, device="cuda")[1:].view(shape)
         hin.copy_(to_dev(h, F32))
@@ -450,7 +450,7 @@ def test_pairs_of_points_reconstruction_in_graphs(oracle):
     h_ref, obj_ref, s_ref = oracle.fb(g, c, G, lam, step=0.0, n_iter=K, n_power=6,
                                       flags=oracle.POSITIVITY | oracle.PRECOND)
     import paper_1901_06503_amd as ff
-    with ff.Plan(to_dev(c, F32), k["dx"], k["T"], k["angles"], cfl=k["cfl"]) as P:
+    with ff.Plan(to_dev(c, F32), k["dx"], k["T"], k["angles"], cfl=k["cfl"], stencil_steps=2) as P:
         assert P.nt == 7 and P.steps_per_pass == 2
         if _compute_units() == 256:
             assert P.stencil_shape == (128, 16, 8)
