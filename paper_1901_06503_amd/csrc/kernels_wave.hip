@@ -771,8 +771,11 @@ wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
   fetch(std::integral_constant<int, 0>{}, zstart);
   fetch(std::integral_constant<int, 1>{}, zstart + 1);
 
-  auto step = [&](auto phase, int zs) {
+  // STAGE2: whether the plane's stage 2 is needed (not on the group's first four
+  // planes, whose o, two planes behind, lies before the chunk)
+  auto step = [&](auto phase, auto stage2, int zs) {
     constexpr int Q = decltype(phase)::value;
+    constexpr bool STAGE2 = decltype(stage2)::value;
     constexpr int P = Q % 5, B = Q % 2;
     constexpr int Sm2 = (P + 3) % 5, Sm1 = (P + 4) % 5, S0 = P, Sp1 = (P + 1) % 5, Sp2 = (P + 2) % 5;
     constexpr int Sm3 = (P + 2) % 5, Sm4 = (P + 1) % 5;
@@ -831,8 +834,8 @@ wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
 #pragma unroll
       for (int m = 0; m < NIN; ++m) st_ranged(q_pl, own ? plane_bytes : 0u, soff[m], qv[m]);
     }
-    // stage 2: o(z) on the interior slots, z = zs - 2 (computed on every plane, stored
-    // from z = zbeg on; before that the q planes it reads are not yet written)
+    if constexpr (!STAGE2) return;
+    // stage 2: o(z) on the interior slots, z = zs - 2 >= zbeg
     {
       T nq[NIN][NB];
 #pragma unroll
@@ -844,7 +847,7 @@ wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
         nq[m][NB - 2] = c[-2 * KX];
         nq[m][NB - 1] = c[2 * KX];
       }
-      T *o_pl = o_out + (size_t)max(z, 0) * plane;
+      T *o_pl = o_out + (size_t)z * plane;
       T ov[NIN];
 #pragma unroll
       for (int m = 0; m < NIN; ++m) {
@@ -860,31 +863,37 @@ wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
         asm volatile("" : : "v"(ov[m]));
       }
 #pragma unroll
-      for (int m = 0; m < NIN; ++m) st_ranged(o_pl, z >= zbeg ? plane_bytes : 0u, soff[m], ov[m]);
+      for (int m = 0; m < NIN; ++m) st_ranged(o_pl, plane_bytes, soff[m], ov[m]);
     }
   };
 
   const int zlast = zend + 1;                // last stage-1 plane
-  for (int zb = zstart; zb <= zlast; zb += 10) {
-    step(std::integral_constant<int, 0>{}, zb);
+  using No2 = std::false_type;
+  using With2 = std::true_type;
+  step(std::integral_constant<int, 0>{}, No2{}, zstart);       // o planes zbeg-4 .. zbeg-1
+  step(std::integral_constant<int, 1>{}, No2{}, zstart + 1);
+  step(std::integral_constant<int, 2>{}, No2{}, zstart + 2);
+  step(std::integral_constant<int, 3>{}, No2{}, zstart + 3);
+  for (int zb = zbeg + 2; zb <= zlast; zb += 10) {             // o planes zbeg .. zend-1
+    step(std::integral_constant<int, 4>{}, With2{}, zb);
     if (zb + 1 > zlast) break;
-    step(std::integral_constant<int, 1>{}, zb + 1);
+    step(std::integral_constant<int, 5>{}, With2{}, zb + 1);
     if (zb + 2 > zlast) break;
-    step(std::integral_constant<int, 2>{}, zb + 2);
+    step(std::integral_constant<int, 6>{}, With2{}, zb + 2);
     if (zb + 3 > zlast) break;
-    step(std::integral_constant<int, 3>{}, zb + 3);
+    step(std::integral_constant<int, 7>{}, With2{}, zb + 3);
     if (zb + 4 > zlast) break;
-    step(std::integral_constant<int, 4>{}, zb + 4);
+    step(std::integral_constant<int, 8>{}, With2{}, zb + 4);
     if (zb + 5 > zlast) break;
-    step(std::integral_constant<int, 5>{}, zb + 5);
+    step(std::integral_constant<int, 9>{}, With2{}, zb + 5);
     if (zb + 6 > zlast) break;
-    step(std::integral_constant<int, 6>{}, zb + 6);
+    step(std::integral_constant<int, 10>{}, With2{}, zb + 6);
     if (zb + 7 > zlast) break;
-    step(std::integral_constant<int, 7>{}, zb + 7);
+    step(std::integral_constant<int, 11>{}, With2{}, zb + 7);
     if (zb + 8 > zlast) break;
-    step(std::integral_constant<int, 8>{}, zb + 8);
+    step(std::integral_constant<int, 12>{}, With2{}, zb + 8);
     if (zb + 9 > zlast) break;
-    step(std::integral_constant<int, 9>{}, zb + 9);
+    step(std::integral_constant<int, 13>{}, With2{}, zb + 9);
   }
 }
 
@@ -1130,8 +1139,10 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
   };
   fetch(zstart);
 
-  auto step = [&](auto phase, int zs) {
-    constexpr int Q = decltype(phase)::value;
+  // NS: the stages a plane needs (the first four planes of a group only feed stage 1's
+  // q to later planes, the next four have no o of the chunk yet)
+  auto step = [&](auto phase, auto nstages, int zs) {
+    constexpr int Q = decltype(phase)::value, NS = decltype(nstages)::value;
     constexpr int P = Q % 5, B = Q % 2;
     // ring and window slot of plane zs + d
     constexpr int Sm6 = (P + 4) % 5, Sm5 = P, Sm4 = (P + 1) % 5, Sm3 = (P + 2) % 5, Sm2 = (P + 3) % 5;
@@ -1182,8 +1193,9 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
       for (int m = 0; m < PPT; ++m) qb[m][S0 * QP + (m < PPT - 1 ? 2 * AX : 0)] = qv[m];
     }
 
-    // stage 2: r(z1) on slots 0..2 (computed on every plane; the planes before the
-    // chunk's first stage-2 plane read q planes not yet written and are discarded)
+    if constexpr (NS == 1) return;
+
+    // stage 2: r(z1) on slots 0..2, from z1 = zbeg - 2 on
     T rv[PPT - 1];
     {
       T nq[PPT - 1][NB2];
@@ -1228,7 +1240,9 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
       for (int m = 0; m < NIN; ++m) st_ranged(r_pl, own ? plane_bytes : 0u, boff[m], rv[m]);
     }
 
-    // stage 3: o(z2) on the interior slots (stored from z2 = zbeg on)
+    if constexpr (NS == 2) return;
+
+    // stage 3: o(z2) on the interior slots, from z2 = zbeg on
     {
       T nr[NIN][NB + 1];
 #pragma unroll
@@ -1258,33 +1272,44 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
         ov[m] = T(2) * c0 - v[NB] + kw[m][Sm4] * S;
         asm volatile("" : : "v"(ov[m]));
       }
-      T *o_pl = o_out + (size_t)max(z2, 0) * plane;
+      T *o_pl = o_out + (size_t)z2 * plane;
 #pragma unroll
-      for (int m = 0; m < NIN; ++m) st_ranged(o_pl, z2 >= zbeg ? plane_bytes : 0u, boff[m], ov[m]);
+      for (int m = 0; m < NIN; ++m) st_ranged(o_pl, plane_bytes, boff[m], ov[m]);
     }
   };
 
   const int zlast = zend + 3;                 // last stage-1 plane
-  for (int zb = zstart; zb <= zlast; zb += 10) {
-    step(std::integral_constant<int, 0>{}, zb);
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  using S3 = std::integral_constant<int, 3>;
+  step(std::integral_constant<int, 0>{}, S1{}, zstart);       // r planes zbeg-6 .. zbeg-3, o zbeg-8 ..
+  step(std::integral_constant<int, 1>{}, S1{}, zstart + 1);
+  step(std::integral_constant<int, 2>{}, S1{}, zstart + 2);
+  step(std::integral_constant<int, 3>{}, S1{}, zstart + 3);
+  step(std::integral_constant<int, 4>{}, S2{}, zbeg);         // r planes zbeg-2 .. zbeg+1, o zbeg-4 ..
+  step(std::integral_constant<int, 5>{}, S2{}, zbeg + 1);
+  step(std::integral_constant<int, 6>{}, S2{}, zbeg + 2);
+  step(std::integral_constant<int, 7>{}, S2{}, zbeg + 3);
+  for (int zb = zbeg + 4; zb <= zlast; zb += 10) {            // o planes zbeg .. zend-1
+    step(std::integral_constant<int, 8>{}, S3{}, zb);
     if (zb + 1 > zlast) break;
-    step(std::integral_constant<int, 1>{}, zb + 1);
+    step(std::integral_constant<int, 9>{}, S3{}, zb + 1);
     if (zb + 2 > zlast) break;
-    step(std::integral_constant<int, 2>{}, zb + 2);
+    step(std::integral_constant<int, 10>{}, S3{}, zb + 2);
     if (zb + 3 > zlast) break;
-    step(std::integral_constant<int, 3>{}, zb + 3);
+    step(std::integral_constant<int, 11>{}, S3{}, zb + 3);
     if (zb + 4 > zlast) break;
-    step(std::integral_constant<int, 4>{}, zb + 4);
+    step(std::integral_constant<int, 12>{}, S3{}, zb + 4);
     if (zb + 5 > zlast) break;
-    step(std::integral_constant<int, 5>{}, zb + 5);
+    step(std::integral_constant<int, 13>{}, S3{}, zb + 5);
     if (zb + 6 > zlast) break;
-    step(std::integral_constant<int, 6>{}, zb + 6);
+    step(std::integral_constant<int, 14>{}, S3{}, zb + 6);
     if (zb + 7 > zlast) break;
-    step(std::integral_constant<int, 7>{}, zb + 7);
+    step(std::integral_constant<int, 15>{}, S3{}, zb + 7);
     if (zb + 8 > zlast) break;
-    step(std::integral_constant<int, 8>{}, zb + 8);
+    step(std::integral_constant<int, 16>{}, S3{}, zb + 8);
     if (zb + 9 > zlast) break;
-    step(std::integral_constant<int, 9>{}, zb + 9);
+    step(std::integral_constant<int, 17>{}, S3{}, zb + 9);
   }
 }
 
