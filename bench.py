@@ -427,12 +427,14 @@ def time_wave(torch, plan, reps=3):
 def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
     """The dominant kernel of the path (the leapfrog stencil) and its average launch
     duration, measured live.  A forward W_T solve is n_t leapfrog steps: with one step
-    per pass, n_t launches of wave_step_blocked; with k = 2 or 3 steps per pass, one
-    first-step launch, M = (n_t - 1) // k launches of the k-step kernel and a shorter
-    pass for the remaining (n_t - 1) % k steps (a single step, or a pair of steps in a
-    two-step launch).  The k-step kernel's duration is (t(W_T) - t_first - t_rest) / M,
-    with the single-step duration measured on a plan that runs one step per pass and
-    the pair duration, where needed, derived the same way on a two-step plan.
+    per pass, n_t launches of wave_step_blocked; with two steps per pass, one
+    first-step launch, M = (n_t - 1) // 2 launches of the two-step kernel and a single
+    step for an odd remainder; with three, M = 1 + (n_t - 3) // 3 three-step launches
+    (the first starts the solve from p(0)) and a single step or a pair for the
+    remaining (n_t - 3) % 3 steps.  The k-step kernel's duration is
+    (t(W_T) - t_first - t_rest) / M, with the single-step duration measured on a plan
+    that runs one step per pass and the pair duration, where needed, derived the same
+    way on a two-step plan.
     Bytes per launch, two ways: algorithmic = 4 words per point update (read p(k),
     p(k-1), k'; write p(k+1): 16 B FP32, 32 B FP64) x the updates a launch makes per
     voxel (1, 2 or 3); compulsory = the words per voxel a launch must move at least
@@ -455,9 +457,14 @@ def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
             t_w2 = time_wave(torch, p2)
             pairs2, singles2 = divmod(p2.nt - 1, 2)
             t_pair = (t_w2 - (1 + singles2) * t_single) / pairs2
-    full, rest = divmod(plan.nt - 1, k)
+    if k == 3 and plan.nt >= 3:
+        # the solve's first pass is a three-step launch too (it starts from p(0))
+        full, rest = divmod(plan.nt - 3, 3)
+        full, t_first = full + 1, 0.0
+    else:
+        (full, rest), t_first = divmod(plan.nt - 1, k), t_single
     t_rest = 0.0 if rest == 0 else (t_single if rest == 1 else t_pair)
-    out.update(kernel=multi_kernel_name(plan, dtype == torch.float64), t_launch=(t_w - t_single - t_rest) / full,
+    out.update(kernel=multi_kernel_name(plan, dtype == torch.float64), t_launch=(t_w - t_first - t_rest) / full,
                alg_bytes=k * 4 * esz * nvox, compulsory_bytes=5 * esz * nvox, updates_per_launch=k,
                t_single_launch=t_single)
     if t_pair is not None:

@@ -68,12 +68,20 @@ hipError_t launch_wave_pair(const Dims &d, const T *pm1, const T *pk, T *q, T *o
 template <typename T>
 void wave_pair_shape(const Dims &d, int *tile_x, int *tile_y, int *zchunk);
 // Three leapfrog steps in one pass: r = p(k+2), o = p(k+3) from pm1 = p(k-1), pk =
-// p(k) (p(k+1) stays on chip).  All four buffers must be distinct.  *taken = false
-// (and nothing launched) where the grid, element size or buffer alignment has no
-// three-step kernel; the caller then takes smaller passes.
+// p(k) (p(k+1) stays on chip).  first: the pass starts the solve from pk = p(0) with
+// zero initial velocity (its first step is STEP_FIRST; pm1 is not read) and yields
+// p(2), p(3).  The buffers must be distinct.  *taken = false (and nothing launched)
+// where the grid, element size or buffer alignment has no three-step kernel; the
+// caller then takes smaller passes.
 template <typename T>
 hipError_t launch_wave_triple(const Dims &d, const T *pm1, const T *pk, T *r, T *o, const T *kap, hipStream_t s,
-                              bool *taken);
+                              bool first, bool *taken);
+// Two leapfrog steps in one pass whose second is divided by k' (the adjoint solve's
+// last two steps, STEP_LEAP then STEP_LEAP_DIV): q = p(k+1), o = p(k+2) / k'.  Only
+// where the two-step pass runs in wave_step2_split; *taken = false otherwise.
+template <typename T>
+hipError_t launch_wave_pair_div(const Dims &d, const T *pm1, const T *pk, T *q, T *o, const T *kap, hipStream_t s,
+                                bool *taken);
 // Tile and planes per work-group of launch_wave_triple for this grid (8-byte aligned
 // buffers); false where it takes no three-step pass.
 template <typename T>

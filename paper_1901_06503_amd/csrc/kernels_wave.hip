@@ -636,7 +636,9 @@ __device__ __forceinline__ T ld_ranged(const T *base, unsigned bytes, unsigned b
 // stores, i.e. where they are written; with it, it sinks them past the z loop's
 // exit tests to the next plane, which halves the prefetch distance: the FP32 pairs
 // kernel is 1% faster without, the FP64 kernel 7% faster with (without, it spills).
-template <typename T, bool RESTRICT>
+// DIV: the second step is the adjoint solve's last one, divided by k' (the
+// single-step kernel's STEP_LEAP_DIV, the same expression).
+template <typename T, bool RESTRICT, bool DIV = false>
 __global__ void __launch_bounds__(512, 1)
 wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> pm1,
                  std::conditional_t<RESTRICT, const T *__restrict__, const T *> pk,
@@ -859,7 +861,9 @@ wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
         s1 += r1[m][Sm3] + r1[m][Sm1];
         s2 += r1[m][Sm4] + r1[m][S0];
         const T S = T(16) * s1 - s2 - T(90) * c0;
-        ov[m] = T(2) * c0 - w[m][Sm2] + kr[m][Sm2] * S;
+        T v = T(2) * c0 - w[m][Sm2] + kr[m][Sm2] * S;
+        if constexpr (DIV) v = v / kr[m][Sm2];
+        ov[m] = v;
         asm volatile("" : : "v"(ov[m]));
       }
 #pragma unroll
@@ -973,7 +977,10 @@ struct LdsFence<T, 36> {
 // plans keep two steps per pass unless FFPAT_PLAN_THREE_STEP asks otherwise).
 // Tried: q's z-column in registers too (spills: 51.3 us at 256^3), k' of stages 2
 // and 3 loaded again instead of kept (43.2), loads two planes ahead (42.5).
-template <typename T, bool RESTRICT>
+// FIRSTSTEP: the pass starts the solve: stage 1 is the first step from p(0) with zero
+// initial velocity (the single-step kernel's STEP_FIRST, the same expression; pm1 is
+// not read), so the pass yields p(2) and p(3).
+template <typename T, bool RESTRICT, bool FIRSTSTEP = false>
 __global__ void __launch_bounds__(512, 1)
 wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> pm1,
                  std::conditional_t<RESTRICT, const T *__restrict__, const T *> pk,
@@ -1128,11 +1135,12 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
   T nw[PPT], npv[PPT], nkv[PPT], nring;
   auto fetch = [&](int zf) {
     const unsigned bw = plane_range(zf + 2), bc = plane_range(zf);
-    const T *pw = plane_at(pk, zf + 2), *pp = plane_at(pm1, zf), *pkap = plane_at(kap, zf), *pr = plane_at(pk, zf);
+    const T *pw = plane_at(pk, zf + 2), *pp = FIRSTSTEP ? pk : plane_at(pm1, zf);
+    const T *pkap = plane_at(kap, zf), *pr = plane_at(pk, zf);
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
       nw[m] = ld_ranged(pw, bw, boff[m]);
-      npv[m] = ld_ranged(pp, bc, boff[m]);
+      if constexpr (!FIRSTSTEP) npv[m] = ld_ranged(pp, bc, boff[m]);
       nkv[m] = ld_ranged(pkap, bc, boff[m]);
     }
     nring = ld_ranged(pr, bc, roff);
@@ -1152,7 +1160,8 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
       w[m][Sp2] = nw[m];
-      pv[m] = npv[m];
+      if constexpr (FIRSTSTEP) pv[m] = T(0);
+      else pv[m] = npv[m];
       kv[m] = nkv[m];
     }
 #pragma unroll
@@ -1187,7 +1196,8 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
         s1 += w[m][Sm1] + w[m][Sp1];
         s2 += w[m][Sm2] + w[m][Sp2];
         const T S = T(16) * s1 - s2 - T(90) * c0;
-        qv[m] = T(2) * c0 - pv[m] + kv[m] * S;
+        if constexpr (FIRSTSTEP) qv[m] = c0 + T(0.5) * kv[m] * S;
+        else qv[m] = T(2) * c0 - pv[m] + kv[m] * S;
       }
 #pragma unroll
       for (int m = 0; m < PPT; ++m) qb[m][S0 * QP + (m < PPT - 1 ? 2 * AX : 0)] = qv[m];
@@ -1626,10 +1636,10 @@ static bool triple_applies(const Dims &d, const BlockedConfig &cfg, bool aligned
 
 template <typename T>
 hipError_t launch_wave_triple(const Dims &d, const T *pm1, const T *pk, T *r_out, T *o_out, const T *kap,
-                              hipStream_t s, bool *taken)
+                              hipStream_t s, bool first, bool *taken)
 {
   const BlockedConfig cfg = blocked_config(d, sizeof(T));
-  const bool aligned = ((reinterpret_cast<uintptr_t>(pm1) | reinterpret_cast<uintptr_t>(pk) |
+  const bool aligned = (((first ? 0 : reinterpret_cast<uintptr_t>(pm1)) | reinterpret_cast<uintptr_t>(pk) |
                          reinterpret_cast<uintptr_t>(r_out) | reinterpret_cast<uintptr_t>(o_out) |
                          reinterpret_cast<uintptr_t>(kap)) & 7) == 0;
   *taken = triple_applies<T>(d, cfg, aligned);
@@ -1638,16 +1648,55 @@ hipError_t launch_wave_triple(const Dims &d, const T *pm1, const T *pk, T *r_out
     const Dims e = x2_dims(d);
     const PairShape p = triple_shape<f32x2>(e, cfg);
     const int grid = ((p.n_tiles + 7) / 8) * 8;
-    wave_step3_split<f32x2, false><<<grid, 512, 0, s>>>(
-        reinterpret_cast<const f32x2 *>(pm1), reinterpret_cast<const f32x2 *>(pk), reinterpret_cast<f32x2 *>(r_out),
-        reinterpret_cast<f32x2 *>(o_out), reinterpret_cast<const f32x2 *>(kap), e.nx, e.ny, e.nz, p.zchunk, p.tiles_x,
-        p.tiles_y, p.n_tiles, cfg.order);
+    const f32x2 *a = reinterpret_cast<const f32x2 *>(first ? pk : pm1), *b = reinterpret_cast<const f32x2 *>(pk);
+    f32x2 *r2 = reinterpret_cast<f32x2 *>(r_out), *o2 = reinterpret_cast<f32x2 *>(o_out);
+    const f32x2 *k2 = reinterpret_cast<const f32x2 *>(kap);
+    if (first)
+      wave_step3_split<f32x2, false, true><<<grid, 512, 0, s>>>(a, b, r2, o2, k2, e.nx, e.ny, e.nz, p.zchunk, p.tiles_x,
+                                                                p.tiles_y, p.n_tiles, cfg.order);
+    else
+      wave_step3_split<f32x2, false, false><<<grid, 512, 0, s>>>(a, b, r2, o2, k2, e.nx, e.ny, e.nz, p.zchunk,
+                                                                 p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
   } else {
     const PairShape p = triple_shape<T>(d, cfg);
     const int grid = ((p.n_tiles + 7) / 8) * 8;
-    wave_step3_split<T, true><<<grid, 512, 0, s>>>(pm1, pk, r_out, o_out, kap, d.nx, d.ny, d.nz, p.zchunk, p.tiles_x,
-                                                   p.tiles_y, p.n_tiles, cfg.order);
+    if (first)
+      wave_step3_split<T, true, true><<<grid, 512, 0, s>>>(pk, pk, r_out, o_out, kap, d.nx, d.ny, d.nz, p.zchunk,
+                                                           p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
+    else
+      wave_step3_split<T, true, false><<<grid, 512, 0, s>>>(pm1, pk, r_out, o_out, kap, d.nx, d.ny, d.nz, p.zchunk,
+                                                            p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
   }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_wave_pair_div(const Dims &d, const T *pm1, const T *pk, T *q_out, T *o_out, const T *kap,
+                                hipStream_t s, bool *taken)
+{
+  const BlockedConfig cfg = blocked_config(d, sizeof(T));
+  *taken = false;
+  if (!cfg.split || d.ndim != 3) return hipSuccess;
+  if constexpr (sizeof(T) == 4) {
+    const bool aligned = ((reinterpret_cast<uintptr_t>(pm1) | reinterpret_cast<uintptr_t>(pk) |
+                           reinterpret_cast<uintptr_t>(q_out) | reinterpret_cast<uintptr_t>(o_out) |
+                           reinterpret_cast<uintptr_t>(kap)) & 7) == 0;
+    if (!aligned || !pair_x2<T>(d, cfg)) return hipSuccess;
+    const Dims e = x2_dims(d);
+    const PairShape p = pair_shape_split<f32x2>(e, cfg);
+    const int grid = ((p.n_tiles + 7) / 8) * 8;
+    wave_step2_split<f32x2, false, true><<<grid, 512, 0, s>>>(
+        reinterpret_cast<const f32x2 *>(pm1), reinterpret_cast<const f32x2 *>(pk), reinterpret_cast<f32x2 *>(q_out),
+        reinterpret_cast<f32x2 *>(o_out), reinterpret_cast<const f32x2 *>(kap), e.nx, e.ny, e.nz, p.zchunk, p.tiles_x,
+        p.tiles_y, p.n_tiles, cfg.order);
+  } else {
+    if (pair_variant<T>(d, cfg) != PAIR_RY4_T512) return hipSuccess;
+    const PairShape p = pair_shape_split<T>(d, cfg);
+    const int grid = ((p.n_tiles + 7) / 8) * 8;
+    wave_step2_split<T, true, true><<<grid, 512, 0, s>>>(pm1, pk, q_out, o_out, kap, d.nx, d.ny, d.nz, p.zchunk,
+                                                         p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
+  }
+  *taken = true;
   return hipGetLastError();
 }
 
@@ -1839,7 +1888,9 @@ hipError_t launch_c_stats(const Dims &d, const T *c, double *partials, int nbloc
   template hipError_t launch_wave_pair<T>(const Dims &, const T *, const T *, T *, T *, const T *, hipStream_t); \
   template void wave_pair_shape<T>(const Dims &, int *, int *, int *);                                     \
   template hipError_t launch_wave_triple<T>(const Dims &, const T *, const T *, T *, T *, const T *, hipStream_t, \
-                                            bool *);                                                        \
+                                            bool, bool *);                                                  \
+  template hipError_t launch_wave_pair_div<T>(const Dims &, const T *, const T *, T *, T *, const T *,        \
+                                              hipStream_t, bool *);                                         \
   template bool wave_triple_shape<T>(const Dims &, int *, int *, int *);                                    \
   template bool wave_triples_available<T>(const Dims &);                                                   \
   template hipError_t launch_wave_step<T>(StencilKind, StepMode, const Dims &, const T *, const T *, T *,  \

@@ -331,7 +331,7 @@ int leapfrog_chain(ffpat_plan *P, const T *pm1, bool pm1_owned, T *pk, int steps
       T *a = pool.take();
       T *b = (steps == 3) ? out : pool.take();
       bool taken = false;
-      HIP_TRY(launch_wave_triple<T>(P->d, pm1, pk, a, b, kap, s, &taken));
+      HIP_TRY(launch_wave_triple<T>(P->d, pm1, pk, a, b, kap, s, false, &taken));
       if (taken) {
         if (pm1_owned) pool.give(const_cast<T *>(pm1));
         pool.give(pk);
@@ -343,6 +343,14 @@ int leapfrog_chain(ffpat_plan *P, const T *pm1, bool pm1_owned, T *pk, int steps
       }
       if (b != out) pool.give(b);   // buffers the kernel cannot take (alignment): smaller passes
       pool.give(a);
+    }
+    if (P->use_pairs && div_last && steps == 2 && pool.n >= 1) {
+      // the adjoint's last two steps in one pass, the second divided by k'
+      T *a = pool.take();
+      bool taken = false;
+      HIP_TRY(launch_wave_pair_div<T>(P->d, pm1, pk, a, out, kap, s, &taken));
+      pool.give(a);
+      if (taken) return FFPAT_OK;
     }
     const bool pair = P->use_pairs && multi >= 2 && pool.n >= (steps == 2 ? 1 : 2);
     if (pair) {
@@ -370,6 +378,28 @@ int leapfrog_chain(ffpat_plan *P, const T *pm1, bool pm1_owned, T *pk, int steps
   return FFPAT_OK;
 }
 
+// The first three steps of a solve from p(0) = in in one three-step pass, when the
+// plan runs them and at least `after` steps follow: p(2), p(3) into two volumes of
+// the pool (p(3) into `out` when nothing follows).  *done = false: not taken.
+template <typename T>
+int first_triple(ffpat_plan *P, const T *in, T *out, int after, Pool<T> &pool, T **p2, T **p3, bool *done,
+                 hipStream_t s)
+{
+  *done = false;
+  if (!P->use_triples || P->nt - 3 < after || pool.n < (P->nt == 3 ? 1 : 2)) return FFPAT_OK;
+  T *a = pool.take();
+  T *b = (P->nt == 3) ? out : pool.take();
+  HIP_TRY(launch_wave_triple<T>(P->d, nullptr, in, a, b, static_cast<const T *>(P->kap()), s, true, done));
+  if (!*done) {
+    if (b != out) pool.give(b);
+    pool.give(a);
+    return FFPAT_OK;
+  }
+  *p2 = a;
+  *p3 = b;
+  return FFPAT_OK;
+}
+
 // out = W_T in (in read-only; pool: scratch volumes distinct from in and out)
 template <typename T>
 int wave_forward(ffpat_plan *P, const T *in, T *out, Pool<T> pool, hipStream_t s)
@@ -379,6 +409,10 @@ int wave_forward(ffpat_plan *P, const T *in, T *out, Pool<T> pool, hipStream_t s
     HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, in, nullptr, out, kap, s));
     return FFPAT_OK;
   }
+  T *p2 = nullptr, *p3 = nullptr;
+  bool done = false;
+  if (int rc = first_triple<T>(P, in, out, 0, pool, &p2, &p3, &done, s)) return rc;
+  if (done) return P->nt == 3 ? FFPAT_OK : leapfrog_chain<T>(P, p2, true, p3, P->nt - 3, out, false, pool, s);
   T *p1 = pool.take();
   HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, in, nullptr, p1, kap, s));
   return leapfrog_chain<T>(P, in, false, p1, P->nt - 1, out, false, pool, s);
@@ -392,6 +426,14 @@ int wave_adjoint_from_scaled(ffpat_plan *P, T *b, T *out, Pool<T> pool, hipStrea
   if (P->nt == 1) {
     HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST_DIV, P->d, b, nullptr, out, kap, s));
     return FFPAT_OK;
+  }
+  // the last step divides by k', so a first three-step pass needs a step after it
+  T *p2 = nullptr, *p3 = nullptr;
+  bool done = false;
+  if (int rc = first_triple<T>(P, b, out, 1, pool, &p2, &p3, &done, s)) return rc;
+  if (done) {
+    pool.give(b);
+    return leapfrog_chain<T>(P, p2, true, p3, P->nt - 3, out, true, pool, s);
   }
   T *p1 = pool.take();
   HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, b, nullptr, p1, kap, s));
