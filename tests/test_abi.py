@@ -80,7 +80,8 @@ def test_workspace_bytes_accounts_for_all_buffers(lib):
     (dict(nx=0), -1), (dict(dx=0.0), -1), (dict(dx=float("nan")), -1), (dict(T=-1.0), -1),
     (dict(n_angles=0), -1), (dict(ns=-3), -1), (dict(ds=-1.0), -1), (dict(dtype=7), -6), (dict(ndim=4), -1),
     (dict(angles=[0.0, float("inf")], n_angles=2), -1),
-    (dict(flags=4), 0), (dict(flags=8), 0), (dict(flags=4 | 8), -1), (dict(flags=16), -1), (dict(flags=1 << 31), -1),
+    (dict(flags=4), 0), (dict(flags=8), 0), (dict(flags=32), 0), (dict(flags=4 | 8), -1), (dict(flags=4 | 32), -1),
+    (dict(flags=8 | 32), -1), (dict(flags=16), -1), (dict(flags=1 << 31), -1),
 ])
 def test_geometry_validation(lib, kw, status):
     g, _a = _geom(**kw)
