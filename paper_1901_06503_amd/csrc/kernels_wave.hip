@@ -910,6 +910,16 @@ struct LdsFence<T, 14> {
   }
 };
 template <typename T>
+struct LdsFence<T, 26> {
+  static __device__ __forceinline__ void all(T *v)
+  {
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),
+                 "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]),
+                 "+v"(v[14]), "+v"(v[15]), "+v"(v[16]), "+v"(v[17]), "+v"(v[18]), "+v"(v[19]), "+v"(v[20]),
+                 "+v"(v[21]), "+v"(v[22]), "+v"(v[23]), "+v"(v[24]), "+v"(v[25]));
+  }
+};
+template <typename T>
 struct LdsFence<T, 30> {
   static __device__ __forceinline__ void all(T *v)
   {
@@ -971,12 +981,13 @@ struct LdsFence<T, 36> {
 // same for q did not fit in 256 VGPRs).  The value a thread has just computed for
 // its own column is taken from its register.  A ring slot is rewritten five
 // planes after it was written, after the barrier that follows its last read.
-// Loads run one plane ahead (two would spill).  Measured on MI355X, us per
-// leapfrog step (two-step kernel / this one): FP32 256^3 40.3 / 37.4, 384^3 129.3
-// / 124.9; FP64 256^3 70.2 / 81.6 (the FP64 form spills 36 bytes per lane, so its
+// Loads run one plane ahead (two would spill).  In FP64 (four x-neighbour reads per
+// point) r's z-column is read from the ring as well, which keeps it within 256 VGPRs.
+// Measured on MI355X, us per leapfrog step (two-step kernel / this one): FP32 256^3
+// 39.9 / 36.3, 384^3 129.3 / 123.5; FP64 256^3 70.0 / 69.2, 384^3 254.6 / 250.0 (FP64
 // plans keep two steps per pass unless FFPAT_PLAN_THREE_STEP asks otherwise).
-// Tried: q's z-column in registers too (spills: 51.3 us at 256^3), k' of stages 2
-// and 3 loaded again instead of kept (43.2), loads two planes ahead (42.5).
+// Tried: q's z-column in registers too (spills: 51.3 us at 256^3 FP32), k' of stages
+// 2 and 3 loaded again instead of kept (43.2), loads two planes ahead (42.5).
 // FIRSTSTEP: the pass starts the solve: stage 1 is the first step from p(0) with zero
 // initial velocity (the single-step kernel's STEP_FIRST, the same expression; pm1 is
 // not read), so the pass yields p(2) and p(3).
@@ -1003,6 +1014,7 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
   constexpr int PPT = NIN + 2;
   constexpr int NB = NX + 4;                  // LDS reads per point: x-y neighbours
   constexpr int NB2 = NB + 4;                 // stage 2: and q's centre and three z-neighbours
+  constexpr bool RWIN = NX == 2;              // r's z-column in registers (pairs; FP64 reads it from LDS)
   static_assert(NIN == 2 && N2 <= NTH && N1 <= NTH && NR <= NTH && 2 * N2 >= NTH && 2 * N1 >= NTH &&
                     2 * NR >= NTH,
                 "slot layout");
@@ -1241,7 +1253,7 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
       for (int m = 0; m < PPT - 1; ++m) rb[m][Sm2 * RP + (m < NIN ? 2 * CX : 0)] = rv[m];
 #pragma unroll
       for (int m = 0; m < NIN; ++m) {
-        rw[m][Sm2] = rv[m];
+        if constexpr (RWIN) rw[m][Sm2] = rv[m];
         asm volatile("" : : "v"(rv[m]));
       }
       const bool own = z1 >= zbeg && z1 < zend;
@@ -1254,7 +1266,8 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
 
     // stage 3: o(z2) on the interior slots, from z2 = zbeg on
     {
-      T nr[NIN][NB + 1];
+      constexpr int N3 = RWIN ? NB + 1 : NB + 5;   // LDS reads per slot
+      T nr[NIN][N3];
 #pragma unroll
       for (int m = 0; m < NIN; ++m) {
         const LP c = rb[m] + (Sm4 * RP + 2 * CX);
@@ -1265,19 +1278,27 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
         v[NX + 2] = c[-2 * CX];
         v[NX + 3] = c[2 * CX];
         v[NB] = qb[m][Sm4 * QP + 2 * AX];   // q(z2)
+        if constexpr (!RWIN) {
+          v[NB + 1] = c[0];
+          v[NB + 2] = rb[m][Sm5 * RP + 2 * CX];
+          v[NB + 3] = rb[m][Sm3 * RP + 2 * CX];
+          v[NB + 4] = rb[m][Sm6 * RP + 2 * CX];
+        }
       }
-      LdsFence<T, NIN * (NB + 1)>::all(&nr[0][0]);
+      LdsFence<T, NIN * N3>::all(&nr[0][0]);
       T ov[NIN];
 #pragma unroll
       for (int m = 0; m < NIN; ++m) {
         const T *v = nr[m];
-        const T c0 = rw[m][Sm4];
+        const T c0 = RWIN ? rw[m][Sm4] : v[NB + 1];
+        const T zm1 = RWIN ? rw[m][Sm5] : v[NB + 2], zp1 = RWIN ? rw[m][Sm3] : v[NB + 3];
+        const T zm2 = RWIN ? rw[m][Sm6] : v[NB + 4];
         T s1, s2;
         NbrX<T>::terms(v, c0, s1, s2);
         s1 = s1 + (v[NX + 0] + v[NX + 1]);
         s2 = s2 + (v[NX + 2] + v[NX + 3]);
-        s1 += rw[m][Sm5] + rw[m][Sm3];
-        s2 += rw[m][Sm6] + rv[m];
+        s1 += zm1 + zp1;
+        s2 += zm2 + rv[m];
         const T S = T(16) * s1 - s2 - T(90) * c0;
         ov[m] = T(2) * c0 - v[NB] + kw[m][Sm4] * S;
         asm volatile("" : : "v"(ov[m]));
@@ -1772,8 +1793,10 @@ bool wave_triples_preferred(const Dims &d, size_t esz)
 {
   const BlockedConfig cfg = blocked_config(d, esz);
   if (cfg.triple >= 0) return cfg.triple == 1;
-  // FP32 (pairs of points): 7% faster than two steps per pass at 256^3, 3% at 384^3;
-  // FP64: slower (see wave_step3_split)
+  // FP32 (pairs of points), measured on MI355X, us per leapfrog step two / three steps
+  // per pass: 224^3 25.2 / 25.0, 256^3 39.9 / 36.3, 288^3 68.6 / 67.7, 352^3 112.4 /
+  // 106.5, 448^3 219.7 / 212.4, 512^3 306.0 / 272.9.  FP64: 1-2% at 256^3 and 384^3,
+  // slower where short z-chunks make its 8-plane halo costly; kept at two.
   return esz == 4;
 }
 
