@@ -47,9 +47,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def _link(objs, lib: str):
+# roctx ranges of the C ABI calls (rocprofiler-sdk's marker library, beside libamdhip64)
+LINK_LIBS = ["-lrocprofiler-sdk-roctx"]
+
+
+def _link(objs, lib: str, libs=()):
     tmp = lib + ".tmp"
-    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC"] + objs + ["-o", tmp]
+    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC"] + objs + list(libs) + ["-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -81,7 +85,7 @@ def build_sanitized(jobs: int = 4) -> str:
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(one, SOURCES))
     lib = os.path.join(SAN_DIR, "libffpat.so")
-    _link(objs, lib)
+    _link(objs, lib, LINK_LIBS)
     return lib
 
 
@@ -91,7 +95,7 @@ def build(jobs: int = 4, verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(_compile, SOURCES + PROBE_SOURCES))
-    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[:len(SOURCES)], LIB, LINK_LIBS)
     _link(objs[len(SOURCES):], PROBE_LIB)
     if verbose:
         print(f"built {LIB}")

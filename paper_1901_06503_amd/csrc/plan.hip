@@ -18,6 +18,8 @@
 #include "kernels.h"
 #include "../../include/ffpat.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -25,6 +27,18 @@
 #include <mutex>
 #include <string>
 #include <vector>
+
+// A named host-side range for timeline tools (roctx; rocprofv3 --marker-trace shows
+// them): each C-ABI call that enqueues device work opens one, and the reconstruction
+// marks its power iteration, graph captures and FB iterations.  The ranges time the
+// host's enqueueing, not the kernels (which the kernel trace shows); without a tool
+// attached they cost a call each.
+struct TraceRange {
+  explicit TraceRange(const char *name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
 
 using namespace ffpat;
 
@@ -634,6 +648,7 @@ int fb_iteration(ffpat_plan *P, const T *G, T *h, const ffpat_fb_params *prm, hi
 template <typename F>
 int capture_graph(ffpat_plan *P, GraphCache &gc, F &&body)
 {
+  TraceRange trace("graph_capture");
   if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
   if (gc.exec) {
     HIP_TRY(hipGraphExecDestroy(gc.exec));
@@ -713,6 +728,7 @@ int fb_enqueue(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, hipS
   } else if (prm->step > 0) {
     HIP_TRY(launch_set(sc + SC_STEP, prm->step, s));
   } else if (graphs) {
+    TraceRange trace("power_iteration");
     const uint32_t key = prm->flags & (FFPAT_PRECOND | FFPAT_TWO_STEP);
     if (!P->g_power.matches(nullptr, nullptr, nullptr, prm->det_mask, key, 0.0, n_power, 0.0, 0)) {
       rc = capture_graph(P, P->g_power, [&](hipStream_t cs) {
@@ -723,11 +739,13 @@ int fb_enqueue(ffpat_plan *P, const T *G, const ffpat_fb_params *prm, T *h, hipS
     }
     HIP_TRY(hipGraphLaunch(P->g_power.exec, s));
   } else {
+    TraceRange trace("power_iteration");
     rc = power_iteration<T>(P, n_power, two_step, precond, prm->det_mask, s);
     if (rc) return rc;
   }
   P->has_step = true;
   if (prm->n_iter <= 0) return FFPAT_OK;
+  TraceRange trace("fb_iterations");
   if (graphs) {
     const uint32_t key = prm->flags & (FFPAT_PRECOND | FFPAT_POSITIVITY | FFPAT_REG_GRAD | FFPAT_TWO_STEP);
     const CgControl cc = cg_control<T>(prm);
@@ -891,6 +909,7 @@ int ffpat_workspace_bytes(const ffpat_geom *geom, size_t *bytes)
 
 int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, ffpat_plan **out)
 {
+  TraceRange trace("ffpat_plan_create");
   CHECK_PTR(out, "out");
   *out = nullptr;
   Resolved r;
@@ -999,6 +1018,7 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
 
 int ffpat_plan_set_speed(ffpat_plan *plan, const void *c_dev, void *stream)
 {
+  TraceRange trace("ffpat_plan_set_speed");
   CHECK_PLAN(plan);
   CHECK_PTR(c_dev, "c_dev");
   DeviceGuard guard(plan->device);
@@ -1074,6 +1094,7 @@ int ffpat_plan_destroy(ffpat_plan *plan)
 
 int ffpat_forward(ffpat_plan *plan, const void *h_dev, void *g_dev, void *stream)
 {
+  TraceRange trace("ffpat_forward");
   CHECK_PLAN(plan);
   CHECK_PTR(h_dev, "h_dev");
   CHECK_PTR(g_dev, "g_dev");
@@ -1085,6 +1106,7 @@ int ffpat_forward(ffpat_plan *plan, const void *h_dev, void *g_dev, void *stream
 
 int ffpat_adjoint(ffpat_plan *plan, const void *g_dev, void *h_dev, void *stream)
 {
+  TraceRange trace("ffpat_adjoint");
   CHECK_PLAN(plan);
   CHECK_PTR(h_dev, "h_dev");
   CHECK_PTR(g_dev, "g_dev");
@@ -1096,6 +1118,7 @@ int ffpat_adjoint(ffpat_plan *plan, const void *g_dev, void *h_dev, void *stream
 
 int ffpat_wave(ffpat_plan *plan, const void *h_dev, void *p_dev, void *stream)
 {
+  TraceRange trace("ffpat_wave");
   CHECK_PLAN(plan);
   CHECK_PTR(h_dev, "h_dev");
   CHECK_PTR(p_dev, "p_dev");
@@ -1111,6 +1134,7 @@ int ffpat_wave(ffpat_plan *plan, const void *h_dev, void *p_dev, void *stream)
 
 int ffpat_wave_adjoint(ffpat_plan *plan, const void *g_dev, void *q_dev, void *stream)
 {
+  TraceRange trace("ffpat_wave_adjoint");
   CHECK_PLAN(plan);
   CHECK_PTR(g_dev, "g_dev");
   CHECK_PTR(q_dev, "q_dev");
@@ -1122,6 +1146,7 @@ int ffpat_wave_adjoint(ffpat_plan *plan, const void *g_dev, void *q_dev, void *s
 
 int ffpat_project(ffpat_plan *plan, const void *vol_dev, void *g_dev, void *stream)
 {
+  TraceRange trace("ffpat_project");
   CHECK_PLAN(plan);
   CHECK_PTR(vol_dev, "vol_dev");
   CHECK_PTR(g_dev, "g_dev");
@@ -1134,6 +1159,7 @@ int ffpat_project(ffpat_plan *plan, const void *vol_dev, void *g_dev, void *stre
 
 int ffpat_backproject(ffpat_plan *plan, const void *g_dev, void *vol_dev, void *stream)
 {
+  TraceRange trace("ffpat_backproject");
   CHECK_PLAN(plan);
   CHECK_PTR(vol_dev, "vol_dev");
   CHECK_PTR(g_dev, "g_dev");
@@ -1146,6 +1172,7 @@ int ffpat_backproject(ffpat_plan *plan, const void *g_dev, void *vol_dev, void *
 
 int ffpat_ramp(ffpat_plan *plan, const void *r_dev, void *y_dev, void *stream)
 {
+  TraceRange trace("ffpat_ramp");
   CHECK_PLAN(plan);
   CHECK_PTR(r_dev, "r_dev");
   CHECK_PTR(y_dev, "y_dev");
@@ -1159,6 +1186,7 @@ int ffpat_ramp(ffpat_plan *plan, const void *r_dev, void *y_dev, void *stream)
 
 int ffpat_fbp(ffpat_plan *plan, const void *G_dev, void *vol_dev, void *stream)
 {
+  TraceRange trace("ffpat_fbp");
   CHECK_PLAN(plan);
   CHECK_PTR(G_dev, "G_dev");
   CHECK_PTR(vol_dev, "vol_dev");
@@ -1192,6 +1220,7 @@ static int check_fb_args(ffpat_plan *plan, const void *G_dev, const ffpat_fb_par
 int ffpat_reconstruct(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev,
                       double *step_used, void *stream)
 {
+  TraceRange trace("ffpat_reconstruct");
   int rc = check_fb_args(plan, G_dev, params, h_dev);
   if (rc) return rc;
   DeviceGuard guard(plan->device);
@@ -1203,6 +1232,7 @@ int ffpat_reconstruct(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params
 
 int ffpat_fb_enqueue(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev, void *stream)
 {
+  TraceRange trace("ffpat_fb_enqueue");
   int rc = check_fb_args(plan, G_dev, params, h_dev);
   if (rc) return rc;
   DeviceGuard guard(plan->device);
@@ -1214,6 +1244,7 @@ int ffpat_fb_enqueue(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params 
 int ffpat_fb_enqueue_noalloc(ffpat_plan *plan, const void *G_dev, const ffpat_fb_params *params, void *h_dev,
                              void *stream)
 {
+  TraceRange trace("ffpat_fb_enqueue_noalloc");
   int rc = check_fb_args(plan, G_dev, params, h_dev);
   if (rc) return rc;
   if (params->n_iter > kNoAllocMaxIter)
@@ -1234,6 +1265,7 @@ int ffpat_fb_enqueue_noalloc(ffpat_plan *plan, const void *G_dev, const ffpat_fb
 
 int ffpat_fb_report(ffpat_plan *plan, double *step_used, double *objective, int32_t n, void *stream)
 {
+  TraceRange trace("ffpat_fb_report");
   CHECK_PLAN(plan);
   if (n < 0) return fail(FFPAT_EINVAL, "n must be >= 0");
   if (n > 0 && !objective) return fail(FFPAT_EINVAL, "objective is NULL");
