@@ -526,14 +526,24 @@ def operator_384(torch, ff, synth, seed):
 
 
 def host_cpu_model():
+    """The host CPU as /proc/cpuinfo names it, with its family and model numbers (a
+    virtual machine may report only a generic name)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("model name", "cpu family", "model") and k not in info:
+                    info[k] = v
+            if len(info) == 3:
+                break
     except OSError:
         pass
-    import platform
-    return platform.processor() or "unknown"
+    if "model name" not in info:
+        import platform
+        return platform.processor() or "unknown"
+    extra = ", ".join(f"{k} {info[k]}" for k in ("cpu family", "model") if k in info)
+    return info["model name"] + (f" ({extra})" if extra else "")
 
 
 def cpu_baseline(case, G, step):
