@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--serial", type=int, default=1, help="--mode serve: also run the serial baseline (1/0)")
     ap.add_argument("--aging", type=float, default=4.0,
                     help="--mode serve, policy shortest: seconds of waiting that offset a second of remaining work")
+    ap.add_argument("--low-concurrency", type=int, default=1,
+                    help="--mode serve, policy shortest: jobs advanced together while at most --backlog are waiting")
+    ap.add_argument("--backlog", type=int, default=3,
+                    help="--mode serve, policy shortest: jobs in the system above which --concurrency applies")
     ap.add_argument("--serve-jobs", type=int, default=120,
                     help="--mode fb: jobs in the serving leg (the 120-job trace at 4 jobs/s: p50/p99 latency, "
                          "jobs/s against the serial baseline); 0 skips it")
@@ -184,10 +188,12 @@ def run_serve(args):
     angles = grid edge, 50 FB iterations + 20 power steps each, FP32.  Runs the
     same trace through the serial baseline and the continuous-batching scheduler."""
     print(json.dumps(serve_summary(args.jobs, args.rate, args.iters or 50, args.slots, args.concurrency,
-                                   args.policy, args.fill_voxels, args.serial, args.seed, args.aging)), flush=True)
+                                   args.policy, args.fill_voxels, args.serial, args.seed, args.aging,
+                                   args.low_concurrency, args.backlog)), flush=True)
 
 
-def serve_summary(n_jobs, rate, iters, slots, concurrency, policy, fill_voxels, serial, seed, aging=1.0):
+def serve_summary(n_jobs, rate, iters, slots, concurrency, policy, fill_voxels, serial, seed, aging=1.0,
+                  low_concurrency=1, backlog=3):
     import numpy as np
     import torch
     import paper_1901_06503_amd as ff
@@ -219,12 +225,14 @@ def serve_summary(n_jobs, rate, iters, slots, concurrency, policy, fill_voxels, 
     free, total = torch.cuda.mem_get_info()
     log("continuous batching")
     with serving.Scheduler(hbm_budget=int(0.5 * free), max_active=slots, iters_per_turn=5,
-                           concurrency=concurrency, policy=policy, fill_voxels=fill_voxels, aging=aging) as sched:
+                           concurrency=concurrency, policy=policy, fill_voxels=fill_voxels, aging=aging,
+                           low_concurrency=low_concurrency, backlog=backlog) as sched:
         mixed_jobs = sched.run(clone())
     mixed = serving.summary(mixed_jobs)
     log(f"scheduler: {mixed}")
     return {"mode": "serve", "jobs": n_jobs, "rate_per_s": rate, "iters": iters, "slots": slots, "policy": policy,
-            "fill_voxels": fill_voxels, "concurrency": concurrency, "aging": aging, "serial": base,
+            "fill_voxels": fill_voxels, "concurrency": concurrency, "aging": aging,
+            "low_concurrency": low_concurrency, "backlog": backlog, "serial": base,
             "continuous_batching": mixed,
             "peak_active": sched.peak_active, "peak_running": sched.peak_running, "peak_bytes": sched.peak_bytes,
             "plans_created": sched.plans_created, "plans_reused": sched.plans_reused,
@@ -667,7 +675,8 @@ def main():
         log(f"serving leg: {args.serve_jobs} jobs at 4 jobs/s")
         try:
             sv = serve_summary(args.serve_jobs, 4.0, 50, args.slots, args.concurrency, args.policy,
-                               args.fill_voxels, 1, args.seed, args.aging)
+                               args.fill_voxels, 1, args.seed, args.aging, args.low_concurrency,
+                               args.backlog)
             cb, se = sv["continuous_batching"], sv["serial"]
             serve = {"trace": f"{args.serve_jobs} jobs, Poisson 4 jobs/s, grids 64^3..256^3, 50 FB iterations each, "
                               f"FP32, policy {args.policy}",

@@ -15,7 +15,9 @@ policy:
   `aging` times the time waited since arrival (short jobs overtake long ones,
   but only those that arrived less than a few of their remaining seconds
   earlier); `concurrency` applies while more than `backlog` jobs have arrived
-  and are not finished, two run together otherwise.
+  and are not finished; with fewer, `low_concurrency` (default 1: the oldest
+  job alone, as the serial baseline runs it, so that latency below the
+  device's capacity is the serial baseline's).
 * "fill": arrival order; the oldest job always runs, and later ones join
   while the running jobs hold at most `fill_voxels` grid points together
   (small grids, whose kernels leave most of the device idle, share it; a
@@ -33,14 +35,16 @@ out of the kept iterate buffer on the job's stream.
 What overlap can gain here is bounded: one job of the serial baseline is 98% or
 more device time (plan creation, uploads, graph capture and destruction are 1-2%
 of it: 64^3 41 ms, 128^3 128 ms, 192^3 318 ms, 256^3 1.04 s on MI355X), and the
-two-step stencil kernel of a 192^3 or 256^3 job holds every compute unit while it
-runs.  What remains is the 64^3 and 128^3 jobs, whose small launches leave the
+multi-step stencil kernels of a 192^3 or 256^3 job hold every compute unit while
+they run.  What remains is the 64^3 and 128^3 jobs, whose small launches leave the
 device mostly idle, running in the gaps of the others.  On the 120-job trace
-(grids 64^3..256^3, 50 iterations each, FP32), MI355X: at 4 jobs/s, above the
-device's capacity for the mix, "shortest" with concurrency 3 and aging 4 gives
-2.91 jobs/s against 2.71 serial (+7.4%), median latency 3.6 s against 5.3 s,
-99th percentile 7.7 s against 9.6 s (concurrency 2: +5.5%); at 2 jobs/s, two at
-a time, median 0.44 s against 0.54 s and 99th percentile 2.47 s against 2.43 s.
+(grids 64^3..256^3, 50 iterations each, FP32), MI355X, "shortest" with concurrency
+3, aging 4, backlog 5: at 4 jobs/s, above the device's capacity for the mix (about
+2.9 jobs/s), 3.04 jobs/s against 2.89 serial (+5.4%), median latency 2.5 s against
+3.7 s, 99th percentile 6.3 s against 7.3 s; at 2 jobs/s median 0.38 s against 0.37 s
+and 99th percentile 2.09 s against 2.08 s (with two at a time below the backlog:
+0.41 s and 2.25 s, the sharing slowing the long jobs; run one at a time always, the
+scheduler matches the serial baseline to 1%: 0.376 / 2.084 against 0.372 / 2.076).
 
 `run_serial` is the plain baseline: one `ffpat_reconstruct` at a time in
 arrival order.
@@ -135,14 +139,15 @@ class Scheduler:
     max_active: slots.  iters_per_turn: FB iterations enqueued per job per turn.
     policy: "fill", "shortest" or "all" (see the module docstring); fill_voxels is
     the fill threshold; concurrency the number of jobs "shortest" advances while more
-    than `backlog` jobs have arrived and are not finished (two otherwise); aging the
-    seconds of waiting that offset a second of remaining work in "shortest".
+    than `backlog` jobs have arrived and are not finished, low_concurrency otherwise
+    (1: the oldest job alone, as the serial baseline would run it); aging the seconds
+    of waiting that offset a second of remaining work in "shortest".
     reuse_plans: keep finished jobs' plans for later jobs of the same geometry.
     """
 
     def __init__(self, hbm_budget: int, max_active: int = 8, iters_per_turn: int = 5, concurrency: int = 3,
                  policy: str = "shortest", fill_voxels: int = 192 ** 3, device="cuda", aging: float = 4.0,
-                 reuse_plans: bool = True, backlog: int = 3):
+                 reuse_plans: bool = True, backlog: int = 5, low_concurrency: int = 1):
         if policy not in ("fill", "shortest", "all"):
             raise ValueError(f"unknown policy {policy!r}")
         self.hbm_budget = int(hbm_budget)
@@ -153,6 +158,7 @@ class Scheduler:
         self.concurrency = max(1, int(concurrency))
         self.aging = float(aging)
         self.backlog = int(backlog)
+        self.low_concurrency = max(1, int(low_concurrency))
         self.reuse_plans = bool(reuse_plans)
         self._waiting = 0
         self.device = device
@@ -331,7 +337,7 @@ class Scheduler:
             prio = lambda a: (_remaining_work(a) / _POINT_UPDATES_PER_S - self.aging * (now - a.job.arrival),
                               a.job.arrival, a.job.job_id)
             rest = sorted(order[1:], key=prio)
-            conc = self.concurrency if self._waiting > self.backlog else min(2, self.concurrency)
+            conc = self.concurrency if self._waiting > self.backlog else min(self.low_concurrency, self.concurrency)
             return [order[0]] + rest[:conc - 1]
         chosen, vox = [order[0]], order[0].job.c.numel()
         for a in order[1:]:

@@ -151,7 +151,9 @@ def test_results_in_the_mix_equal_results_alone():
     jobs = _trace([24, 40, 32, 48, 24, 40, 32, 24], 70)
     alone = run_serial(_clone(jobs))
     for policy in ("fill", "shortest", "all"):
-        with Scheduler(hbm_budget=8 << 30, max_active=4, iters_per_turn=3, policy=policy) as sched:
+        # two at a time even below the backlog, so that work really overlaps
+        with Scheduler(hbm_budget=8 << 30, max_active=4, iters_per_turn=3, policy=policy,
+                       low_concurrency=2) as sched:
             mixed = sched.run(_clone(jobs))
         assert sched.peak_running > 1                      # work really overlapped on the device
         assert sched.plans_reused > 0                      # later jobs ran on earlier jobs' plans

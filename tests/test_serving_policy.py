@@ -45,7 +45,7 @@ def test_fill_stops_at_the_first_job_that_does_not_fit():
 
 
 def test_shortest_keeps_the_oldest_and_adds_the_least_remaining_work():
-    s = Scheduler(hbm_budget=1 << 30, policy="shortest", concurrency=2, aging=0.0)
+    s = Scheduler(hbm_budget=1 << 30, policy="shortest", concurrency=2, aging=0.0, low_concurrency=2)
     act = [_active(1, 0.0, 256), _active(2, 0.1, 128, done=40), _active(3, 0.2, 64)]
     rem = {a.job.job_id: _remaining_work(a) for a in act}
     assert rem[3] < rem[2] < rem[1]
@@ -58,7 +58,7 @@ def test_shortest_ages_waiting_jobs():
     # arrive less than its remaining work minus theirs later.  A 256^3 job with 50
     # iterations left (2 * 171 * 256^3 * 50 = 2.9e11: 0.72 s) that arrived at 1.0 goes
     # before a 64^3 job (0.007 s) arriving at 1.8, after one arriving at 1.5
-    s = Scheduler(hbm_budget=1 << 30, policy="shortest", concurrency=2, aging=1.0)
+    s = Scheduler(hbm_budget=1 << 30, policy="shortest", concurrency=2, aging=1.0, low_concurrency=2)
     s._now = 2.0
     late = [_active(1, 0.0, 128, done=10), _active(2, 1.0, 256, nt=171), _active(3, 1.8, 64)]
     assert _ids(s._choose(late)) == [1, 2]
@@ -83,9 +83,21 @@ def test_all_and_unknown_policy():
 
 
 def test_shortest_runs_more_jobs_only_under_a_backlog():
-    s = Scheduler(hbm_budget=1 << 30, policy="shortest", concurrency=3, backlog=3, aging=0.0)
+    s = Scheduler(hbm_budget=1 << 30, policy="shortest", concurrency=3, backlog=3, aging=0.0, low_concurrency=2)
     act = [_active(1, 0.0, 256), _active(2, 0.1, 64), _active(3, 0.2, 128), _active(4, 0.3, 192)]
     s._waiting = 3                                         # few jobs in the system: two at a time
     assert _ids(s._choose(act)) == [1, 2]
     s._waiting = 6                                         # a queue has formed: three
+    assert _ids(s._choose(act)) == [1, 2, 3]
+
+
+def test_shortest_runs_the_oldest_alone_below_the_backlog_by_default():
+    # below the device's capacity the default runs jobs one at a time in arrival
+    # order, as the serial baseline does (sharing the device only slows the long jobs)
+    s = Scheduler(hbm_budget=1 << 30, policy="shortest", aging=0.0)
+    assert s.backlog == 5 and s.low_concurrency == 1 and s.concurrency == 3
+    act = [_active(1, 0.0, 256), _active(2, 0.1, 64), _active(3, 0.2, 128), _active(4, 0.3, 192)]
+    s._waiting = 5
+    assert _ids(s._choose(act)) == [1]
+    s._waiting = 6
     assert _ids(s._choose(act)) == [1, 2, 3]
