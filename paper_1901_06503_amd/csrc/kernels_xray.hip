@@ -317,20 +317,24 @@ static bool xray_lds_enabled()
 }
 
 // planes per work-group of the staged backprojector (0: use the L2-gather
-// kernel): 8 in FP32 from 8 planes on (the bin position and weights serve 8
-// planes; 3% faster than 4 at 256^3 / 256 angles), else 4 (FP64: 8 planes of
-// accumulators would not fit the register budget); FFPAT_XRAY_LDS_ZP = 4 or 8
-// overrides for FP32
-static int xray_lds_planes(int nz, size_t esz)
+// kernel): in FP32 16 where that still gives at least 256 work-groups (64 x 64
+// voxel tiles), 8 from 8 planes on (the bin position and weights serve the planes:
+// 8 are 3% faster than 4 at 256^3 / 256 angles, 16 another 6%, 588.7 -> 554.4 us),
+// else 4 (FP64: 8 planes of accumulators would not fit the register budget);
+// FFPAT_XRAY_LDS_ZP = 4, 8 or 16 overrides for FP32
+static int xray_lds_planes(const Dims &d, size_t esz)
 {
   static const int env = [] {
     const char *e = getenv("FFPAT_XRAY_LDS_ZP");
     const int v = e ? atoi(e) : 0;
-    return (v == 4 || v == 8) ? v : 0;
+    return (v == 4 || v == 8 || v == 16) ? v : 0;
   }();
+  const int nz = d.nz;
   if (nz < 4) return 0;
   if (esz == 8) return 4;
   if (env) return nz >= env ? env : 4;
+  const long tiles = (long)((d.nx + 63) / 64) * ((d.ny + 63) / 64);
+  if (nz >= 16 && tiles * ((nz + 15) / 16) >= 256) return 16;
   return nz >= 8 ? 8 : 4;
 }
 
@@ -628,12 +632,18 @@ template <typename T>
 hipError_t launch_backproject(const Dims &d, int n_angles, int ns, const AngleParams *ap, bool two_tap,
                               const T *gpad, T *vol, const T *kap, hipStream_t s)
 {
-  const int zp = xray_lds_planes(d.nz, sizeof(T));
+  int zp = xray_lds_planes(d, sizeof(T));
+  if (zp == 16 && ns + kRowPadL + kRowPadR > kLdsBytes / (int)(16 * sizeof(T))) zp = 8;   // long rows
   if (two_tap && zp > 0 && ns + kRowPadL + kRowPadR <= kLdsBytes / (int)(zp * sizeof(T)) && xray_lds_enabled()) {
     const int tiles_x = (d.nx + 63) / 64, tiles_y = (d.ny + 63) / 64;
     const long n_work = (long)tiles_x * tiles_y * ((d.nz + zp - 1) / zp);
     const long grid = (n_work + 7) / 8 * 8;
     if constexpr (sizeof(T) == 4) {
+      if (zp == 16) {
+        backproject_lds_kernel<T, 16><<<(unsigned)grid, 1024, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns,
+                                                                      kap, tiles_x, tiles_y, (int)n_work);
+        return hipGetLastError();
+      }
       if (zp == 8) {
         backproject_lds_kernel<T, 8><<<(unsigned)grid, 1024, 0, s>>>(gpad, vol, ap, n_angles, d.nx, d.ny, d.nz, ns,
                                                                      kap, tiles_x, tiles_y, (int)n_work);
