@@ -471,6 +471,10 @@ def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
         full, t_first = full + 1, 0.0
     else:
         (full, rest), t_first = divmod(plan.nt - 1, k), t_single
+    if full == 0:                       # too few steps for a multi-step launch
+        out.update(kernel="wave_step_blocked", t_launch=t_single, alg_bytes=4 * esz * nvox,
+                   compulsory_bytes=4 * esz * nvox, updates_per_launch=1)
+        return out
     t_rest = 0.0 if rest == 0 else (t_single if rest == 1 else t_pair)
     out.update(kernel=multi_kernel_name(plan, dtype == torch.float64), t_launch=(t_w - t_first - t_rest) / full,
                alg_bytes=k * 4 * esz * nvox, compulsory_bytes=5 * esz * nvox, updates_per_launch=k,
