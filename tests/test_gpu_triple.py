@@ -9,7 +9,7 @@ adjoint's dividing last step alone), FP32 over pairs of x-adjacent points on rag
 grids (even nx, 128 x 16 tiles) and FP64 on ragged and degenerate grids (one voxel
 wide in x, y or z), several z-chunks and rounds of work-groups, caller buffers off
 8-byte alignment (the three-step kernel is then not taken), Algorithm 8 with
-captured graphs, and the 256^3 workload.
+captured graphs, the 256^3 workload, and the serving loop.
 """
 import numpy as np
 import pytest
@@ -172,3 +172,39 @@ def test_256cubed_workload_equals_two_steps(dtype):
         assert P3.steps_per_pass == 3 and P3.nt == P2.nt
         assert torch.equal(P3.wave(h), P2.wave(h))
         assert torch.equal(P3.wave_adjoint(h), P2.wave_adjoint(h))
+
+
+def test_serving_mix_with_three_step_plans():
+    """The serving loop on jobs whose plans run three steps per pass (FP32, 40 x 250 x
+    250, plans reused across jobs, captured graphs replayed on the jobs' streams): every
+    job's result in the mix equals its result alone, bit for bit."""
+    import paper_1901_06503_amd as ff
+    from paper_1901_06503_amd.serving import Job, Scheduler, run_serial
+    shape = (40, 250, 250)
+    _tag(shape, F32, "serving")
+    jobs = []
+    angles = None
+    for i in range(4):
+        k = make_case(shape, 40 + i, n_angles=6, T=0.1)
+        angles = k["angles"] if angles is None else angles     # one geometry: plans are reused
+        c = to_dev(rounded(k["c"], F32), F32)
+        with ff.Plan(c, k["dx"], k["T"], angles) as P:
+            assert P.steps_per_pass == 3
+            G = P.forward(to_dev(rounded(np.abs(k["h"]), F32), F32))
+        torch.cuda.synchronize()
+        jobs.append(Job(job_id=i, arrival=0.01 * i, c=c.cpu().pin_memory(), G=G.cpu().pin_memory(), dx=k["dx"],
+                        T=k["T"], angles=angles, lam=1e-3, n_iter=4, n_power=3))
+
+    def clone():
+        return [Job(job_id=j.job_id, arrival=j.arrival, c=j.c, G=j.G, dx=j.dx, T=j.T, angles=j.angles, lam=j.lam,
+                    n_iter=j.n_iter, n_power=j.n_power) for j in jobs]
+
+    alone = sorted(run_serial(clone()), key=lambda j: j.job_id)
+    with Scheduler(hbm_budget=8 << 30, max_active=4, iters_per_turn=2, low_concurrency=2) as sched:
+        mixed = sorted(sched.run(clone()), key=lambda j: j.job_id)
+    assert sched.peak_running > 1 and sched.plans_reused > 0
+    for a, b in zip(alone, mixed):
+        assert a.status == b.status == "done"
+        assert a.step == b.step
+        assert torch.equal(a.h, b.h)
+        assert np.array_equal(np.array(a.objective), np.array(b.objective))
