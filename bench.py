@@ -485,12 +485,13 @@ def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
 
 
 def multi_kernel_name(plan, f64):
-    """The kernel a plan's multi-step launches run: wave_step3_split for three steps
-    per pass; for two, wave_step2_split with 8-byte elements and the 64 x 16 element
-    tile (FP64, and FP32 as pairs of x-adjacent points, a 128-point-wide tile on a
-    grid of even nx), else wave_step2_blocked."""
+    """The kernel a plan's multi-step launches run: for three steps per pass
+    wave_step3_wide (FP32, pairs of x-adjacent points, 1024 threads) or
+    wave_step3_split (FP64); for two, wave_step2_split with 8-byte elements and the
+    64 x 16 element tile (FP64, and FP32 as pairs of points, a 128-point-wide tile on
+    a grid of even nx), else wave_step2_blocked."""
     if plan.steps_per_pass == 3:
-        return "wave_step3_split"
+        return "wave_step3_split" if f64 else "wave_step3_wide"
     if os.environ.get("FFPAT_STENCIL2_SPLIT", "1") == "0":
         return "wave_step2_blocked"
     tx, ty, _ = plan.stencil_shape

@@ -954,15 +954,16 @@ struct LdsFence<T, 36> {
   }
 };
 
-// Three leapfrog steps per pass (eq. wave1): from p(k-1), p(k) and k' the kernel
-// computes q = p(k+1), r = p(k+2) and o = p(k+3) and writes r and o, the two levels
-// the next pass starts from: five words per voxel for three steps (the two-step
-// kernel moves five for two).  Same tile (64 x 16 elements, 512 threads, one group
-// per compute unit), same arithmetic, in the same order, as wave_step2_split, so
-// the results equal those of two- and one-step passes bit for bit.
+// Three leapfrog steps per pass (eq. wave1), FP64: from p(k-1), p(k) and k' the
+// kernel computes q = p(k+1), r = p(k+2) and o = p(k+3) and writes r and o, the two
+// levels the next pass starts from: five words per voxel for three steps (the
+// two-step kernel moves five for two).  Same tile (64 x 16 elements, 512 threads, one
+// group per compute unit), same arithmetic, in the same order, as wave_step2_split,
+// so the results equal those of two- and one-step passes bit for bit.  (FP32, as
+// pairs of points, runs the same stages in wave_step3_wide.)
 //
-// Regions of the tile, in elements (E = one step's x reach: 1 for pairs of points,
-// 2 in FP64; two rows in y):
+// Regions of the tile, in elements (E = one step's x reach: 2 in FP64, 1 for pairs of
+// points; two rows in y):
 //   p(k) plane in LDS: tile + 3E in x, 6 rows in y        (KX x KY)
 //   stage 1, q:        tile + 2E, 4 rows                  (AX x AY)
 //   stage 2, r:        tile + E, 2 rows                   (CX x CY)
@@ -976,18 +977,16 @@ struct LdsFence<T, 36> {
 // exactly zero, as the zero values outside the grid require, without a mask.
 // Per plane zs (stage 1), in one barrier interval: stage 1 at zs, stage 2 at zs - 2,
 // stage 3 at zs - 4.  The q and r planes live in 5-plane LDS rings; stage 2 reads
-// q's x-y neighbours, centre and z-neighbours there, stage 3 r's x-y neighbours,
-// while the z-column of r that stage 3 needs stays in the thread's registers (the
-// same for q did not fit in 256 VGPRs).  The value a thread has just computed for
-// its own column is taken from its register.  A ring slot is rewritten five
-// planes after it was written, after the barrier that follows its last read.
-// Loads run one plane ahead (two would spill).  In FP64 (four x-neighbour reads per
-// point) r's z-column is read from the ring as well, which keeps it within 256 VGPRs.
-// Measured on MI355X, us per leapfrog step (two-step kernel / this one): FP32 256^3
-// 39.9 / 36.3, 384^3 129.3 / 123.5; FP64 256^3 70.0 / 69.2, 384^3 254.6 / 250.0 (FP64
-// plans keep two steps per pass unless FFPAT_PLAN_THREE_STEP asks otherwise).
-// Tried: q's z-column in registers too (spills: 51.3 us at 256^3 FP32), k' of stages
-// 2 and 3 loaded again instead of kept (43.2), loads two planes ahead (42.5).
+// q's x-y neighbours, centre and z-neighbours there, stage 3 r's.  The value a thread
+// has just computed for its own column is taken from its register.  A ring slot is
+// rewritten five planes after it was written, after the barrier that follows its
+// last read.  Loads run one plane ahead.
+// Measured on MI355X, us per leapfrog step (two-step kernel / this one): 256^3 70.0 /
+// 69.2, 384^3 254.6 / 250.0 (FP64 plans keep two steps per pass unless
+// FFPAT_PLAN_THREE_STEP asks otherwise).  The same kernel over pairs of FP32 points,
+// with r's z-column in registers, ran 36.3 us per step at 256^3 (two-step 39.9);
+// there q's z-column in registers too spilled (51.3), k' of stages 2 and 3 loaded
+// again instead of kept took 43.2, loads two planes ahead 42.5.
 // FIRSTSTEP: the pass starts the solve: stage 1 is the first step from p(0) with zero
 // initial velocity (the single-step kernel's STEP_FIRST, the same expression; pm1 is
 // not read), so the pass yields p(2) and p(3).
@@ -1012,9 +1011,9 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
   constexpr int N1 = AX * AY - CX * CY;       // ring of stage 1 (pairs 312, FP64 368)
   constexpr int NR = KX * KY - AX * AY;       // outer ring of the p(k) plane (pairs 328, FP64 400)
   constexpr int PPT = NIN + 2;
+  static_assert(std::is_same_v<T, double>, "pairs of FP32 points run wave_step3_wide");
   constexpr int NB = NX + 4;                  // LDS reads per point: x-y neighbours
   constexpr int NB2 = NB + 4;                 // stage 2: and q's centre and three z-neighbours
-  constexpr bool RWIN = NX == 2;              // r's z-column in registers (pairs; FP64 reads it from LDS)
   static_assert(NIN == 2 && N2 <= NTH && N1 <= NTH && NR <= NTH && 2 * N2 >= NTH && 2 * N1 >= NTH &&
                     2 * NR >= NTH,
                 "slot layout");
@@ -1055,7 +1054,6 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
   auto plane_at = [&](const T *f, int z) { return f + (size_t)min(max(z, 0), nz - 1) * plane; };
   T w[PPT][5];        // p(k) z-window of every slot
   T kw[PPT - 1][5];   // k' of the slots of stage 2, planes zs-4..zs
-  T rw[NIN][5];       // r z-window of the interior slots
 #pragma unroll
   for (int m = 0; m < PPT; ++m) {
     int lx, ly;
@@ -1099,7 +1097,6 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       kw[m][q] = T(0);
-      if (m < NIN) rw[m][q] = T(0);
     }
 
   // LDS base of each slot in each array, at its lowest read (slots that only write
@@ -1252,10 +1249,7 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
 #pragma unroll
       for (int m = 0; m < PPT - 1; ++m) rb[m][Sm2 * RP + (m < NIN ? 2 * CX : 0)] = rv[m];
 #pragma unroll
-      for (int m = 0; m < NIN; ++m) {
-        if constexpr (RWIN) rw[m][Sm2] = rv[m];
-        asm volatile("" : : "v"(rv[m]));
-      }
+      for (int m = 0; m < NIN; ++m) asm volatile("" : : "v"(rv[m]));
       const bool own = z1 >= zbeg && z1 < zend;
       T *r_pl = r_out + (size_t)min(max(z1, 0), nz - 1) * plane;
 #pragma unroll
@@ -1266,7 +1260,7 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
 
     // stage 3: o(z2) on the interior slots, from z2 = zbeg on
     {
-      constexpr int N3 = RWIN ? NB + 1 : NB + 5;   // LDS reads per slot
+      constexpr int N3 = NB + 5;   // LDS reads per slot
       T nr[NIN][N3];
 #pragma unroll
       for (int m = 0; m < NIN; ++m) {
@@ -1278,21 +1272,19 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
         v[NX + 2] = c[-2 * CX];
         v[NX + 3] = c[2 * CX];
         v[NB] = qb[m][Sm4 * QP + 2 * AX];   // q(z2)
-        if constexpr (!RWIN) {
-          v[NB + 1] = c[0];
-          v[NB + 2] = rb[m][Sm5 * RP + 2 * CX];
-          v[NB + 3] = rb[m][Sm3 * RP + 2 * CX];
-          v[NB + 4] = rb[m][Sm6 * RP + 2 * CX];
-        }
+        v[NB + 1] = c[0];
+        v[NB + 2] = rb[m][Sm5 * RP + 2 * CX];
+        v[NB + 3] = rb[m][Sm3 * RP + 2 * CX];
+        v[NB + 4] = rb[m][Sm6 * RP + 2 * CX];
       }
       LdsFence<T, NIN * N3>::all(&nr[0][0]);
       T ov[NIN];
 #pragma unroll
       for (int m = 0; m < NIN; ++m) {
         const T *v = nr[m];
-        const T c0 = RWIN ? rw[m][Sm4] : v[NB + 1];
-        const T zm1 = RWIN ? rw[m][Sm5] : v[NB + 2], zp1 = RWIN ? rw[m][Sm3] : v[NB + 3];
-        const T zm2 = RWIN ? rw[m][Sm6] : v[NB + 4];
+        const T c0 = v[NB + 1];
+        const T zm1 = v[NB + 2], zp1 = v[NB + 3];
+        const T zm2 = v[NB + 4];
         T s1, s2;
         NbrX<T>::terms(v, c0, s1, s2);
         s1 = s1 + (v[NX + 0] + v[NX + 1]);
@@ -1322,6 +1314,372 @@ wave_step3_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
   step(std::integral_constant<int, 6>{}, S2{}, zbeg + 2);
   step(std::integral_constant<int, 7>{}, S2{}, zbeg + 3);
   for (int zb = zbeg + 4; zb <= zlast; zb += 10) {            // o planes zbeg .. zend-1
+    step(std::integral_constant<int, 8>{}, S3{}, zb);
+    if (zb + 1 > zlast) break;
+    step(std::integral_constant<int, 9>{}, S3{}, zb + 1);
+    if (zb + 2 > zlast) break;
+    step(std::integral_constant<int, 10>{}, S3{}, zb + 2);
+    if (zb + 3 > zlast) break;
+    step(std::integral_constant<int, 11>{}, S3{}, zb + 3);
+    if (zb + 4 > zlast) break;
+    step(std::integral_constant<int, 12>{}, S3{}, zb + 4);
+    if (zb + 5 > zlast) break;
+    step(std::integral_constant<int, 13>{}, S3{}, zb + 5);
+    if (zb + 6 > zlast) break;
+    step(std::integral_constant<int, 14>{}, S3{}, zb + 6);
+    if (zb + 7 > zlast) break;
+    step(std::integral_constant<int, 15>{}, S3{}, zb + 7);
+    if (zb + 8 > zlast) break;
+    step(std::integral_constant<int, 16>{}, S3{}, zb + 8);
+    if (zb + 9 > zlast) break;
+    step(std::integral_constant<int, 17>{}, S3{}, zb + 9);
+  }
+}
+
+template <typename T>
+struct LdsFence<T, 6> {
+  static __device__ __forceinline__ void all(T *v)
+  {
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]));
+  }
+};
+template <typename T>
+struct LdsFence<T, 11> {
+  static __device__ __forceinline__ void all(T *v)
+  {
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),
+                 "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]));
+  }
+};
+template <typename T>
+struct LdsFence<T, 10> {
+  static __device__ __forceinline__ void all(T *v)
+  {
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),
+                 "+v"(v[7]), "+v"(v[8]), "+v"(v[9]));
+  }
+};
+template <typename T>
+struct LdsFence<T, 12> {
+  static __device__ __forceinline__ void all(T *v)
+  {
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),
+                 "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]));
+  }
+};
+template <typename T>
+struct LdsFence<T, 20> {
+  static __device__ __forceinline__ void all(T *v)
+  {
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),
+                 "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]),
+                 "+v"(v[14]), "+v"(v[15]), "+v"(v[16]), "+v"(v[17]), "+v"(v[18]), "+v"(v[19]));
+  }
+};
+
+// Ring slots of wave_step3_wide: wave w of a work-group (16 waves) takes the ring role
+// wide_role_of(w) (2: the ring of stage 2, 1: the ring of stage 1, 0: the outer ring
+// of the p(k) plane) as the wide_role_index(w)-th wave of that role.  Five waves for
+// 296 and 312 points, six for 328; ordered so that with wave w on SIMD w % 4 the SIMDs
+// carry 4, 4, 4 and 3 ring stages per plane (grouped by role, waves 0-4, 5-9 and
+// 10-15: 33.9 us per step at 256^3 as well, 124.2 against 121.3 at 384^3).
+__host__ __device__ constexpr int wide_role_of(int w)
+{
+  constexpr int r[16] = {2, 2, 2, 1, 2, 2, 1, 1, 0, 0, 1, 1, 0, 0, 0, 0};
+  return r[w];
+}
+__host__ __device__ constexpr int wide_role_index(int w)
+{
+  int n = 0;
+  for (int v = 0; v < w; ++v) n += wide_role_of(v) == wide_role_of(w);
+  return n;
+}
+__host__ __device__ constexpr unsigned long long wide_pack(bool index)
+{
+  unsigned long long p = 0;
+  for (int w = 0; w < 16; ++w)
+    p |= (unsigned long long)(index ? wide_role_index(w) : wide_role_of(w)) << (4 * w);
+  return p;
+}
+
+// Three leapfrog steps per pass (eq. wave1) over pairs of FP32 points, with 1024
+// threads: the tile (64 x 16 elements), the stages, the LDS rings and the arithmetic
+// of wave_step3_split, but one interior point per thread (wave w takes tile row w) and
+// one ring point, whose kind is the wave's: the ring of stage 2 (stages 1 and 2), the
+// ring of stage 1 (stage 1) or the outer ring of the p(k) plane (loaded into LDS
+// only).  Each wave computes its own slots only (with 512 threads and two interior
+// points each, every thread also carries one point of each ring, repeated on the
+// threads beyond a ring's count), and four waves per SIMD hide more of the per-plane
+// chain (LDS reads, arithmetic, LDS writes, three times, and one barrier) than two.
+// With 128 VGPRs, r's z-column is read from the ring (in registers the kernel spills),
+// and the ring's stage-2 reads share the interior's wait (separate waits: 34.6 against
+// 33.9 us per step at 256^3; stage 3's reads issued with stage 2's spill).  The sums
+// run in the same order as in the one- and two-step passes, whose results it equals
+// bit for bit.  Measured on MI355X, us per leapfrog step, 512 threads (two interior
+// points per thread, r's z-column in registers) / this kernel: 224^3 24.75 / 22.54,
+// 256^3 35.86 / 33.94, 288^3 67.52 / 63.42, 352^3 106.61 / 98.83, 384^3 123.85 /
+// 121.33, 448^3 212.06 / 201.31, 512^3 272.69 / 264.87.
+template <bool FIRSTSTEP>
+__global__ void __launch_bounds__(1024, 1)
+wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, const f32x2 *kap, int nx, int ny,
+                int nz, int zchunk, int tiles_x, int tiles_y, int n_tiles, int xy_fastest)
+{
+  using T = f32x2;
+  constexpr int NTH = 1024, BX = 64, BY = 16;
+  constexpr int NX = NbrX<T>::N;              // 2: the elements at x - 1 and x + 1
+  constexpr int E = NX / 2;
+  constexpr int XH = 3 * E;
+  constexpr int KX = BX + 2 * XH, KY = BY + 12;
+  constexpr int AX = BX + 4 * E, AY = BY + 8;
+  constexpr int CX = BX + 2 * E, CY = BY + 4;
+  constexpr int N2 = CX * CY - BX * BY;       // ring of stage 2 (296)
+  constexpr int N1 = AX * AY - CX * CY;       // ring of stage 1 (312)
+  constexpr int NR = KX * KY - AX * AY;       // outer ring of the p(k) plane (328)
+  constexpr int NB = NX + 4;
+  constexpr int NB2 = NB + 4;
+  static_assert(BX * BY == NTH && N2 <= 5 * 64 && N1 <= 5 * 64 && NR <= 6 * 64, "slot layout");
+  constexpr int KP = KY * KX, QP = AY * AX, RP = CY * CX;
+  // p(k) planes and q ring with 2 rows of headroom in front (see the LDS bases below)
+  __shared__ T lkm[2 * KX + 2 * KP];
+  __shared__ T lqm[2 * AX + 5 * QP];
+  __shared__ T lr[5][RP];
+  T *const lk0 = lkm + 2 * KX, *const lq0 = lqm + 2 * AX;
+
+  const int b = blockIdx.x;
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int t = (b % 8) * per_xcd + b / 8;
+  if (t >= n_tiles) return;
+  const int n_zc = (nz + zchunk - 1) / zchunk;
+  int zc, txy;
+  if (xy_fastest) {
+    const int n_xy = tiles_x * tiles_y;
+    txy = t % n_xy;
+    zc = t / n_xy;
+  } else {
+    zc = t % n_zc;
+    txy = t / n_zc;
+  }
+  const int x0 = (txy % tiles_x) * BX, y0 = (txy / tiles_x) * BY;
+  const int zbeg = zc * zchunk;
+  const int zend = min(nz, zbeg + zchunk);
+  const size_t plane = (size_t)nx * ny;
+  const int zstart = zbeg - 4;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr unsigned long long ROLES = wide_pack(false), RIDX = wide_pack(true);
+  const int role = (int)((ROLES >> (4 * wv)) & 15);
+  const int ridx = (int)((RIDX >> (4 * wv)) & 15);
+  const bool ring1 = role >= 1, ring2 = role == 2;   // the ring point computes stage 1 / stage 2
+
+  const unsigned plane_bytes = (unsigned)(plane * sizeof(T));
+  auto plane_range = [&](int z) { return (z >= 0 && z < nz) ? plane_bytes : 0u; };
+  auto plane_at = [&](const T *f, int z) { return f + (size_t)min(max(z, 0), nz - 1) * plane; };
+  auto grid_off = [&](int lx, int ly) {
+    const int gx = x0 - XH + lx, gy = y0 - 6 + ly;
+    const bool ing = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    return ing ? (unsigned)((gy * nx + gx) * sizeof(T)) : 0xFFFFFFF0u;
+  };
+
+  // interior point: row wv of the tile, element lane
+  const int ilx = XH + lane, ily = 6 + wv;
+  // ring point: ring of width E (x) and 2 rows (y) just outside a region of rw x rh
+  // elements whose origin sits at (inset E, 2 inset) in the p(k) plane
+  int rlx, rly;
+  {
+    const int rwid = role == 2 ? CX : (role == 1 ? AX : KX);
+    const int rh = role == 2 ? CY : (role == 1 ? AY : KY);
+    const int n = role == 2 ? N2 : (role == 1 ? N1 : NR);
+    const int inset = role;
+    int u = ridx * 64 + lane;
+    u = u < n ? u : u - n;                    // lanes beyond the count repeat a point of the ring
+    int sx, sy;
+    if (u < 4 * rwid) {
+      const int r = u / rwid;
+      sy = r < 2 ? r : rh - 4 + r;
+      sx = u - r * rwid;
+    } else {
+      const int j = u - 4 * rwid;
+      sy = 2 + j / (2 * E);
+      const int cc = j % (2 * E);
+      sx = cc < E ? cc : rwid - 2 * E + cc;
+    }
+    rlx = sx + inset * E;
+    rly = sy + 2 * inset;
+  }
+  const unsigned boffI = grid_off(ilx, ily), boffR = grid_off(rlx, rly);
+
+  T wI[5], wR[5], kwI[5], kwR[5];
+#pragma unroll
+  for (int d = -2; d <= 1; ++d) {
+    const int zq = zstart + d;
+    wI[(d + 5) % 5] = ld_ranged(plane_at(pk, zq), plane_range(zq), boffI);
+    wR[(d + 5) % 5] = ld_ranged(plane_at(pk, zq), plane_range(zq), boffR);
+  }
+  wI[2] = T(0);
+  wR[2] = T(0);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    kwI[q] = T(0);
+    kwR[q] = T(0);
+  }
+
+  // LDS bases kept opaque (base + immediate offset per access, as in wave_step3_split),
+  // each 2 rows above its point, the lowest row a stage reads; the headroom in front
+  // of lk0 and lq0 keeps that inside the arrays for ring points near the top that only
+  // write there (the outer ring's p(k), stage 1's ring's q)
+  using LP = __attribute__((address_space(3))) T *;
+  auto opaque = [](T *p) {
+    LP q = (LP)p;
+    asm volatile("" : "+v"(q));
+    return q;
+  };
+  const int ilofs = ily * KX + ilx, iqrd = (ily - 2) * AX + (ilx - E), irrd = (ily - 4) * CX + (ilx - 2 * E);
+  const int rlofs = rly * KX + rlx, rqrd = (rly - 2) * AX + (rlx - E);
+  const int rrrd = ring2 ? (rly - 4) * CX + (rlx - 2 * E) : 0;
+  const LP kbI = opaque(&lk0[ilofs - 2 * KX]), qbI = opaque(&lq0[iqrd - 2 * AX]), rbI = opaque(&lr[0][irrd - 2 * CX]);
+  const LP kbR = opaque(&lk0[rlofs - 2 * KX]), qbR = opaque(&lq0[ring1 ? rqrd - 2 * AX : 0]);
+  const LP rwrR = opaque(&lr[0][rrrd]);
+
+  T nwI, npvI, nkvI, nwR, npvR, nkvR;
+  auto fetch = [&](int zf) {
+    const unsigned bw = plane_range(zf + 2), bc = plane_range(zf), bcr = ring1 ? bc : 0u;
+    const T *pw = plane_at(pk, zf + 2), *pp = FIRSTSTEP ? pk : plane_at(pm1, zf);
+    const T *pkap = plane_at(kap, zf);
+    nwI = ld_ranged(pw, bw, boffI);
+    if constexpr (!FIRSTSTEP) npvI = ld_ranged(pp, bc, boffI);
+    nkvI = ld_ranged(pkap, bc, boffI);
+    nwR = ld_ranged(pw, bw, boffR);
+    if constexpr (!FIRSTSTEP) npvR = ld_ranged(pp, bcr, boffR);
+    nkvR = ld_ranged(pkap, bcr, boffR);
+  };
+  fetch(zstart);
+
+  auto stencil = [](const T *nb, T c0, T zm1, T zp1, T zm2, T zp2) {
+    T s1, s2;
+    NbrX<T>::terms(nb, c0, s1, s2);
+    s1 = s1 + (nb[NX + 0] + nb[NX + 1]);
+    s2 = s2 + (nb[NX + 2] + nb[NX + 3]);
+    s1 += zm1 + zp1;
+    s2 += zm2 + zp2;
+    return T(16) * s1 - s2 - T(90) * c0;
+  };
+  auto xy_reads = [](LP c, int pitch, T *v) {
+    NbrX<T>::load(c, v);
+    v[NX + 0] = c[-pitch];
+    v[NX + 1] = c[pitch];
+    v[NX + 2] = c[-2 * pitch];
+    v[NX + 3] = c[2 * pitch];
+  };
+
+  auto step = [&](auto phase, auto nstages, int zs) {
+    constexpr int Q = decltype(phase)::value, NS = decltype(nstages)::value;
+    constexpr int P = Q % 5, B = Q % 2;
+    constexpr int Sm6 = (P + 4) % 5, Sm5 = P, Sm4 = (P + 1) % 5, Sm3 = (P + 2) % 5, Sm2 = (P + 3) % 5;
+    constexpr int Sm1 = (P + 4) % 5, S0 = P, Sp1 = (P + 1) % 5, Sp2 = (P + 2) % 5;
+    const int z1 = zs - 2, z2 = zs - 4;
+    wI[Sp2] = nwI;
+    wR[Sp2] = nwR;
+    T pvI = T(0), pvR = T(0);
+    if constexpr (!FIRSTSTEP) {
+      pvI = npvI;
+      pvR = npvR;
+    }
+    const T kvI = nkvI, kvR = nkvR;
+    kwI[S0] = kvI;
+    kwR[S0] = kvR;
+    kbI[B * KP + 2 * KX] = wI[S0];
+    kbR[B * KP + 2 * KX] = wR[S0];
+    fetch(zs + 1);
+    __syncthreads();
+
+    // stage 1: q(zs) on the interior point and on a ring point of stage 1 or 2
+    T qI, qR = T(0);
+    {
+      T nb[2][NB];
+      xy_reads(kbI + (B * KP + 2 * KX), KX, nb[0]);
+      if (ring1) {
+        xy_reads(kbR + (B * KP + 2 * KX), KX, nb[1]);
+        LdsFence<T, 2 * NB>::all(&nb[0][0]);
+        const T c0 = wR[S0];
+        const T S = stencil(nb[1], c0, wR[Sm1], wR[Sp1], wR[Sm2], wR[Sp2]);
+        qR = FIRSTSTEP ? c0 + T(0.5) * kvR * S : T(2) * c0 - pvR + kvR * S;
+        qbR[S0 * QP + 2 * AX] = qR;
+      } else {
+        LdsFence<T, NB>::all(&nb[0][0]);
+      }
+      const T c0 = wI[S0];
+      const T S = stencil(nb[0], c0, wI[Sm1], wI[Sp1], wI[Sm2], wI[Sp2]);
+      qI = FIRSTSTEP ? c0 + T(0.5) * kvI * S : T(2) * c0 - pvI + kvI * S;
+      qbI[S0 * QP + 2 * AX] = qI;
+    }
+    if constexpr (NS == 1) return;
+
+    // stage 2: r(z1) on the interior point and on a ring point of stage 2; q's centre
+    // and z-neighbours from the ring, q(zs) of the thread's own column from stage 1
+    T rI;
+    {
+      T nq[2][NB2];
+      auto reads = [&](LP qb, T *v) {
+        xy_reads(qb + (Sm2 * QP + 2 * AX), AX, v);
+        v[NB + 0] = qb[Sm2 * QP + 2 * AX];
+        v[NB + 1] = qb[Sm3 * QP + 2 * AX];
+        v[NB + 2] = qb[Sm1 * QP + 2 * AX];
+        v[NB + 3] = qb[Sm4 * QP + 2 * AX];
+      };
+      reads(qbI, nq[0]);
+      if (ring2) {
+        reads(qbR, nq[1]);
+        LdsFence<T, 2 * NB2>::all(&nq[0][0]);
+        const T *v = nq[1];
+        const T S = stencil(v, v[NB], v[NB + 1], v[NB + 2], v[NB + 3], qR);
+        const T rR = T(2) * v[NB] - wR[Sm2] + kwR[Sm2] * S;
+        rwrR[Sm2 * RP] = rR;
+      } else {
+        LdsFence<T, NB2>::all(&nq[0][0]);
+      }
+      const T *v = nq[0];
+      const T S = stencil(v, v[NB], v[NB + 1], v[NB + 2], v[NB + 3], qI);
+      rI = T(2) * v[NB] - wI[Sm2] + kwI[Sm2] * S;
+      rbI[Sm2 * RP + 2 * CX] = rI;
+      asm volatile("" : : "v"(rI));
+      const bool own = z1 >= zbeg && z1 < zend;
+      st_ranged(r_out + (size_t)min(max(z1, 0), nz - 1) * plane, own ? plane_bytes : 0u, boffI, rI);
+    }
+    if constexpr (NS == 2) return;
+
+    // stage 3: o(z2) on the interior point; r's centre and z-neighbours from the ring
+    // as well (with them in registers the kernel exceeds 128 VGPRs), r(zs - 2) of the
+    // thread's own column from stage 2
+    {
+      T nr[NB + 5];
+      xy_reads(rbI + (Sm4 * RP + 2 * CX), CX, nr);
+      nr[NB] = qbI[Sm4 * QP + 2 * AX];   // q(z2)
+      nr[NB + 1] = rbI[Sm4 * RP + 2 * CX];
+      nr[NB + 2] = rbI[Sm5 * RP + 2 * CX];
+      nr[NB + 3] = rbI[Sm3 * RP + 2 * CX];
+      nr[NB + 4] = rbI[Sm6 * RP + 2 * CX];
+      LdsFence<T, NB + 5>::all(nr);
+      const T S = stencil(nr, nr[NB + 1], nr[NB + 2], nr[NB + 3], nr[NB + 4], rI);
+      const T o = T(2) * nr[NB + 1] - nr[NB] + kwI[Sm4] * S;
+      asm volatile("" : : "v"(o));
+      st_ranged(o_out + (size_t)z2 * plane, plane_bytes, boffI, o);
+    }
+  };
+
+  const int zlast = zend + 3;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  using S3 = std::integral_constant<int, 3>;
+  step(std::integral_constant<int, 0>{}, S1{}, zstart);
+  step(std::integral_constant<int, 1>{}, S1{}, zstart + 1);
+  step(std::integral_constant<int, 2>{}, S1{}, zstart + 2);
+  step(std::integral_constant<int, 3>{}, S1{}, zstart + 3);
+  step(std::integral_constant<int, 4>{}, S2{}, zbeg);
+  step(std::integral_constant<int, 5>{}, S2{}, zbeg + 1);
+  step(std::integral_constant<int, 6>{}, S2{}, zbeg + 2);
+  step(std::integral_constant<int, 7>{}, S2{}, zbeg + 3);
+  for (int zb = zbeg + 4; zb <= zlast; zb += 10) {
     step(std::integral_constant<int, 8>{}, S3{}, zb);
     if (zb + 1 > zlast) break;
     step(std::integral_constant<int, 9>{}, S3{}, zb + 1);
@@ -1638,8 +1996,12 @@ static PairShape triple_shape(const Dims &d, const BlockedConfig &cfg)
 {
   static const int occ = [] {
     int n = 0;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wave_step3_split<T, std::is_same_v<T, double>>,
-                                                        512, 0) == hipSuccess ? n : 0;
+    hipError_t e;
+    if constexpr (std::is_same_v<T, f32x2>)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wave_step3_wide<false>, 1024, 0);
+    else
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wave_step3_split<T, true>, 512, 0);
+    return e == hipSuccess ? n : 0;
   }();
   const int cus = device_cus();
   return pair_shape_for(d.nx, d.ny, d.nz, 64, 16, occ > 0 ? occ : 1, cus > 0 ? cus : 256, true, cfg.zchunk3);
@@ -1673,11 +2035,11 @@ hipError_t launch_wave_triple(const Dims &d, const T *pm1, const T *pk, T *r_out
     f32x2 *r2 = reinterpret_cast<f32x2 *>(r_out), *o2 = reinterpret_cast<f32x2 *>(o_out);
     const f32x2 *k2 = reinterpret_cast<const f32x2 *>(kap);
     if (first)
-      wave_step3_split<f32x2, false, true><<<grid, 512, 0, s>>>(a, b, r2, o2, k2, e.nx, e.ny, e.nz, p.zchunk, p.tiles_x,
-                                                                p.tiles_y, p.n_tiles, cfg.order);
+      wave_step3_wide<true><<<grid, 1024, 0, s>>>(a, b, r2, o2, k2, e.nx, e.ny, e.nz, p.zchunk, p.tiles_x, p.tiles_y,
+                                                  p.n_tiles, cfg.order);
     else
-      wave_step3_split<f32x2, false, false><<<grid, 512, 0, s>>>(a, b, r2, o2, k2, e.nx, e.ny, e.nz, p.zchunk,
-                                                                 p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
+      wave_step3_wide<false><<<grid, 1024, 0, s>>>(a, b, r2, o2, k2, e.nx, e.ny, e.nz, p.zchunk, p.tiles_x, p.tiles_y,
+                                                   p.n_tiles, cfg.order);
   } else {
     const PairShape p = triple_shape<T>(d, cfg);
     const int grid = ((p.n_tiles + 7) / 8) * 8;
