@@ -40,9 +40,9 @@ they run.  What remains is the 64^3 and 128^3 jobs, whose small launches leave t
 device mostly idle, running in the gaps of the others.  On the 120-job trace
 (grids 64^3..256^3, 50 iterations each, FP32), MI355X, "shortest" with concurrency
 3, aging 4, backlog 5: at 4 jobs/s, above the device's capacity for the mix (about
-2.9 jobs/s), 3.04 jobs/s against 2.89 serial (+5.4%), median latency 2.5 s against
-3.7 s, 99th percentile 6.3 s against 7.3 s; at 2 jobs/s median 0.38 s against 0.37 s
-and 99th percentile 2.09 s against 2.08 s (with two at a time below the backlog:
+3 jobs/s), 3.16 jobs/s against 2.96 serial (+7.1%), median latency 1.7 s against
+3.2 s, 99th percentile 5.1 s against 6.6 s; at 2 jobs/s (with a 6% slower FP32
+stencil) median 0.38 s against 0.37 s and 99th percentile 2.09 s against 2.08 s (with two at a time below the backlog:
 0.41 s and 2.25 s, the sharing slowing the long jobs; run one at a time always, the
 scheduler matches the serial baseline to 1%: 0.376 / 2.084 against 0.372 / 2.076).
 
