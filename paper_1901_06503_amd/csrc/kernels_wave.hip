@@ -1377,73 +1377,47 @@ struct LdsFence<T, 20> {
   }
 };
 
-// Ring slots of wave_step3_wide: wave w of a work-group (16 waves) takes the ring role
-// wide_role_of(w) (2: the ring of stage 2, 1: the ring of stage 1, 0: the outer ring
-// of the p(k) plane) as the wide_role_index(w)-th wave of that role.  Five waves for
-// 296 and 312 points, six for 328; ordered so that with wave w on SIMD w % 4 the SIMDs
-// carry 4, 4, 4 and 3 ring stages per plane (grouped by role, waves 0-4, 5-9 and
-// 10-15: 33.9 us per step at 256^3 as well, 124.2 against 121.3 at 384^3).
-__host__ __device__ constexpr int wide_role_of(int w)
-{
-  constexpr int r[16] = {2, 2, 2, 1, 2, 2, 1, 1, 0, 0, 1, 1, 0, 0, 0, 0};
-  return r[w];
-}
-__host__ __device__ constexpr int wide_role_index(int w)
-{
-  int n = 0;
-  for (int v = 0; v < w; ++v) n += wide_role_of(v) == wide_role_of(w);
-  return n;
-}
-__host__ __device__ constexpr unsigned long long wide_pack(bool index)
-{
-  unsigned long long p = 0;
-  for (int w = 0; w < 16; ++w)
-    p |= (unsigned long long)(index ? wide_role_index(w) : wide_role_of(w)) << (4 * w);
-  return p;
-}
-
 // Three leapfrog steps per pass (eq. wave1) over pairs of FP32 points, with 1024
 // threads: the tile (64 x 16 elements), the stages, the LDS rings and the arithmetic
 // of wave_step3_split, but one interior point per thread (wave w takes tile row w) and
 // one ring point, whose kind is the wave's: the ring of stage 2 (stages 1 and 2), the
 // ring of stage 1 (stage 1) or the outer ring of the p(k) plane (loaded into LDS
-// only).  Each wave computes its own slots only (with 512 threads and two interior
-// points each, every thread also carries one point of each ring, repeated on the
-// threads beyond a ring's count), and four waves per SIMD hide more of the per-plane
-// chain (LDS reads, arithmetic, LDS writes, three times, and one barrier) than two.
-// With 128 VGPRs, r's z-column is read from the ring (in registers the kernel spills),
-// and the ring's stage-2 reads share the interior's wait (separate waits: 34.6 against
-// 33.9 us per step at 256^3; stage 3's reads issued with stage 2's spill).  The sums
-// run in the same order as in the one- and two-step passes, whose results it equals
-// bit for bit.  Measured on MI355X, us per leapfrog step, 512 threads (two interior
-// points per thread, r's z-column in registers) / this kernel: 224^3 24.75 / 22.54,
-// 256^3 35.86 / 33.94, 288^3 67.52 / 63.42, 352^3 106.61 / 98.83, 384^3 123.85 /
-// 121.33, 448^3 212.06 / 201.31, 512^3 272.69 / 264.87.
+// only).  The layout is wide3_interior, wide3_ring and wide3_role of launch_rules.h.
+// Each wave computes its own slots only (with 512 threads and two interior points
+// each, every thread also carries one point of each ring, repeated on the threads
+// beyond a ring's count), and four waves per SIMD hide more of the per-plane chain
+// (LDS reads, arithmetic, LDS writes, three times, and one barrier) than two.  With
+// 128 VGPRs, r's z-column is read from the ring (in registers the kernel spills).
+// The sums run in the same order as in the one- and two-step passes, whose results
+// it equals bit for bit.
+// Measured on MI355X, us per leapfrog step, 512 threads (two interior points per
+// thread, r's z-column in registers) / this kernel: 224^3 24.75 / 22.54, 256^3 35.86 /
+// 33.94, 288^3 67.52 / 63.42, 352^3 106.61 / 98.83, 384^3 123.85 / 121.33, 448^3
+// 212.06 / 201.31, 512^3 272.69 / 264.87; the outer-ring waves then dropped their
+// p(k-1) and k' loads: 33.5 at 256^3, 119.0 at 384^3.  Variants (256^3 / 384^3): the
+// ring's stage-2 reads behind a wait of their own 34.6 at 256^3; roles grouped by kind
+// (waves 0-4, 5-9, 10-15) 33.9 / 124.2; the outer-ring waves issuing all three stages'
+// reads at once 34.6 / 123.3; k' of the ring's stage 2 loaded again instead of kept
+// 35.8 / 128.3; stage 2's reads issued with stage 1's (spills) 42.0 / 151.1.
 template <bool FIRSTSTEP>
 __global__ void __launch_bounds__(1024, 1)
 wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, const f32x2 *kap, int nx, int ny,
                 int nz, int zchunk, int tiles_x, int tiles_y, int n_tiles, int xy_fastest)
 {
   using T = f32x2;
-  constexpr int NTH = 1024, BX = 64, BY = 16;
+  using L = Wide3;
+  constexpr int NTH = L::NTH, BX = L::BX, BY = L::BY;
   constexpr int NX = NbrX<T>::N;              // 2: the elements at x - 1 and x + 1
-  constexpr int E = NX / 2;
-  constexpr int XH = 3 * E;
-  constexpr int KX = BX + 2 * XH, KY = BY + 12;
-  constexpr int AX = BX + 4 * E, AY = BY + 8;
-  constexpr int CX = BX + 2 * E, CY = BY + 4;
-  constexpr int N2 = CX * CY - BX * BY;       // ring of stage 2 (296)
-  constexpr int N1 = AX * AY - CX * CY;       // ring of stage 1 (312)
-  constexpr int NR = KX * KY - AX * AY;       // outer ring of the p(k) plane (328)
+  constexpr int E = L::E, XH = L::XH;
+  constexpr int KX = L::KX, AX = L::AX, CX = L::CX;
   constexpr int NB = NX + 4;
   constexpr int NB2 = NB + 4;
-  static_assert(BX * BY == NTH && N2 <= 5 * 64 && N1 <= 5 * 64 && NR <= 6 * 64, "slot layout");
-  constexpr int KP = KY * KX, QP = AY * AX, RP = CY * CX;
-  // p(k) planes and q ring with 2 rows of headroom in front (see the LDS bases below)
-  __shared__ T lkm[2 * KX + 2 * KP];
-  __shared__ T lqm[2 * AX + 5 * QP];
-  __shared__ T lr[5][RP];
-  T *const lk0 = lkm + 2 * KX, *const lq0 = lqm + 2 * AX;
+  static_assert(NX == 2 * E && BX * BY == NTH && L::N2 <= 5 * 64 && L::N1 <= 5 * 64 && L::NR <= 6 * 64,
+                "slot layout");
+  constexpr int KP = L::KP, QP = L::QP, RP = L::RP;
+  __shared__ T lk[L::LK];                     // p(k) planes (double-buffered), with headroom
+  __shared__ T lq[L::LQ];                     // q ring, with headroom
+  __shared__ T lr[L::LR];                     // r ring
 
   const int b = blockIdx.x;
   const int per_xcd = (n_tiles + 7) / 8;
@@ -1465,11 +1439,19 @@ wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, c
   const size_t plane = (size_t)nx * ny;
   const int zstart = zbeg - 4;
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  constexpr unsigned long long ROLES = wide_pack(false), RIDX = wide_pack(true);
-  const int role = (int)((ROLES >> (4 * wv)) & 15);
-  const int ridx = (int)((RIDX >> (4 * wv)) & 15);
+  // the wave's ring role and its rank among the waves of that role, from constants
+  constexpr unsigned long long ROLES = [] {
+    unsigned long long r = 0;
+    for (int w = 0; w < 16; ++w) r |= (unsigned long long)wide3_role(w) << (4 * w);
+    return r;
+  }();
+  constexpr unsigned long long RANKS = [] {
+    unsigned long long r = 0;
+    for (int w = 0; w < 16; ++w) r |= (unsigned long long)wide3_role_index(w) << (4 * w);
+    return r;
+  }();
+  const int role = (int)((ROLES >> (4 * wv)) & 15), rank = (int)((RANKS >> (4 * wv)) & 15);
   const bool ring1 = role >= 1, ring2 = role == 2;   // the ring point computes stage 1 / stage 2
 
   const unsigned plane_bytes = (unsigned)(plane * sizeof(T));
@@ -1481,32 +1463,9 @@ wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, c
     return ing ? (unsigned)((gy * nx + gx) * sizeof(T)) : 0xFFFFFFF0u;
   };
 
-  // interior point: row wv of the tile, element lane
-  const int ilx = XH + lane, ily = 6 + wv;
-  // ring point: ring of width E (x) and 2 rows (y) just outside a region of rw x rh
-  // elements whose origin sits at (inset E, 2 inset) in the p(k) plane
-  int rlx, rly;
-  {
-    const int rwid = role == 2 ? CX : (role == 1 ? AX : KX);
-    const int rh = role == 2 ? CY : (role == 1 ? AY : KY);
-    const int n = role == 2 ? N2 : (role == 1 ? N1 : NR);
-    const int inset = role;
-    int u = ridx * 64 + lane;
-    u = u < n ? u : u - n;                    // lanes beyond the count repeat a point of the ring
-    int sx, sy;
-    if (u < 4 * rwid) {
-      const int r = u / rwid;
-      sy = r < 2 ? r : rh - 4 + r;
-      sx = u - r * rwid;
-    } else {
-      const int j = u - 4 * rwid;
-      sy = 2 + j / (2 * E);
-      const int cc = j % (2 * E);
-      sx = cc < E ? cc : rwid - 2 * E + cc;
-    }
-    rlx = sx + inset * E;
-    rly = sy + 2 * inset;
-  }
+  // interior point (row wv of the tile, element lane) and ring point of the thread
+  const PlanePoint ip = wide3_interior(tid), rp = wide3_ring_point(role, rank, tid & 63);
+  const int ilx = ip.lx, ily = ip.ly, rlx = rp.lx, rly = rp.ly;
   const unsigned boffI = grid_off(ilx, ily), boffR = grid_off(rlx, rly);
 
   T wI[5], wR[5], kwI[5], kwR[5];
@@ -1524,34 +1483,34 @@ wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, c
     kwR[q] = T(0);
   }
 
-  // LDS bases kept opaque (base + immediate offset per access, as in wave_step3_split),
-  // each 2 rows above its point, the lowest row a stage reads; the headroom in front
-  // of lk0 and lq0 keeps that inside the arrays for ring points near the top that only
-  // write there (the outer ring's p(k), stage 1's ring's q)
+  // LDS bases (wide3_bases) kept opaque, so that every access is base + immediate
+  // offset, as in wave_step3_split
   using LP = __attribute__((address_space(3))) T *;
   auto opaque = [](T *p) {
     LP q = (LP)p;
     asm volatile("" : "+v"(q));
     return q;
   };
-  const int ilofs = ily * KX + ilx, iqrd = (ily - 2) * AX + (ilx - E), irrd = (ily - 4) * CX + (ilx - 2 * E);
-  const int rlofs = rly * KX + rlx, rqrd = (rly - 2) * AX + (rlx - E);
-  const int rrrd = ring2 ? (rly - 4) * CX + (rlx - 2 * E) : 0;
-  const LP kbI = opaque(&lk0[ilofs - 2 * KX]), qbI = opaque(&lq0[iqrd - 2 * AX]), rbI = opaque(&lr[0][irrd - 2 * CX]);
-  const LP kbR = opaque(&lk0[rlofs - 2 * KX]), qbR = opaque(&lq0[ring1 ? rqrd - 2 * AX : 0]);
-  const LP rwrR = opaque(&lr[0][rrrd]);
+  const Wide3Bases lb = wide3_bases_of(ip, rp, role);
+  const LP kbI = opaque(&lk[lb.kI]), qbI = opaque(&lq[lb.qI]), rbI = opaque(&lr[lb.rI]);
+  const LP kbR = opaque(&lk[lb.kR]), qbR = opaque(&lq[lb.qR]), rwrR = opaque(&lr[lb.rR]);
 
   T nwI, npvI, nkvI, nwR, npvR, nkvR;
   auto fetch = [&](int zf) {
-    const unsigned bw = plane_range(zf + 2), bc = plane_range(zf), bcr = ring1 ? bc : 0u;
+    const unsigned bw = plane_range(zf + 2), bc = plane_range(zf);
     const T *pw = plane_at(pk, zf + 2), *pp = FIRSTSTEP ? pk : plane_at(pm1, zf);
     const T *pkap = plane_at(kap, zf);
     nwI = ld_ranged(pw, bw, boffI);
     if constexpr (!FIRSTSTEP) npvI = ld_ranged(pp, bc, boffI);
     nkvI = ld_ranged(pkap, bc, boffI);
     nwR = ld_ranged(pw, bw, boffR);
-    if constexpr (!FIRSTSTEP) npvR = ld_ranged(pp, bcr, boffR);
-    nkvR = ld_ranged(pkap, bcr, boffR);
+    if (ring1) {                              // outer-ring waves need neither
+      if constexpr (!FIRSTSTEP) npvR = ld_ranged(pp, bc, boffR);
+      nkvR = ld_ranged(pkap, bc, boffR);
+    } else {
+      npvR = T(0);
+      nkvR = T(0);
+    }
   };
   fetch(zstart);
 

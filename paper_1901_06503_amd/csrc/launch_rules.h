@@ -1,5 +1,6 @@
 // Launch-shape rules of the leapfrog stencil kernels: tile height and z-chunk of
-// the one-step kernel, z-chunk and tile width of the two-step kernel.  Plain host
+// the one-step kernel, z-chunk and tile width of the two-step kernel, and the slot
+// layout of the 1024-thread three-step kernel.  Plain host
 // arithmetic on the grid, the element size, the device's compute units and the
 // work-groups a unit holds at once (the callers query those from the runtime);
 // nothing here touches the device, so the rules are testable on any host.
@@ -171,6 +172,116 @@ inline bool pair_wide_better(const PairShape &narrow, const PairShape &wide)
 inline bool pair_x_pairs(bool wide, int nx)
 {
   return wide && nx % 2 == 0;
+}
+
+// ------------------------------------------- three steps per pass, 1024 threads
+
+// Slot layout of wave_step3_wide (pairs of FP32 points, one 8-byte element per pair:
+// one leapfrog step reaches one element in x and two rows in y).  Coordinates are
+// (lx, ly) in the tile's p(k) plane with its halo, KX x KY elements; stage 1 (q)
+// covers AX x AY of it from (1, 2), stage 2 (r) CX x CY from (2, 4), stage 3 (o)
+// the BX x BY tile from (3, 6).  Constant expressions shared by the kernel and the
+// host-side check of the layout.
+struct Wide3 {
+  static constexpr int NTH = 1024, BX = 64, BY = 16, E = 1, XH = 3 * E;
+  static constexpr int KX = BX + 2 * XH, KY = BY + 12;
+  static constexpr int AX = BX + 4 * E, AY = BY + 8;
+  static constexpr int CX = BX + 2 * E, CY = BY + 4;
+  static constexpr int N2 = CX * CY - BX * BY;   // ring of stage 2 (296 points)
+  static constexpr int N1 = AX * AY - CX * CY;   // ring of stage 1 (312)
+  static constexpr int NR = KX * KY - AX * AY;   // outer ring of the p(k) plane (328)
+  static constexpr int KP = KY * KX, QP = AY * AX, RP = CY * CX;
+  // LDS arrays in elements: two p(k) planes and a 5-plane q ring, each with two rows of
+  // headroom in front, and a 5-plane r ring
+  static constexpr int KPAD = 2 * KX, QPAD = 2 * AX;
+  static constexpr int LK = KPAD + 2 * KP, LQ = QPAD + 5 * QP, LR = 5 * RP;
+};
+
+// Ring role of wave w (16 waves): 2 the ring of stage 2 (stages 1 and 2), 1 the ring
+// of stage 1 (stage 1), 0 the outer ring of the p(k) plane (loaded into LDS only).
+// Five, five and six waves, ordered so that with wave w on SIMD w % 4 the SIMDs carry
+// 4, 4, 4 and 3 ring stages per plane.
+constexpr int wide3_role(int w)
+{
+  constexpr int r[16] = {2, 2, 2, 1, 2, 2, 1, 1, 0, 0, 1, 1, 0, 0, 0, 0};
+  return r[w];
+}
+
+// Rank of wave w among the waves of its role.
+constexpr int wide3_role_index(int w)
+{
+  int n = 0;
+  for (int v = 0; v < w; ++v) n += wide3_role(v) == wide3_role(w);
+  return n;
+}
+
+struct PlanePoint {
+  int lx, ly;
+};
+
+// Thread tid's interior point: tile row tid / 64, element tid % 64.
+constexpr PlanePoint wide3_interior(int tid)
+{
+  return {Wide3::XH + tid % 64, 6 + tid / 64};
+}
+
+// The ring point of lane `lane` of the rank-th wave of ring role `role`: point u =
+// rank x 64 + lane of the ring of width E (x) and 2 rows (y) around the region of
+// that role (rw x rh elements at (role E, 2 role)); lanes beyond the ring's count
+// repeat a point of it.
+constexpr PlanePoint wide3_ring_point(int role, int rank, int lane)
+{
+  const int rw = role == 2 ? Wide3::CX : (role == 1 ? Wide3::AX : Wide3::KX);
+  const int rh = role == 2 ? Wide3::CY : (role == 1 ? Wide3::AY : Wide3::KY);
+  const int n = role == 2 ? Wide3::N2 : (role == 1 ? Wide3::N1 : Wide3::NR);
+  constexpr int E = Wide3::E;
+  int u = rank * 64 + lane;
+  u = u < n ? u : u - n;
+  int sx = 0, sy = 0;
+  if (u < 4 * rw) {                      // rows 0, 1, rh - 2, rh - 1, full width
+    const int r = u / rw;
+    sy = r < 2 ? r : rh - 4 + r;
+    sx = u - r * rw;
+  } else {                               // rows 2 .. rh - 3, the E columns on either side
+    const int j = u - 4 * rw;
+    sy = 2 + j / (2 * E);
+    const int cc = j % (2 * E);
+    sx = cc < E ? cc : rw - 2 * E + cc;
+  }
+  return {sx + role * E, sy + 2 * role};
+}
+
+// Thread tid's ring point.
+constexpr PlanePoint wide3_ring(int tid)
+{
+  return wide3_ring_point(wide3_role(tid / 64), wide3_role_index(tid / 64), tid % 64);
+}
+
+// LDS element indices, from the start of each array, of thread tid's slot bases: each
+// 2 rows above its point in the array's plane (the lowest row any stage reads; the
+// kernel adds the plane's offset, 2 rows and the neighbour's shift as immediates).
+// The headroom keeps this inside the arrays for the ring points near the top that only
+// write there (the outer ring's p(k), stage 1's ring's q).  The ring point's q base
+// serves rings with stage 1, its r base (at the point: it only writes r) the ring of
+// stage 2; elsewhere they are 0 and unused.
+struct Wide3Bases {
+  int kI, qI, rI, kR, qR, rR;
+};
+constexpr Wide3Bases wide3_bases_of(PlanePoint i, PlanePoint r, int role)
+{
+  using L = Wide3;
+  Wide3Bases b{};
+  b.kI = L::KPAD + (i.ly - 2) * L::KX + i.lx;
+  b.qI = L::QPAD + (i.ly - 4) * L::AX + (i.lx - L::E);
+  b.rI = (i.ly - 6) * L::CX + (i.lx - 2 * L::E);
+  b.kR = L::KPAD + (r.ly - 2) * L::KX + r.lx;
+  b.qR = role >= 1 ? L::QPAD + (r.ly - 4) * L::AX + (r.lx - L::E) : 0;
+  b.rR = role == 2 ? (r.ly - 4) * L::CX + (r.lx - 2 * L::E) : 0;
+  return b;
+}
+constexpr Wide3Bases wide3_bases(int tid)
+{
+  return wide3_bases_of(wide3_interior(tid), wide3_ring(tid), wide3_role(tid / 64));
 }
 
 }  // namespace ffpat

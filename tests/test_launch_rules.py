@@ -102,3 +102,18 @@ def test_one_step_tile_and_chunk(cli, key):
     nz, ny, nx, esz = key
     tx, ty, zc = _run(cli, "step", nx, ny, nz, esz)
     assert (tx, ty, zc) == (64,) + STEP[key]
+
+
+def test_three_step_1024_thread_slot_layout(cli):
+    """The slot layout of the 1024-thread three-step kernel (wide3_interior, wide3_ring,
+    wide3_role, wide3_bases): the 1024 interior points are the tile; the ring points of
+    each role are exactly the ring of that role (296 around stage 2's region, 312 around
+    stage 1's, 328 around the p(k) plane's inner part), so every point of the p(k) plane
+    has one kind of slot; every LDS access the kernel makes from those bases (p(k) planes
+    with both parities, the five slots of the q and r rings, the stencil's x and y
+    neighbours) stays inside its array with an immediate offset below 64 KiB and reads
+    or writes the intended element; and the ring stages per plane are spread 4, 4, 4, 3
+    over the four SIMDs."""
+    out = subprocess.run([cli, "wide3"], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.split() == ["ok", "1024", "296", "312", "328"]
