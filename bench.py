@@ -63,7 +63,7 @@ def parse():
                     help="--mode serve, policy shortest: seconds of waiting that offset a second of remaining work")
     ap.add_argument("--low-concurrency", type=int, default=1,
                     help="--mode serve, policy shortest: jobs advanced together while at most --backlog are waiting")
-    ap.add_argument("--backlog", type=int, default=3,
+    ap.add_argument("--backlog", type=int, default=5,
                     help="--mode serve, policy shortest: jobs in the system above which --concurrency applies")
     ap.add_argument("--serve-jobs", type=int, default=120,
                     help="--mode fb: jobs in the serving leg (the 120-job trace at 4 jobs/s: p50/p99 latency, "
@@ -193,7 +193,7 @@ def run_serve(args):
 
 
 def serve_summary(n_jobs, rate, iters, slots, concurrency, policy, fill_voxels, serial, seed, aging=1.0,
-                  low_concurrency=1, backlog=3):
+                  low_concurrency=1, backlog=5):
     import numpy as np
     import torch
     import paper_1901_06503_amd as ff
