@@ -1495,7 +1495,7 @@ wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, c
   const LP kbI = opaque(&lk[lb.kI]), qbI = opaque(&lq[lb.qI]), rbI = opaque(&lr[lb.rI]);
   const LP kbR = opaque(&lk[lb.kR]), qbR = opaque(&lq[lb.qR]), rwrR = opaque(&lr[lb.rR]);
 
-  T nwI, npvI, nkvI, nwR, npvR, nkvR;
+  T nwI, npvI, nkvI, nwR, npvR = T(0), nkvR = T(0);
   auto fetch = [&](int zf) {
     const unsigned bw = plane_range(zf + 2), bc = plane_range(zf);
     const T *pw = plane_at(pk, zf + 2), *pp = FIRSTSTEP ? pk : plane_at(pm1, zf);
@@ -1507,9 +1507,6 @@ wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, c
     if (ring1) {                              // outer-ring waves need neither
       if constexpr (!FIRSTSTEP) npvR = ld_ranged(pp, bc, boffR);
       nkvR = ld_ranged(pkap, bc, boffR);
-    } else {
-      npvR = T(0);
-      nkvR = T(0);
     }
   };
   fetch(zstart);
