@@ -89,6 +89,32 @@ def build_sanitized(jobs: int = 4) -> str:
     return lib
 
 
+def device_resource_report(src: str) -> dict:
+    """Compiles the device code of csrc/`src` for gfx950 with the library's flags and
+    returns the compiler's resource report per kernel: {mangled name: {field: value}},
+    fields as the compiler prints them ("VGPRs", "ScratchSize [bytes/lane]",
+    "Occupancy [waves/SIMD]", "LDS Size [bytes/block]", ...).  CPU only."""
+    import re
+    import tempfile
+    flags = [f for f in HIP_FLAGS if f != "-fPIC"]
+    with tempfile.TemporaryDirectory() as tmp:
+        cmd = [hipcc()] + flags + ["--offload-device-only", "-Rpass-analysis=kernel-resource-usage",
+                                   "-c", os.path.join(CSRC, src), "-o", os.path.join(tmp, "dev.o")]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compiling {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    report, cur = {}, None
+    for line in r.stderr.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = report.setdefault(m.group(1), {})
+            continue
+        m = re.search(r"remark:\s+(.+?): (\S+) \[-Rpass-analysis=kernel-resource-usage\]", line)
+        if m and cur is not None:
+            cur[m.group(1).strip()] = m.group(2)
+    return report
+
+
 def build(jobs: int = 4, verbose: bool = False) -> str:
     """Compiles every source (always, also when a library exists) and links
     libffpat.so and libffpat_probe.so."""
