@@ -65,6 +65,9 @@ def parse():
                     help="--mode serve, policy shortest: jobs advanced together while at most --backlog are waiting")
     ap.add_argument("--backlog", type=int, default=5,
                     help="--mode serve, policy shortest: jobs in the system above which --concurrency applies")
+    ap.add_argument("--join-voxels", type=int, default=128 ** 3,
+                    help="--mode serve and the serving leg, policy shortest: below --backlog, jobs of at most "
+                         "this many grid points run beside the oldest (0: none)")
     ap.add_argument("--serve-jobs", type=int, default=120,
                     help="--mode fb: jobs in the serving leg (the 120-job trace at 4 jobs/s: p50/p99 latency, "
                          "jobs/s against the serial baseline); 0 skips it")
@@ -189,11 +192,11 @@ def run_serve(args):
     same trace through the serial baseline and the continuous-batching scheduler."""
     print(json.dumps(serve_summary(args.jobs, args.rate, args.iters or 50, args.slots, args.concurrency,
                                    args.policy, args.fill_voxels, args.serial, args.seed, args.aging,
-                                   args.low_concurrency, args.backlog)), flush=True)
+                                   args.low_concurrency, args.backlog, args.join_voxels)), flush=True)
 
 
 def serve_summary(n_jobs, rate, iters, slots, concurrency, policy, fill_voxels, serial, seed, aging=1.0,
-                  low_concurrency=1, backlog=5):
+                  low_concurrency=1, backlog=5, join_voxels=128 ** 3):
     import numpy as np
     import torch
     import paper_1901_06503_amd as ff
@@ -226,13 +229,13 @@ def serve_summary(n_jobs, rate, iters, slots, concurrency, policy, fill_voxels, 
     log("continuous batching")
     with serving.Scheduler(hbm_budget=int(0.5 * free), max_active=slots, iters_per_turn=5,
                            concurrency=concurrency, policy=policy, fill_voxels=fill_voxels, aging=aging,
-                           low_concurrency=low_concurrency, backlog=backlog) as sched:
+                           low_concurrency=low_concurrency, backlog=backlog, join_voxels=join_voxels) as sched:
         mixed_jobs = sched.run(clone())
     mixed = serving.summary(mixed_jobs)
     log(f"scheduler: {mixed}")
     return {"mode": "serve", "jobs": n_jobs, "rate_per_s": rate, "iters": iters, "slots": slots, "policy": policy,
             "fill_voxels": fill_voxels, "concurrency": concurrency, "aging": aging,
-            "low_concurrency": low_concurrency, "backlog": backlog, "serial": base,
+            "low_concurrency": low_concurrency, "backlog": backlog, "join_voxels": join_voxels, "serial": base,
             "continuous_batching": mixed,
             "peak_active": sched.peak_active, "peak_running": sched.peak_running, "peak_bytes": sched.peak_bytes,
             "plans_created": sched.plans_created, "plans_reused": sched.plans_reused,
@@ -681,7 +684,7 @@ def main():
         try:
             sv = serve_summary(args.serve_jobs, 4.0, 50, args.slots, args.concurrency, args.policy,
                                args.fill_voxels, 1, args.seed, args.aging, args.low_concurrency,
-                               args.backlog)
+                               args.backlog, args.join_voxels)
             cb, se = sv["continuous_batching"], sv["serial"]
             serve = {"trace": f"{args.serve_jobs} jobs, Poisson 4 jobs/s, grids 64^3..256^3, 50 FB iterations each, "
                               f"FP32, policy {args.policy}",

@@ -16,8 +16,11 @@ policy:
   but only those that arrived less than a few of their remaining seconds
   earlier); `concurrency` applies while more than `backlog` jobs have arrived
   and are not finished; with fewer, `low_concurrency` (default 1: the oldest
-  job alone, as the serial baseline runs it, so that latency below the
-  device's capacity is the serial baseline's).
+  job, as the serial baseline runs it) joined by jobs of at most `join_voxels`
+  grid points (default 128^3), up to `concurrency` in all: small grids, whose
+  launches leave most of the device idle, need not wait behind a long job,
+  which they slow only a little (sharing the device with larger jobs slows the
+  long ones that set the tail).
 * "fill": arrival order; the oldest job always runs, and later ones join
   while the running jobs hold at most `fill_voxels` grid points together
   (small grids, whose kernels leave most of the device idle, share it; a
@@ -39,12 +42,14 @@ multi-step stencil kernels of a 192^3 or 256^3 job hold every compute unit while
 they run.  What remains is the 64^3 and 128^3 jobs, whose small launches leave the
 device mostly idle, running in the gaps of the others.  On the 120-job trace
 (grids 64^3..256^3, 50 iterations each, FP32), MI355X, "shortest" with concurrency
-3, aging 4, backlog 5: at 4 jobs/s, above the device's capacity for the mix (about
-3 jobs/s), 3.16 jobs/s against 2.96 serial (+7.1%), median latency 1.7 s against
-3.2 s, 99th percentile 5.1 s against 6.6 s; at 2 jobs/s (with a 6% slower FP32
-stencil) median 0.38 s against 0.37 s and 99th percentile 2.09 s against 2.08 s (with two at a time below the backlog:
-0.41 s and 2.25 s, the sharing slowing the long jobs; run one at a time always, the
-scheduler matches the serial baseline to 1%: 0.376 / 2.084 against 0.372 / 2.076).
+3, aging 4, backlog 5, small jobs (up to 128^3) joining below the backlog: at 4
+jobs/s, above the device's capacity for the mix (about 3 jobs/s), 3.20 jobs/s against
+2.97 serial (+8%), median latency 1.5 s against 3.1 s, 99th percentile 4.7 s against
+6.4 s; at 2 jobs/s median 0.358 s against 0.366 s, 99th percentile 1.82 s against
+1.85 s, mean 0.48 s against 0.53 s (without the joining: 0.373 / 1.855 s; with any
+two jobs at a time below the backlog, an earlier measurement: 0.41 s and 2.25 s
+against 0.37 / 2.08 serial, the sharing slowing the long jobs; run one at a time
+always, the scheduler matches the serial baseline to 1%).
 
 `run_serial` is the plain baseline: one `ffpat_reconstruct` at a time in
 arrival order.
@@ -140,14 +145,15 @@ class Scheduler:
     policy: "fill", "shortest" or "all" (see the module docstring); fill_voxels is
     the fill threshold; concurrency the number of jobs "shortest" advances while more
     than `backlog` jobs have arrived and are not finished, low_concurrency otherwise
-    (1: the oldest job alone, as the serial baseline would run it); aging the seconds
+    (1: the oldest job alone, as the serial baseline would run it), joined, up to
+    `concurrency` jobs, by jobs of at most `join_voxels` grid points; aging the seconds
     of waiting that offset a second of remaining work in "shortest".
     reuse_plans: keep finished jobs' plans for later jobs of the same geometry.
     """
 
     def __init__(self, hbm_budget: int, max_active: int = 8, iters_per_turn: int = 5, concurrency: int = 3,
                  policy: str = "shortest", fill_voxels: int = 192 ** 3, device="cuda", aging: float = 4.0,
-                 reuse_plans: bool = True, backlog: int = 5, low_concurrency: int = 1):
+                 reuse_plans: bool = True, backlog: int = 5, low_concurrency: int = 1, join_voxels: int = 128 ** 3):
         if policy not in ("fill", "shortest", "all"):
             raise ValueError(f"unknown policy {policy!r}")
         self.hbm_budget = int(hbm_budget)
@@ -159,6 +165,7 @@ class Scheduler:
         self.aging = float(aging)
         self.backlog = int(backlog)
         self.low_concurrency = max(1, int(low_concurrency))
+        self.join_voxels = int(join_voxels)
         self.reuse_plans = bool(reuse_plans)
         self._waiting = 0
         self.device = device
@@ -337,8 +344,11 @@ class Scheduler:
             prio = lambda a: (_remaining_work(a) / _POINT_UPDATES_PER_S - self.aging * (now - a.job.arrival),
                               a.job.arrival, a.job.job_id)
             rest = sorted(order[1:], key=prio)
-            conc = self.concurrency if self._waiting > self.backlog else min(self.low_concurrency, self.concurrency)
-            return [order[0]] + rest[:conc - 1]
+            if self._waiting > self.backlog:
+                return [order[0]] + rest[:self.concurrency - 1]
+            conc = min(self.low_concurrency, self.concurrency)
+            small = [a for a in rest[conc - 1:] if a.job.c.numel() <= self.join_voxels]
+            return [order[0]] + rest[:conc - 1] + small[:self.concurrency - conc]
         chosen, vox = [order[0]], order[0].job.c.numel()
         for a in order[1:]:
             if vox + a.job.c.numel() > self.fill_voxels:

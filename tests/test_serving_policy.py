@@ -83,7 +83,8 @@ def test_all_and_unknown_policy():
 
 
 def test_shortest_runs_more_jobs_only_under_a_backlog():
-    s = Scheduler(hbm_budget=1 << 30, policy="shortest", concurrency=3, backlog=3, aging=0.0, low_concurrency=2)
+    s = Scheduler(hbm_budget=1 << 30, policy="shortest", concurrency=3, backlog=3, aging=0.0, low_concurrency=2,
+                  join_voxels=0)
     act = [_active(1, 0.0, 256), _active(2, 0.1, 64), _active(3, 0.2, 128), _active(4, 0.3, 192)]
     s._waiting = 3                                         # few jobs in the system: two at a time
     assert _ids(s._choose(act)) == [1, 2]
@@ -91,13 +92,35 @@ def test_shortest_runs_more_jobs_only_under_a_backlog():
     assert _ids(s._choose(act)) == [1, 2, 3]
 
 
-def test_shortest_runs_the_oldest_alone_below_the_backlog_by_default():
-    # below the device's capacity the default runs jobs one at a time in arrival
-    # order, as the serial baseline does (sharing the device only slows the long jobs)
+def test_shortest_below_the_backlog_by_default():
+    # below the device's capacity the default runs the oldest job, as the serial
+    # baseline does, plus only jobs of at most 128^3 points (their small launches leave
+    # the device mostly idle; sharing it with larger jobs slows the long ones)
     s = Scheduler(hbm_budget=1 << 30, policy="shortest", aging=0.0)
-    assert s.backlog == 5 and s.low_concurrency == 1 and s.concurrency == 3
-    act = [_active(1, 0.0, 256), _active(2, 0.1, 64), _active(3, 0.2, 128), _active(4, 0.3, 192)]
+    assert s.backlog == 5 and s.low_concurrency == 1 and s.concurrency == 3 and s.join_voxels == 128 ** 3
+    act = [_active(1, 0.0, 256), _active(2, 0.1, 192), _active(3, 0.2, 256), _active(4, 0.3, 192)]
     s._waiting = 5
     assert _ids(s._choose(act)) == [1]
     s._waiting = 6
-    assert _ids(s._choose(act)) == [1, 2, 3]
+    assert _ids(s._choose(act)) == [1, 2, 4]
+    mixed = [_active(1, 0.0, 256), _active(2, 0.1, 64), _active(3, 0.2, 128), _active(4, 0.3, 192)]
+    s._waiting = 5
+    assert _ids(s._choose(mixed)) == [1, 2, 3]
+
+
+def test_small_jobs_join_the_oldest_below_the_backlog():
+    # join_voxels: below the backlog, jobs of at most that many grid points run beside
+    # the oldest (up to `concurrency` jobs), in the policy's order; larger ones wait
+    s = Scheduler(hbm_budget=1 << 30, policy="shortest", aging=0.0, join_voxels=128 ** 3)
+    act = [_active(1, 0.0, 256), _active(2, 0.1, 192), _active(3, 0.2, 128), _active(4, 0.3, 64),
+           _active(5, 0.4, 64)]
+    s._waiting = 5
+    assert _ids(s._choose(act)) == [1, 4, 5]              # the two 64^3 jobs: least remaining work
+    s._waiting = 6                                         # above the backlog: unchanged rule
+    assert _ids(s._choose(act)) == [1, 4, 5]
+    s.join_voxels = 0
+    s._waiting = 5
+    assert _ids(s._choose(act)) == [1]
+    s.join_voxels = 128 ** 3
+    big_only = [_active(1, 0.0, 256), _active(2, 0.1, 192)]
+    assert _ids(s._choose(big_only)) == [1]
