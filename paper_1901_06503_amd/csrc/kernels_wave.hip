@@ -1960,16 +1960,20 @@ static PairShape triple_shape(const Dims &d, const BlockedConfig &cfg)
     return e == hipSuccess ? n : 0;
   }();
   const int cus = device_cus();
-  return pair_shape_for(d.nx, d.ny, d.nz, 64, 16, occ > 0 ? occ : 1, cus > 0 ? cus : 256, true, cfg.zchunk3);
+  return pair_shape_for(d.nx, d.ny, d.nz, 64, 16, occ > 0 ? occ : 1, cus > 0 ? cus : 256, true, cfg.zchunk3,
+                        kTripleZmin);
 }
 
 // Where three steps per pass run: wherever the two-step pass would take
-// wave_step2_split (FP32 as pairs of points, FP64 with the 64 x 16 tile).
+// wave_step2_split (FP32 as pairs of points, FP64 with the 64 x 16 tile), and in FP32
+// also on the grids of wide3_grid_ok where the two-step rule keeps the 64-point tile
+// (unless pairs or the 128-point tile are switched off).
 template <typename T>
 static bool triple_applies(const Dims &d, const BlockedConfig &cfg, bool aligned)
 {
   if (!cfg.split || cfg.triple == 0 || d.ndim != 3) return false;
-  if constexpr (sizeof(T) == 4) return aligned && pair_x2<T>(d, cfg);
+  if constexpr (sizeof(T) == 4)
+    return aligned && (pair_x2<T>(d, cfg) || (cfg.x2 != 0 && cfg.bx2 != 64 && wide3_grid_ok(d.nx, d.ny, d.nz)));
   else return pair_variant<T>(d, cfg) == PAIR_RY4_T512;
 }
 

@@ -63,10 +63,10 @@ inline long pair_rounds(long groups, long resident)
 // 128-wide and 40..64 FP64, at 320^3..512^3); its picks, e.g. 128-wide FP32 384^3
 // 28 planes 152.1 us (32: 163.1), FP64 384^3 55 planes 274.2 (64: 296.6), 448^3 50
 // planes 446.0 (64: 455.4); 64 at 320^3 and 512^3.
-inline int pair_zchunk(int nz, long xy, long resident, int per_cu, int zmax)
+inline int pair_zchunk(int nz, long xy, long resident, int per_cu, int zmax, int zmin = 8)
 {
   if (xy < 1) xy = 1;
-  const int zlo = nz < 8 ? nz : 8, zhi = nz < zmax ? nz : zmax;
+  const int zlo = nz < zmin ? nz : zmin, zhi = nz < zmax ? nz : zmax;
   const long fit = resident / xy;
   if (fit >= 1) {
     const long zc = (nz + fit - 1) / fit;
@@ -107,7 +107,8 @@ struct PairShape {
 };
 
 // zchunk > 0 overrides the chunk rule (clamped to nz).
-inline PairShape pair_shape_for(int nx, int ny, int nz, int bx, int by, int per_cu, int cus, bool f64, int zchunk)
+inline PairShape pair_shape_for(int nx, int ny, int nz, int bx, int by, int per_cu, int cus, bool f64, int zchunk,
+                                int zmin = 8)
 {
   PairShape p;
   p.bx = bx;
@@ -117,7 +118,7 @@ inline PairShape pair_shape_for(int nx, int ny, int nz, int bx, int by, int per_
   p.per_cu = per_cu;
   p.cus = cus;
   if (zchunk <= 0)
-    zchunk = pair_zchunk(nz, (long)p.tiles_x * p.tiles_y, (long)cus * per_cu, per_cu, pair_zmax(f64, per_cu));
+    zchunk = pair_zchunk(nz, (long)p.tiles_x * p.tiles_y, (long)cus * per_cu, per_cu, pair_zmax(f64, per_cu), zmin);
   if (zchunk > nz) zchunk = nz;
   p.zchunk = zchunk;
   p.n_tiles = p.tiles_x * p.tiles_y * ((nz + zchunk - 1) / zchunk);
@@ -175,6 +176,28 @@ inline bool pair_x_pairs(bool wide, int nx)
 }
 
 // ------------------------------------------- three steps per pass, 1024 threads
+
+// FP32 grids that take three steps per pass over pairs of points (the 128 x 16 point
+// tile) also where the two-step rule keeps the 64-point tile or one step per pass:
+// even nx of at least 96 points whose pairs fill at least 60% of the tiles' width, ny
+// of at least 64, at least 96^3 points.  Measured on MI355X, cubes, us per leapfrog
+// step, the previous rule / three steps per pass: 96^3 8.15 (one step) / 6.76, 112^3
+// 9.27 (one step) / 7.10, 128^3 9.48 / 8.05, 160^3 14.56 / 14.19, 192^3 18.98 / 18.55,
+// 320^3 85.6 / 76.2; 64^3 4.45 (one step) / 5.7 at best, so smaller grids keep theirs.
+inline bool wide3_grid_ok(int nx, int ny, int nz)
+{
+  if (nx % 2 != 0 || nx < 96 || ny < 64) return false;
+  if ((long long)nx * ny * nz < 96LL * 96 * 96) return false;
+  const int pairs = nx / 2, tiles = (pairs + 63) / 64;
+  return 5 * pairs >= 3 * 64 * tiles;
+}
+
+// Shortest z-chunk of the three-step kernel where one round of groups covers the grid
+// (a group marches its chunk plus 8 planes).  Measured on MI355X, us per leapfrog step:
+// 128^3 4 planes 8.05, 5 8.07, 6 8.30, 8 9.16 (half the compute units idle); 96^3 3
+// planes 6.76, 4 7.24, 6 8.10; 112^3 4 planes 7.10, 6 7.98.
+constexpr int kTripleZmin = 3;
+
 
 // Slot layout of wave_step3_wide (pairs of FP32 points, one 8-byte element per pair:
 // one leapfrog step reaches one element in x and two rows in y).  Coordinates are

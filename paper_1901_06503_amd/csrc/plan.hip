@@ -943,11 +943,14 @@ int ffpat_plan_create(const ffpat_geom *geom, const void *c_dev, void *stream, f
   {
     const size_t esz = r.dtype == FFPAT_F64 ? 8 : 4;
     const bool forced = r.flags & (FFPAT_PLAN_TWO_STEP | FFPAT_PLAN_THREE_STEP);
-    P->use_pairs = P->stencil == STENCIL_BLOCKED && wave_pairs_fit(r.d, esz) &&
-                   (forced || (!(r.flags & FFPAT_PLAN_SINGLE_STEP) && wave_pairs_preferred(r.d, esz)));
     const bool triples = esz == 8 ? wave_triples_available<double>(r.d) : wave_triples_available<float>(r.d);
-    P->use_triples = P->use_pairs && triples &&
-                     ((r.flags & FFPAT_PLAN_THREE_STEP) || (!forced && wave_triples_preferred(r.d, esz)));
+    // three steps per pass where preferred, also on grids small enough for one step
+    // per pass otherwise (multi-step passes imply use_pairs, for the remainders)
+    const bool triples_preferred = triples && !forced && wave_triples_preferred(r.d, esz);
+    P->use_pairs = P->stencil == STENCIL_BLOCKED && wave_pairs_fit(r.d, esz) &&
+                   (forced || (!(r.flags & FFPAT_PLAN_SINGLE_STEP) &&
+                               (wave_pairs_preferred(r.d, esz) || triples_preferred)));
+    P->use_triples = P->use_pairs && triples && ((r.flags & FFPAT_PLAN_THREE_STEP) || triples_preferred);
   }
   P->nvox = r.d.nvox();
   P->ndat = (size_t)r.n_angles * r.d.nz * r.ns;

@@ -143,6 +143,15 @@ int main(int argc, char **argv)
     printf("%d %d %d %d %d\n", p.bx, p.by, p.zchunk, p.n_tiles, pairs);
     return 0;
   }
-  fprintf(stderr, "usage: launch_rules_cli pair nx ny nz esz cus per_cu_narrow per_cu_wide | step nx ny nz esz | wide3\n");
+  if (argc >= 6 && !strcmp(argv[1], "triple")) {
+    // FP32 three-step pass over pairs of points: tile width in points, height, chunk,
+    // groups, and whether the grid takes it where the two-step rule keeps 64 points
+    const int nx = atoi(argv[2]), ny = atoi(argv[3]), nz = atoi(argv[4]), cus = atoi(argv[5]);
+    const ffpat::PairShape p = ffpat::pair_shape_for(nx / 2, ny, nz, 64, 16, 1, cus, true, 0, ffpat::kTripleZmin);
+    printf("%d %d %d %d %d\n", 2 * p.bx, p.by, p.zchunk, p.n_tiles, ffpat::wide3_grid_ok(nx, ny, nz) ? 1 : 0);
+    return 0;
+  }
+  fprintf(stderr, "usage: launch_rules_cli pair nx ny nz esz cus per_cu_narrow per_cu_wide | step nx ny nz esz | "
+                  "triple nx ny nz cus | wide3\n");
   return 2;
 }

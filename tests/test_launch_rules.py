@@ -117,3 +117,31 @@ def test_three_step_1024_thread_slot_layout(cli):
     out = subprocess.run([cli, "wide3"], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.split() == ["ok", "1024", "296", "312", "328"]
+
+
+# (nz, ny, nx): planes per group of the FP32 three-step pass (128 x 16 point tile) on
+# 256 compute units, and whether the grid takes it where the two-step rule keeps the
+# 64-point tile or one step per pass
+TRIPLE_FP32 = {
+    (96, 96, 96): (3, 1), (112, 112, 112): (4, 1), (128, 128, 128): (4, 1), (160, 160, 160): (14, 1),
+    (192, 192, 192): (20, 1), (224, 224, 224): (25, 1), (256, 256, 256): (32, 1), (320, 320, 320): (40, 1),
+    (384, 384, 384): (55, 1), (512, 512, 512): (64, 1),
+    (64, 64, 64): (3, 0),            # too small: one step per pass stays faster
+    (130, 130, 130): (10, 0),        # 65 pairs in two 64-pair tiles: half the width idle
+    (40, 250, 250): (5, 1),
+}
+
+
+@pytest.mark.parametrize("shape", sorted(TRIPLE_FP32))
+def test_three_step_chunk_and_grid_rule(cli, shape):
+    nz, ny, nx = shape
+    bx, by, zc, groups, ok = _run(cli, "triple", nx, ny, nz, 256)
+    assert (bx, by) == (128, 16) and (zc, ok) == TRIPLE_FP32[shape]
+    assert groups <= 256 or zc >= 8     # one round of groups where chunks of 3+ planes allow it
+
+
+def test_three_step_grid_rule_edges(cli):
+    assert _run(cli, "triple", 97, 128, 128, 256)[4] == 0    # odd nx: no pairs of points
+    assert _run(cli, "triple", 128, 60, 256, 256)[4] == 0    # ny below 64
+    assert _run(cli, "triple", 94, 128, 128, 256)[4] == 0    # nx below 96
+    assert _run(cli, "triple", 128, 128, 50, 256)[4] == 0    # fewer than 96^3 points
