@@ -43,13 +43,17 @@ they run.  What remains is the 64^3 and 128^3 jobs, whose small launches leave t
 device mostly idle, running in the gaps of the others.  On the 120-job trace
 (grids 64^3..256^3, 50 iterations each, FP32), MI355X, "shortest" with concurrency
 3, aging 4, backlog 5, small jobs (up to 128^3) joining below the backlog: at 4
-jobs/s, above the device's capacity for the mix (about 3 jobs/s), 3.20 jobs/s against
-2.97 serial (+8%), median latency 1.5 s against 3.1 s, 99th percentile 4.7 s against
-6.4 s; at 2 jobs/s median 0.358 s against 0.366 s, 99th percentile 1.82 s against
-1.85 s, mean 0.48 s against 0.53 s (without the joining: 0.373 / 1.855 s; with any
-two jobs at a time below the backlog, an earlier measurement: 0.41 s and 2.25 s
-against 0.37 / 2.08 serial, the sharing slowing the long jobs; run one at a time
-always, the scheduler matches the serial baseline to 1%).
+jobs/s, above the device's capacity for the mix (about 3 jobs/s), 3.23 jobs/s against
+3.11 serial (+3.8%), median latency 1.17 s against 1.96 s, 99th percentile 4.2 s
+against 5.0 s; at 2 jobs/s median 0.331 s against 0.336 s, 99th percentile 1.78 s
+against 1.80 s, mean 0.45 s against 0.50 s.  Since the 128^3 and 192^3 jobs run three
+leapfrog steps per pass (launches that fill the device) the serial baseline is faster
+(2.97 jobs/s before) and leaves less idle device time to overlap (+8% before, with
+3.20 against 2.97 jobs/s).  Without the joining rule the 2 jobs/s latencies were the
+serial baseline's (0.373 / 1.855 s against 0.366 / 1.850 s, before that change); with
+any two jobs at a time below the backlog the long jobs that set the tail slow down
+(an earlier measurement: 0.41 / 2.25 s against 0.37 / 2.08 s serial); run one at a
+time always, the scheduler matches the serial baseline to 1%.
 
 `run_serial` is the plain baseline: one `ffpat_reconstruct` at a time in
 arrival order.
