@@ -11,7 +11,8 @@ adjoint's dividing last step alone), FP32 over pairs of x-adjacent points on rag
 grids (even nx, 128 x 16 tiles) and FP64 on ragged and degenerate grids (one voxel
 wide in x, y or z), several z-chunks and rounds of work-groups, caller buffers off
 8-byte alignment (the three-step kernel is then not taken), Algorithm 8 with
-captured graphs, the 256^3 workload, and the serving loop.
+captured graphs, the 256^3 workload, the serving loop, and the default plans of the
+96^3..160^3 grids that take three steps per pass with 3- to 14-plane chunks.
 """
 import numpy as np
 import pytest
@@ -212,3 +213,32 @@ def test_serving_mix_with_three_step_plans():
         assert a.step == b.step
         assert torch.equal(a.h, b.h)
         assert np.array_equal(np.array(a.objective), np.array(b.objective))
+
+
+# FP32 grids that take three steps per pass by default where the two-step rule keeps
+# the 64-point tile or one step per pass, with the z-chunk the plan picks on 256
+# compute units (one round of groups: 3 or 4 planes up to 128^3)
+DEFAULT_MID = [((96, 96, 96), 3), ((112, 112, 112), 4), ((128, 128, 128), 4), ((160, 160, 160), 14)]
+
+
+@pytest.mark.parametrize("shape,zchunk", DEFAULT_MID, ids=["96", "112", "128", "160"])
+def test_default_plan_takes_three_steps_on_mid_grids(oracle, shape, zchunk):
+    """Default FP32 plans on these grids run wave_step3_wide with short z-chunks; their
+    solves equal those of a plan forced to two steps per pass bit for bit and the
+    oracle within the FP32 operator tolerance (n_t = 11: three passes of three steps,
+    then a pass of two; the adjoint ends with its dividing step alone)."""
+    import paper_1901_06503_amd as ff
+    _tag(shape, F32, "default three-step plan")
+    k = _with_nt(make_case(shape, 37, n_angles=3), F32, 11)
+    g = oracle_geom(oracle, k)
+    c, h = rounded(k["c"], F32), rounded(k["h"], F32)
+    with ff.Plan(to_dev(c, F32), k["dx"], k["T"], k["angles"], cfl=k["cfl"]) as P, _plan(k, F32, 2) as P2:
+        assert P.nt == 11 and P.steps_per_pass == 3 and P2.steps_per_pass == 2
+        if torch.cuda.get_device_properties(0).multi_processor_count == 256:
+            assert P.stencil_shape == (128, 16, zchunk)
+        hd = to_dev(h, F32)
+        f3, f2 = P.wave(hd), P2.wave(hd)
+        a3, a2 = P.wave_adjoint(hd), P2.wave_adjoint(hd)
+    assert torch.equal(f3, f2) and torch.equal(a3, a2)
+    assert rel_l2(to_np(f3), oracle.wave(g, c, h)) <= TOL_WAVE[F32]
+    assert rel_l2(to_np(a3), oracle.wave_T(g, c, h)) <= TOL_WAVE[F32]
