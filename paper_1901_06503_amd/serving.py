@@ -239,16 +239,19 @@ class Scheduler:
 
     def _finish(self, a, now):
         """Hands the iterate to the job (a copy on the job's stream, so that the slot's
-        buffer can serve the next job) and keeps or releases the slot."""
+        buffer can serve the next job) and keeps or releases the slot.  Returns an event
+        recorded after the copy: the job is done when it has completed."""
         import torch
         with torch.cuda.stream(a.stream):
             a.job.h = a.h.clone()
-        a.job.t_done = now
+        copied = torch.cuda.Event()
+        copied.record(a.stream)
         a.slot.last_used = now
         if self.reuse_plans:
             self._idle.append(a.slot)
         else:
             self._release(a.slot)
+        return copied
 
     def run(self, jobs):
         """Serves `jobs` (arrival times in seconds from now) and returns them finished."""
@@ -256,14 +259,18 @@ class Scheduler:
         from . import FfpatError
         pending = sorted(jobs, key=lambda j: j.arrival)
         active: list[_Active] = []
+        finishing = []                       # (job, event after its result's copy)
         t0 = time.perf_counter()
 
         def in_use():
             return sum(a.slot.bytes for a in active) + sum(s.bytes for s in self._idle)
 
-        while pending or active:
+        while pending or active or finishing:
             now = time.perf_counter() - t0
             self._now = now
+            for jf in [f for f in finishing if f[1].query()]:
+                jf[0].t_done = now
+                finishing.remove(jf)
             self._waiting = len(active) + sum(1 for j in pending if j.arrival <= now)
             progressed = False
             # admission: arrived, a free slot, and the footprint fits (a kept plan of the
@@ -307,7 +314,7 @@ class Scheduler:
                         a.job.status = "done"
                     except FfpatError as e:
                         a.job.status = f"failed: {e}"
-                    self._finish(a, time.perf_counter() - t0)
+                    finishing.append((a.job, self._finish(a, time.perf_counter() - t0)))
                     active.remove(a)
             chosen = self._choose(active)
             for a in chosen:
