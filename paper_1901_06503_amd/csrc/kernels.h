@@ -76,6 +76,12 @@ void wave_pair_shape(const Dims &d, int *tile_x, int *tile_y, int *zchunk);
 template <typename T>
 hipError_t launch_wave_triple(const Dims &d, const T *pm1, const T *pk, T *r, T *o, const T *kap, hipStream_t s,
                               bool first, bool *taken);
+// Three leapfrog steps in one pass whose third is divided by k' (the adjoint solve's
+// last three steps): r = p(k+2), o = p(k+3) / k'.  FP32 where launch_wave_triple runs
+// wave_step3_wide; *taken = false (nothing launched) otherwise.
+template <typename T>
+hipError_t launch_wave_triple_div(const Dims &d, const T *pm1, const T *pk, T *r, T *o, const T *kap, hipStream_t s,
+                                  bool *taken);
 // Two leapfrog steps in one pass whose second is divided by k' (the adjoint solve's
 // last two steps, STEP_LEAP then STEP_LEAP_DIV): q = p(k+1), o = p(k+2) / k'.  Only
 // where the two-step pass runs in wave_step2_split; *taken = false otherwise.

@@ -1403,7 +1403,7 @@ struct LdsFence<T, 20> {
 // waits in both arms gave the interior values two definitions, joined by 8-byte
 // register moves (34 per plane; with one wait after the branch, 4), 7% faster per
 // step at 128^3 and 1.5% at 256^3.
-template <bool FIRSTSTEP>
+template <bool FIRSTSTEP, bool DIV = false>
 __global__ void __launch_bounds__(1024, 1)
 wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, const f32x2 *kap, int nx, int ny,
                 int nz, int zchunk, int tiles_x, int tiles_y, int n_tiles, int xy_fastest)
@@ -1621,7 +1621,8 @@ wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, c
       nr[NB + 4] = rbI[Sm6 * RP + 2 * CX];
       LdsFence<T, NB + 5>::all(nr);
       const T S = stencil(nr, nr[NB + 1], nr[NB + 2], nr[NB + 3], nr[NB + 4], rI);
-      const T o = T(2) * nr[NB + 1] - nr[NB] + kwI[Sm4] * S;
+      T o = T(2) * nr[NB + 1] - nr[NB] + kwI[Sm4] * S;
+      if constexpr (DIV) o = o / kwI[Sm4];     // the adjoint solve's last step
       asm volatile("" : : "v"(o));
       st_ranged(o_out + (size_t)z2 * plane, plane_bytes, boffI, o);
     }
@@ -2018,6 +2019,32 @@ hipError_t launch_wave_triple(const Dims &d, const T *pm1, const T *pk, T *r_out
 }
 
 template <typename T>
+hipError_t launch_wave_triple_div(const Dims &d, const T *pm1, const T *pk, T *r_out, T *o_out, const T *kap,
+                                  hipStream_t s, bool *taken)
+{
+  *taken = false;
+  if constexpr (sizeof(T) == 4) {
+    const BlockedConfig cfg = blocked_config(d, sizeof(T));
+    const bool aligned = ((reinterpret_cast<uintptr_t>(pm1) | reinterpret_cast<uintptr_t>(pk) |
+                           reinterpret_cast<uintptr_t>(r_out) | reinterpret_cast<uintptr_t>(o_out) |
+                           reinterpret_cast<uintptr_t>(kap)) & 7) == 0;
+    if (!triple_applies<T>(d, cfg, aligned)) return hipSuccess;
+    const Dims e = x2_dims(d);
+    const PairShape p = triple_shape<f32x2>(e, cfg);
+    const int grid = ((p.n_tiles + 7) / 8) * 8;
+    wave_step3_wide<false, true><<<grid, 1024, 0, s>>>(
+        reinterpret_cast<const f32x2 *>(pm1), reinterpret_cast<const f32x2 *>(pk), reinterpret_cast<f32x2 *>(r_out),
+        reinterpret_cast<f32x2 *>(o_out), reinterpret_cast<const f32x2 *>(kap), e.nx, e.ny, e.nz, p.zchunk, p.tiles_x,
+        p.tiles_y, p.n_tiles, cfg.order);
+    *taken = true;
+    return hipGetLastError();
+  } else {
+    (void)d, (void)pm1, (void)pk, (void)r_out, (void)o_out, (void)kap, (void)s;
+    return hipSuccess;
+  }
+}
+
+template <typename T>
 hipError_t launch_wave_pair_div(const Dims &d, const T *pm1, const T *pk, T *q_out, T *o_out, const T *kap,
                                 hipStream_t s, bool *taken)
 {
@@ -2240,6 +2267,8 @@ hipError_t launch_c_stats(const Dims &d, const T *c, double *partials, int nbloc
                                             bool, bool *);                                                  \
   template hipError_t launch_wave_pair_div<T>(const Dims &, const T *, const T *, T *, T *, const T *,        \
                                               hipStream_t, bool *);                                         \
+  template hipError_t launch_wave_triple_div<T>(const Dims &, const T *, const T *, T *, T *, const T *,      \
+                                                hipStream_t, bool *);                                       \
   template bool wave_triple_shape<T>(const Dims &, int *, int *, int *);                                    \
   template bool wave_triples_available<T>(const Dims &);                                                   \
   template hipError_t launch_wave_step<T>(StencilKind, StepMode, const Dims &, const T *, const T *, T *,  \

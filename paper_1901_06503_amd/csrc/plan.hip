@@ -358,6 +358,14 @@ int leapfrog_chain(ffpat_plan *P, const T *pm1, bool pm1_owned, T *pk, int steps
       if (b != out) pool.give(b);   // buffers the kernel cannot take (alignment): smaller passes
       pool.give(a);
     }
+    if (P->use_triples && div_last && steps == 3 && pool.n >= 1) {
+      // the adjoint's last three steps in one pass, the third divided by k'
+      T *a = pool.take();
+      bool taken = false;
+      HIP_TRY(launch_wave_triple_div<T>(P->d, pm1, pk, a, out, kap, s, &taken));
+      pool.give(a);
+      if (taken) return FFPAT_OK;
+    }
     if (P->use_pairs && div_last && steps == 2 && pool.n >= 1) {
       // the adjoint's last two steps in one pass, the second divided by k'
       T *a = pool.take();

@@ -58,7 +58,8 @@ def _scratch(fields):
 
 
 def test_report_covers_the_hot_kernels(report):
-    for k in ("ffpat::wave_step3_wide<false>", "ffpat::wave_step3_wide<true>", "ffpat::project_lds_kernel<float, 8>",
+    for k in ("ffpat::wave_step3_wide<false, false>", "ffpat::wave_step3_wide<true, false>",
+              "ffpat::wave_step3_wide<false, true>", "ffpat::project_lds_kernel<float, 8>",
               "ffpat::backproject_lds_kernel<float, 16>", "ffpat::residual_ramp_win_kernel<float>",
               "ffpat::prox_l2_kernel<float>"):
         assert k in report, f"{k} missing from the compiler's report"
@@ -74,7 +75,8 @@ def test_no_kernel_spills_beyond_the_listed_exceptions(report):
 
 
 def test_the_three_step_pass_uses_no_scratch(report):
-    for variant in ("ffpat::wave_step3_wide<false>", "ffpat::wave_step3_wide<true>"):
+    for variant in ("ffpat::wave_step3_wide<false, false>", "ffpat::wave_step3_wide<true, false>",
+                    "ffpat::wave_step3_wide<false, true>"):
         f = report[variant]
         assert _scratch(f) == 0 and f.get("VGPRs Spill") == "0", f
         assert int(f["LDS Size [bytes/block]"]) <= 160 * 1024
