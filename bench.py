@@ -438,9 +438,11 @@ def time_wave(torch, plan, reps=3):
 def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
     """The dominant kernel of the path (the leapfrog stencil) and its average launch
     duration, measured live.  A forward W_T solve is n_t leapfrog steps: with one step
-    per pass, n_t launches of wave_step_blocked; with two steps per pass, one
-    first-step launch, M = (n_t - 1) // 2 launches of the two-step kernel and a single
-    step for an odd remainder; with three, M = 1 + (n_t - 3) // 3 three-step launches
+    per pass, n_t launches of wave_step_blocked; with two steps per pass in
+    wave_step2_split, M = 1 + (n_t - 2) // 2 launches of it (the first starts the solve
+    from p(0)) and a single step for an odd remainder, in the other two-step kernel one
+    first-step launch, M = (n_t - 1) // 2 two-step launches and a single step for an
+    odd remainder; with three, M = 1 + (n_t - 3) // 3 three-step launches
     (the first starts the solve from p(0)) and a single step or a pair for the
     remaining (n_t - 3) % 3 steps.  The k-step kernel's duration is
     (t(W_T) - t_first - t_rest) / M, with the single-step duration measured on a plan
@@ -452,6 +454,7 @@ def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
     (4 for one step; read p(k-1), p(k), k', write the last two levels: 5 for two or
     three steps)."""
     esz = 4 if dtype == torch.float32 else 8
+    f64 = dtype == torch.float64
     nvox = math.prod(plan.shape)
     t_w = time_wave(torch, plan)
     k = plan.steps_per_pass
@@ -466,11 +469,20 @@ def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
     if k == 3:
         with ff.Plan(c, dx, T, angles, stencil_steps=2) as p2:
             t_w2 = time_wave(torch, p2)
-            pairs2, singles2 = divmod(p2.nt - 1, 2)
-            t_pair = (t_w2 - (1 + singles2) * t_single) / pairs2
+            if multi_kernel_name(p2, f64) == "wave_step2_split" and p2.nt >= 2:
+                pairs2, singles2 = divmod(p2.nt - 2, 2)      # the first pass is a pair too
+                pairs2 += 1
+                t_pair = (t_w2 - singles2 * t_single) / pairs2
+            else:
+                pairs2, singles2 = divmod(p2.nt - 1, 2)
+                t_pair = (t_w2 - (1 + singles2) * t_single) / pairs2
     if k == 3 and plan.nt >= 3:
         # the solve's first pass is a three-step launch too (it starts from p(0))
         full, rest = divmod(plan.nt - 3, 3)
+        full, t_first = full + 1, 0.0
+    elif k == 2 and plan.nt >= 2 and multi_kernel_name(plan, f64) == "wave_step2_split":
+        # wave_step2_split starts the solve from p(0) as well
+        full, rest = divmod(plan.nt - 2, 2)
         full, t_first = full + 1, 0.0
     else:
         (full, rest), t_first = divmod(plan.nt - 1, k), t_single
@@ -479,7 +491,7 @@ def stencil_roofline(torch, ff, plan, c, dx, T, angles, dtype):
                    compulsory_bytes=4 * esz * nvox, updates_per_launch=1)
         return out
     t_rest = 0.0 if rest == 0 else (t_single if rest == 1 else t_pair)
-    out.update(kernel=multi_kernel_name(plan, dtype == torch.float64), t_launch=(t_w - t_first - t_rest) / full,
+    out.update(kernel=multi_kernel_name(plan, f64), t_launch=(t_w - t_first - t_rest) / full,
                alg_bytes=k * 4 * esz * nvox, compulsory_bytes=5 * esz * nvox, updates_per_launch=k,
                t_single_launch=t_single)
     if t_pair is not None:

@@ -76,6 +76,11 @@ void wave_pair_shape(const Dims &d, int *tile_x, int *tile_y, int *zchunk);
 template <typename T>
 hipError_t launch_wave_triple(const Dims &d, const T *pm1, const T *pk, T *r, T *o, const T *kap, hipStream_t s,
                               bool first, bool *taken);
+// The first two steps of a solve in one pass: q = p(1), o = p(2) from pk = p(0) with
+// zero initial velocity (STEP_FIRST, then STEP_LEAP).  Only where the two-step pass
+// runs in wave_step2_split; *taken = false (nothing launched) otherwise.
+template <typename T>
+hipError_t launch_wave_pair_first(const Dims &d, const T *pk, T *q, T *o, const T *kap, hipStream_t s, bool *taken);
 // Three leapfrog steps in one pass whose third is divided by k' (the adjoint solve's
 // last three steps): r = p(k+2), o = p(k+3) / k'.  FP32 where launch_wave_triple runs
 // wave_step3_wide; *taken = false (nothing launched) otherwise.

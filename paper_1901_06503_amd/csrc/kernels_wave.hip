@@ -637,8 +637,10 @@ __device__ __forceinline__ T ld_ranged(const T *base, unsigned bytes, unsigned b
 // exit tests to the next plane, which halves the prefetch distance: the FP32 pairs
 // kernel is 1% faster without, the FP64 kernel 7% faster with (without, it spills).
 // DIV: the second step is the adjoint solve's last one, divided by k' (the
-// single-step kernel's STEP_LEAP_DIV, the same expression).
-template <typename T, bool RESTRICT, bool DIV = false>
+// single-step kernel's STEP_LEAP_DIV, the same expression).  FIRSTSTEP: the pass
+// starts a solve from pk = p(0) with zero initial velocity (its first step is the
+// single-step kernel's STEP_FIRST expression; pm1 is not read) and yields p(1), p(2).
+template <typename T, bool RESTRICT, bool DIV = false, bool FIRSTSTEP = false>
 __global__ void __launch_bounds__(512, 1)
 wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> pm1,
                  std::conditional_t<RESTRICT, const T *__restrict__, const T *> pk,
@@ -765,7 +767,7 @@ wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
       nw[B][m] = ldb(bw, boff[m]);
-      npv[B][m] = ldb(bp, boff[m]);
+      npv[B][m] = FIRSTSTEP ? T(0) : ldb(bp, boff[m]);
       nkv[B][m] = ldb(bk, boff[m]);
     }
     nring[B] = ldb(br, roff);
@@ -819,7 +821,7 @@ wave_step2_split(std::conditional_t<RESTRICT, const T *__restrict__, const T *> 
       s1 += w[m][Sm1] + w[m][Sp1];
       s2 += w[m][Sm2] + w[m][Sp2];
       const T S = T(16) * s1 - s2 - T(90) * c0;
-      const T qn = T(2) * c0 - pv[m] + kv[m] * S;
+      const T qn = FIRSTSTEP ? c0 + T(0.5) * kv[m] * S : T(2) * c0 - pv[m] + kv[m] * S;
       qv[m] = (ing[m] && zs_in) ? qn : T(0);
     }
 #pragma unroll
@@ -2045,6 +2047,35 @@ hipError_t launch_wave_triple_div(const Dims &d, const T *pm1, const T *pk, T *r
 }
 
 template <typename T>
+hipError_t launch_wave_pair_first(const Dims &d, const T *pk, T *q_out, T *o_out, const T *kap, hipStream_t s,
+                                  bool *taken)
+{
+  const BlockedConfig cfg = blocked_config(d, sizeof(T));
+  *taken = false;
+  if (!cfg.split || d.ndim != 3) return hipSuccess;
+  if constexpr (sizeof(T) == 4) {
+    const bool aligned = ((reinterpret_cast<uintptr_t>(pk) | reinterpret_cast<uintptr_t>(q_out) |
+                           reinterpret_cast<uintptr_t>(o_out) | reinterpret_cast<uintptr_t>(kap)) & 7) == 0;
+    if (!aligned || !pair_x2<T>(d, cfg)) return hipSuccess;
+    const Dims e = x2_dims(d);
+    const PairShape p = pair_shape_split<f32x2>(e, cfg);
+    const int grid = ((p.n_tiles + 7) / 8) * 8;
+    const f32x2 *b = reinterpret_cast<const f32x2 *>(pk);
+    wave_step2_split<f32x2, false, false, true><<<grid, 512, 0, s>>>(
+        b, b, reinterpret_cast<f32x2 *>(q_out), reinterpret_cast<f32x2 *>(o_out),
+        reinterpret_cast<const f32x2 *>(kap), e.nx, e.ny, e.nz, p.zchunk, p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
+  } else {
+    if (pair_variant<T>(d, cfg) != PAIR_RY4_T512) return hipSuccess;
+    const PairShape p = pair_shape_split<T>(d, cfg);
+    const int grid = ((p.n_tiles + 7) / 8) * 8;
+    wave_step2_split<T, true, false, true><<<grid, 512, 0, s>>>(pk, pk, q_out, o_out, kap, d.nx, d.ny, d.nz,
+                                                                p.zchunk, p.tiles_x, p.tiles_y, p.n_tiles, cfg.order);
+  }
+  *taken = true;
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_wave_pair_div(const Dims &d, const T *pm1, const T *pk, T *q_out, T *o_out, const T *kap,
                                 hipStream_t s, bool *taken)
 {
@@ -2269,6 +2300,8 @@ hipError_t launch_c_stats(const Dims &d, const T *c, double *partials, int nbloc
                                               hipStream_t, bool *);                                         \
   template hipError_t launch_wave_triple_div<T>(const Dims &, const T *, const T *, T *, T *, const T *,      \
                                                 hipStream_t, bool *);                                       \
+  template hipError_t launch_wave_pair_first<T>(const Dims &, const T *, T *, T *, const T *, hipStream_t,    \
+                                                bool *);                                                    \
   template bool wave_triple_shape<T>(const Dims &, int *, int *, int *);                                    \
   template bool wave_triples_available<T>(const Dims &);                                                   \
   template hipError_t launch_wave_step<T>(StencilKind, StepMode, const Dims &, const T *, const T *, T *,  \

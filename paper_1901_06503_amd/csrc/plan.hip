@@ -422,6 +422,28 @@ int first_triple(ffpat_plan *P, const T *in, T *out, int after, Pool<T> &pool, T
   return FFPAT_OK;
 }
 
+// The first two steps of a solve from p(0) = in in one two-step pass, where the plan
+// runs two-step passes and at least `after` steps follow: p(1), p(2) into two volumes of
+// the pool (p(2) into `out` when nothing follows).  *done = false: not taken.
+template <typename T>
+int first_pair(ffpat_plan *P, const T *in, T *out, int after, Pool<T> &pool, T **p1, T **p2, bool *done,
+               hipStream_t s)
+{
+  *done = false;
+  if (!P->use_pairs || P->nt - 2 < after || pool.n < (P->nt == 2 ? 1 : 2)) return FFPAT_OK;
+  T *a = pool.take();
+  T *b = (P->nt == 2) ? out : pool.take();
+  HIP_TRY(launch_wave_pair_first<T>(P->d, in, a, b, static_cast<const T *>(P->kap()), s, done));
+  if (!*done) {
+    if (b != out) pool.give(b);
+    pool.give(a);
+    return FFPAT_OK;
+  }
+  *p1 = a;
+  *p2 = b;
+  return FFPAT_OK;
+}
+
 // out = W_T in (in read-only; pool: scratch volumes distinct from in and out)
 template <typename T>
 int wave_forward(ffpat_plan *P, const T *in, T *out, Pool<T> pool, hipStream_t s)
@@ -435,6 +457,9 @@ int wave_forward(ffpat_plan *P, const T *in, T *out, Pool<T> pool, hipStream_t s
   bool done = false;
   if (int rc = first_triple<T>(P, in, out, 0, pool, &p2, &p3, &done, s)) return rc;
   if (done) return P->nt == 3 ? FFPAT_OK : leapfrog_chain<T>(P, p2, true, p3, P->nt - 3, out, false, pool, s);
+  T *q1 = nullptr, *q2 = nullptr;
+  if (int rc = first_pair<T>(P, in, out, 0, pool, &q1, &q2, &done, s)) return rc;
+  if (done) return P->nt == 2 ? FFPAT_OK : leapfrog_chain<T>(P, q1, true, q2, P->nt - 2, out, false, pool, s);
   T *p1 = pool.take();
   HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, in, nullptr, p1, kap, s));
   return leapfrog_chain<T>(P, in, false, p1, P->nt - 1, out, false, pool, s);
@@ -456,6 +481,12 @@ int wave_adjoint_from_scaled(ffpat_plan *P, T *b, T *out, Pool<T> pool, hipStrea
   if (done) {
     pool.give(b);
     return leapfrog_chain<T>(P, p2, true, p3, P->nt - 3, out, true, pool, s);
+  }
+  T *q1 = nullptr, *q2 = nullptr;
+  if (int rc = first_pair<T>(P, b, out, 1, pool, &q1, &q2, &done, s)) return rc;
+  if (done) {
+    pool.give(b);
+    return leapfrog_chain<T>(P, q1, true, q2, P->nt - 2, out, true, pool, s);
   }
   T *p1 = pool.take();
   HIP_TRY(launch_wave_step<T>(P->stencil, STEP_FIRST, P->d, b, nullptr, p1, kap, s));
