@@ -2175,6 +2175,11 @@ bool wave_triples_available(const Dims &d)
 
 bool wave_triples_preferred(const Dims &d, size_t esz)
 {
+  static const bool single = [] {      // FFPAT_STENCIL_TB=0: one step per pass throughout
+    const char *e = getenv("FFPAT_STENCIL_TB");
+    return e && atoi(e) == 0;
+  }();
+  if (single) return false;
   const BlockedConfig cfg = blocked_config(d, esz);
   if (cfg.triple >= 0) return cfg.triple == 1;
   // FP32 (pairs of points), measured on MI355X, us per leapfrog step two / three steps
