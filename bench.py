@@ -195,6 +195,38 @@ def run_serve(args):
                                    args.low_concurrency, args.backlog, args.join_voxels)), flush=True)
 
 
+class BusySampler:
+    """Mean GPU activity (percent of time the graphics engine was busy, as the driver
+    reports it through torch.cuda.utilization) sampled every `period` seconds while
+    the block runs; None where the query is not available."""
+
+    def __init__(self, torch, period=0.1):
+        import threading
+        self.torch, self.period, self.samples = torch, period, []
+        self._stop = threading.Event()
+        self._thread = threading.Thread(target=self._run, daemon=True)
+
+    def _run(self):
+        while not self._stop.is_set():
+            try:
+                self.samples.append(float(self.torch.cuda.utilization()))
+            except Exception:             # no activity query on this system
+                return
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        self._thread.join()
+
+    @property
+    def mean(self):
+        return sum(self.samples) / len(self.samples) if self.samples else None
+
+
 def serve_summary(n_jobs, rate, iters, slots, concurrency, policy, fill_voxels, serial, seed, aging=1.0,
                   low_concurrency=1, backlog=5, join_voxels=128 ** 3):
     import numpy as np
@@ -223,15 +255,19 @@ def serve_summary(n_jobs, rate, iters, slots, concurrency, policy, fill_voxels, 
     base = None
     if serial:
         log("serial baseline")
-        base = serving.summary(serving.run_serial(clone()))
+        with BusySampler(torch) as busy:
+            base = serving.summary(serving.run_serial(clone()))
+        base["gpu_busy_mean_pct"] = busy.mean
         log(f"serial: {base}")
     free, total = torch.cuda.mem_get_info()
     log("continuous batching")
     with serving.Scheduler(hbm_budget=int(0.5 * free), max_active=slots, iters_per_turn=5,
                            concurrency=concurrency, policy=policy, fill_voxels=fill_voxels, aging=aging,
                            low_concurrency=low_concurrency, backlog=backlog, join_voxels=join_voxels) as sched:
-        mixed_jobs = sched.run(clone())
+        with BusySampler(torch) as busy:
+            mixed_jobs = sched.run(clone())
     mixed = serving.summary(mixed_jobs)
+    mixed["gpu_busy_mean_pct"] = busy.mean
     log(f"scheduler: {mixed}")
     return {"mode": "serve", "jobs": n_jobs, "rate_per_s": rate, "iters": iters, "slots": slots, "policy": policy,
             "fill_voxels": fill_voxels, "concurrency": concurrency, "aging": aging,
@@ -703,7 +739,9 @@ def main():
                      "throughput_gain": sv["throughput_gain"],
                      "latency_p50_s": cb["latency_p50_s"], "latency_p99_s": cb["latency_p99_s"],
                      "jobs_per_s": cb["jobs_per_s"], "serial_latency_p50_s": se["latency_p50_s"],
-                     "serial_latency_p99_s": se["latency_p99_s"], "serial_jobs_per_s": se["jobs_per_s"]}
+                     "serial_latency_p99_s": se["latency_p99_s"], "serial_jobs_per_s": se["jobs_per_s"],
+                     "gpu_busy_mean_pct": cb.get("gpu_busy_mean_pct"),
+                     "serial_gpu_busy_mean_pct": se.get("gpu_busy_mean_pct")}
         except Exception as e:          # the serving leg never costs the benchmark line
             serve = {"error": f"{type(e).__name__}: {e}"}
         log(f"serving {serve}")
