@@ -1408,7 +1408,7 @@ struct LdsFence<T, 20> {
 template <bool FIRSTSTEP, bool DIV = false>
 __global__ void __launch_bounds__(1024, 1)
 wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, const f32x2 *kap, int nx, int ny,
-                int nz, int zchunk, int tiles_x, int tiles_y, int n_tiles, int xy_fastest)
+                int nz, int zchunk, int tiles_x, int tiles_y, int n_tiles, int xy_fastest, int raise_outer)
 {
   using T = f32x2;
   using L = Wide3;
@@ -1459,6 +1459,16 @@ wave_step3_wide(const f32x2 *pm1, const f32x2 *pk, f32x2 *r_out, f32x2 *o_out, c
   }();
   const int role = (int)((ROLES >> (4 * wv)) & 15), rank = (int)((RANKS >> (4 * wv)) & 15);
   const bool ring1 = role >= 1, ring2 = role == 2;   // the ring point computes stage 1 / stage 2
+  // The outer-ring waves (p(k) loads and LDS writes only, besides their row of the tile)
+  // issue ahead of the others on their SIMD: the plane's halo reaches LDS sooner and the
+  // barrier opens earlier.  Measured on MI355X, us per leapfrog step, equal priorities /
+  // outer ring raised: 128^3 7.62 / 7.28, 256^3 32.2 / 30.5, 384^3 115.2 / 107.7; raising
+  // the waves of the stage-2 ring instead (the most work) gave nothing (31.9 at 256^3),
+  // raising every wave around its loads and the barrier 32.0, the rings of stages 1 and 2
+  // over the outer ring 31.2.  (Raising the halo- or ring-loading waves of the FP64
+  // two-step kernel, whose threads all carry interior points, changed nothing: 69.2-70.0
+  // us per step at 256^3 either way.)
+  if (raise_outer && role == 0) __builtin_amdgcn_s_setprio(1);
 
   const unsigned plane_bytes = (unsigned)(plane * sizeof(T));
   auto plane_range = [&](int z) { return (z >= 0 && z < nz) ? plane_bytes : 0u; };
@@ -1681,6 +1691,7 @@ struct BlockedConfig {
   int split = 1;     // two-step kernel, 8-byte elements, 64 x 16 tile, 512 threads: wave_step2_split (0: blocked)
   int triple = -1;   // three steps per pass (wave_step3_split): -1 by the rule, 0 never, 1 wherever it applies
   int zchunk3 = 0;   // three-step kernel: planes per work-group (0: from the grid size)
+  int prio3 = 1;     // three-step kernel: outer-ring waves at a raised priority (0: all equal)
 };
 
 static BlockedConfig blocked_config(const Dims &d, size_t esz)
@@ -1703,6 +1714,7 @@ static BlockedConfig blocked_config(const Dims &d, size_t esz)
     if (const char *e = getenv("FFPAT_STENCIL2_SPLIT")) c.split = atoi(e) ? 1 : 0;
     if (const char *e = getenv("FFPAT_STENCIL3")) c.triple = atoi(e) ? 1 : 0;
     if (const char *e = getenv("FFPAT_STENCIL3_ZCHUNK")) c.zchunk3 = atoi(e);
+    if (const char *e = getenv("FFPAT_STENCIL3_PRIO")) c.prio3 = atoi(e) ? 1 : 0;
     if (const char *e = getenv("FFPAT_STENCIL2_THREADS")) {
       const int v = atoi(e);
       c.threads2 = v == 1024 ? 1024 : (v == 256 ? 256 : 512);
@@ -2003,10 +2015,10 @@ hipError_t launch_wave_triple(const Dims &d, const T *pm1, const T *pk, T *r_out
     const f32x2 *k2 = reinterpret_cast<const f32x2 *>(kap);
     if (first)
       wave_step3_wide<true><<<grid, 1024, 0, s>>>(a, b, r2, o2, k2, e.nx, e.ny, e.nz, p.zchunk, p.tiles_x, p.tiles_y,
-                                                  p.n_tiles, cfg.order);
+                                                  p.n_tiles, cfg.order, cfg.prio3);
     else
       wave_step3_wide<false><<<grid, 1024, 0, s>>>(a, b, r2, o2, k2, e.nx, e.ny, e.nz, p.zchunk, p.tiles_x, p.tiles_y,
-                                                   p.n_tiles, cfg.order);
+                                                   p.n_tiles, cfg.order, cfg.prio3);
   } else {
     const PairShape p = triple_shape<T>(d, cfg);
     const int grid = ((p.n_tiles + 7) / 8) * 8;
@@ -2037,7 +2049,7 @@ hipError_t launch_wave_triple_div(const Dims &d, const T *pm1, const T *pk, T *r
     wave_step3_wide<false, true><<<grid, 1024, 0, s>>>(
         reinterpret_cast<const f32x2 *>(pm1), reinterpret_cast<const f32x2 *>(pk), reinterpret_cast<f32x2 *>(r_out),
         reinterpret_cast<f32x2 *>(o_out), reinterpret_cast<const f32x2 *>(kap), e.nx, e.ny, e.nz, p.zchunk, p.tiles_x,
-        p.tiles_y, p.n_tiles, cfg.order);
+        p.tiles_y, p.n_tiles, cfg.order, cfg.prio3);
     *taken = true;
     return hipGetLastError();
   } else {
