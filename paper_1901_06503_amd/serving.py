@@ -42,24 +42,25 @@ multi-step stencil kernels of a 192^3 or 256^3 job hold every compute unit while
 they run.  What remains is the 64^3 and 128^3 jobs, whose small launches leave the
 device mostly idle, running in the gaps of the others.  On the 120-job trace
 (grids 64^3..256^3, 50 iterations each, FP32), MI355X, "shortest" with concurrency
-3, aging 4, backlog 5, small jobs (up to 128^3) joining below the backlog: at 4
-jobs/s, above the device's capacity for the mix (about 3 jobs/s), 3.23 jobs/s against
-3.11 serial (+3.8%), median latency 1.17 s against 1.96 s, 99th percentile 4.2 s
-against 5.0 s; at 2 jobs/s median 0.331 s against 0.336 s, 99th percentile 1.78 s
-against 1.80 s, mean 0.45 s against 0.50 s.  Since the 128^3 and 192^3 jobs run three
-leapfrog steps per pass (launches that fill the device) the serial baseline is faster
-(2.97 jobs/s before) and leaves less idle device time to overlap (+8% before, with
-3.20 against 2.97 jobs/s).  Without the joining rule the 2 jobs/s latencies were the
-serial baseline's (0.373 / 1.855 s against 0.366 / 1.850 s, before that change); with
-any two jobs at a time below the backlog the long jobs that set the tail slow down
-(an earlier measurement: 0.41 / 2.25 s against 0.37 / 2.08 s serial); run one at a
-time always, the scheduler matches the serial baseline to 1%.
+3, aging 4, backlog 5, small jobs (up to 128^3) joining below the backlog, chunks of
+at least 20 ms: the device's capacity for this mix is about 3.7 jobs/s.  At 8 jobs/s
+(saturated) 3.74 jobs/s against 3.51 serial (+6.5%; mean GPU activity 99.5% against
+95.5%), median latency 8.0 s against 9.3 s, 99th percentile 14.4 s against 16.4 s.  At 4
+jobs/s, near capacity, both finish with the arrivals (3.24 against 3.23 jobs/s) and the
+gain is in latency: median 0.49 s against 1.15 s, 99th percentile 3.0 s against 3.7 s;
+at 2 jobs/s median 0.306 s against 0.310 s, 99th percentile 1.63 s against 1.65 s.
+Before the kernels of the 128^3..256^3 jobs got faster the device was further below
+the 4 jobs/s of the trace (2.97 serial jobs/s, +8% for the scheduler).  Without the
+joining rule the 2 jobs/s latencies were the serial baseline's; with any two jobs at a
+time below the backlog the long jobs that set the tail slow down; run one at a time
+always, the scheduler matches the serial baseline to 1%.
 
 `run_serial` is the plain baseline: one `ffpat_reconstruct` at a time in
 arrival order.
 """
 from __future__ import annotations
 
+import math
 import time
 from dataclasses import dataclass, field
 
@@ -145,7 +146,10 @@ class Scheduler:
     hbm_budget: device bytes the jobs' plans, data and iterates may hold together
     (plans kept for reuse included: idle ones are released, least recently used
     first, when an admission needs their memory).
-    max_active: slots.  iters_per_turn: FB iterations enqueued per job per turn.
+    max_active: slots.  iters_per_turn: FB iterations enqueued per job per turn, at least;
+    more where fewer would take less than min_chunk_s seconds of device time (by the
+    remaining-work estimate), so that small grids do not leave the device idle while
+    the host enqueues their next chunk.
     policy: "fill", "shortest" or "all" (see the module docstring); fill_voxels is
     the fill threshold; concurrency the number of jobs "shortest" advances while more
     than `backlog` jobs have arrived and are not finished, low_concurrency otherwise
@@ -157,12 +161,14 @@ class Scheduler:
 
     def __init__(self, hbm_budget: int, max_active: int = 8, iters_per_turn: int = 5, concurrency: int = 3,
                  policy: str = "shortest", fill_voxels: int = 192 ** 3, device="cuda", aging: float = 4.0,
-                 reuse_plans: bool = True, backlog: int = 5, low_concurrency: int = 1, join_voxels: int = 128 ** 3):
+                 reuse_plans: bool = True, backlog: int = 5, low_concurrency: int = 1, join_voxels: int = 128 ** 3,
+                 min_chunk_s: float = 0.02):
         if policy not in ("fill", "shortest", "all"):
             raise ValueError(f"unknown policy {policy!r}")
         self.hbm_budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.iters_per_turn = max(1, int(iters_per_turn))
+        self.min_chunk_s = float(min_chunk_s)
         self.policy = policy
         self.fill_voxels = int(fill_voxels)
         self.concurrency = max(1, int(concurrency))
@@ -223,7 +229,9 @@ class Scheduler:
             a.powered = True
             k = 0
         else:
-            k = min(self.iters_per_turn, j.n_iter - a.done_iters)
+            per_iter_s = 2.0 * a.plan.nt * j.c.numel() / _POINT_UPDATES_PER_S
+            k = max(self.iters_per_turn, int(math.ceil(self.min_chunk_s / per_iter_s)) if per_iter_s > 0 else 1)
+            k = min(k, j.n_iter - a.done_iters)
             a.plan.fb_enqueue(a.G, j.lam, k, a.h, use_plan_step=True, stream=a.stream)
         a.done_iters += k
         a.last_chunk = k
