@@ -221,6 +221,16 @@ class Scheduler:
         job.status = "running"
         return a
 
+    def _chunk(self, a):
+        """FB iterations of an active job's next chunk: iters_per_turn, or more where those
+        would take less than min_chunk_s of device time by the remaining-work estimate,
+        never more than the job has left."""
+        per_iter_s = 2.0 * a.plan.nt * a.job.c.numel() / _POINT_UPDATES_PER_S
+        k = self.iters_per_turn
+        if per_iter_s > 0:
+            k = max(k, int(math.ceil(self.min_chunk_s / per_iter_s)))
+        return min(k, a.job.n_iter - a.done_iters)
+
     def _advance(self, a):
         import torch
         j = a.job
@@ -229,9 +239,7 @@ class Scheduler:
             a.powered = True
             k = 0
         else:
-            per_iter_s = 2.0 * a.plan.nt * j.c.numel() / _POINT_UPDATES_PER_S
-            k = max(self.iters_per_turn, int(math.ceil(self.min_chunk_s / per_iter_s)) if per_iter_s > 0 else 1)
-            k = min(k, j.n_iter - a.done_iters)
+            k = self._chunk(a)
             a.plan.fb_enqueue(a.G, j.lam, k, a.h, use_plan_step=True, stream=a.stream)
         a.done_iters += k
         a.last_chunk = k

@@ -124,3 +124,16 @@ def test_small_jobs_join_the_oldest_below_the_backlog():
     s.join_voxels = 128 ** 3
     big_only = [_active(1, 0.0, 256), _active(2, 0.1, 192)]
     assert _ids(s._choose(big_only)) == [1]
+
+
+def test_chunks_hold_at_least_min_chunk_s_of_device_work():
+    # 2 solves x n_t x points per iteration at 4e11 point updates per second: a 64^3
+    # job (n_t 42, 55 us per iteration) takes all its 50 iterations in one chunk, a
+    # 128^3 job (n_t 85, 0.89 ms) 23, a 256^3 job (n_t 170, 14 ms) the minimum of 5
+    s = Scheduler(hbm_budget=1 << 30, iters_per_turn=5, min_chunk_s=0.02)
+    assert s._chunk(_active(1, 0.0, 64, nt=42)) == 50
+    assert s._chunk(_active(2, 0.0, 128, nt=85)) == 23
+    assert s._chunk(_active(3, 0.0, 256, nt=170)) == 5
+    assert s._chunk(_active(4, 0.0, 128, nt=85, done=40)) == 10      # what is left
+    s.min_chunk_s = 0.0
+    assert s._chunk(_active(5, 0.0, 64, nt=42)) == 5
