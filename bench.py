@@ -71,6 +71,10 @@ def parse():
     ap.add_argument("--serve-jobs", type=int, default=120,
                     help="--mode fb: jobs in the serving leg (the 120-job trace at 4 jobs/s: p50/p99 latency, "
                          "jobs/s against the serial baseline); 0 skips it")
+    ap.add_argument("--serve-saturated-jobs", type=int, default=60,
+                    help="--mode fb: jobs of a second serving trace at 8 jobs/s, above the device's capacity for "
+                         "the mix (throughput of the served form against the serial baseline when both are "
+                         "device-bound); 0 skips it, and so does --serve-jobs 0")
     ap.add_argument("--operator-384", type=int, default=1,
                     help="--mode fb: also time the forward operator A = X W_T at 384^3 / 360 angles / T = 0.6 "
                          "in FP32 and FP64 (the operator HBM fraction, 1/0)")
@@ -745,6 +749,25 @@ def main():
         except Exception as e:          # the serving leg never costs the benchmark line
             serve = {"error": f"{type(e).__name__}: {e}"}
         log(f"serving {serve}")
+    serve_sat = None
+    if args.serve_jobs > 0 and args.serve_saturated_jobs > 0:
+        log(f"saturated serving leg: {args.serve_saturated_jobs} jobs at 8 jobs/s")
+        try:
+            sv = serve_summary(args.serve_saturated_jobs, 8.0, 50, args.slots, args.concurrency, args.policy,
+                               args.fill_voxels, 1, args.seed + 1, args.aging, args.low_concurrency,
+                               args.backlog, args.join_voxels)
+            cb, se = sv["continuous_batching"], sv["serial"]
+            serve_sat = {"trace": f"{args.serve_saturated_jobs} jobs, Poisson 8 jobs/s, grids 64^3..256^3, "
+                                  f"50 FB iterations each, FP32, policy {args.policy}",
+                         "throughput_gain": sv["throughput_gain"], "jobs_per_s": cb["jobs_per_s"],
+                         "serial_jobs_per_s": se["jobs_per_s"], "latency_p50_s": cb["latency_p50_s"],
+                         "latency_p99_s": cb["latency_p99_s"], "serial_latency_p50_s": se["latency_p50_s"],
+                         "serial_latency_p99_s": se["latency_p99_s"],
+                         "gpu_busy_mean_pct": cb.get("gpu_busy_mean_pct"),
+                         "serial_gpu_busy_mean_pct": se.get("gpu_busy_mean_pct")}
+        except Exception as e:          # never costs the benchmark line
+            serve_sat = {"error": f"{type(e).__name__}: {e}"}
+        log(f"saturated serving {serve_sat}")
 
     line = {
         "metric": METRIC,
@@ -783,6 +806,7 @@ def main():
         "operator_384": op384,
         "cpu_baseline": cpu,
         "serving": serve,
+        "serving_saturated": serve_sat,
         "objective_last": float(out.objective[-1]) if len(out.objective) else None,
     }
     print(json.dumps(line), flush=True)
