@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--recipe", default="c256", help="synthetic workload recipe (c128, c256, c384)")
     ap.add_argument("--dtype", default="float32", choices=["float32", "float64"])
     ap.add_argument("--fp64-compare", type=int, default=1, help="also time FB iterations in FP64 (1/0)")
+    ap.add_argument("--reg", default="l2", choices=["l2", "grad"],
+                    help="regulariser of the timed FB iterations: l2 (prox in closed form) or grad "
+                         "(R = 1/2 ||D h||^2, prox by conjugate gradients on the device)")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="time the oracle on a bounded sample (1/0)")
     ap.add_argument("--naive-stencil", action="store_true")
     ap.add_argument("--n", type=int, default=0, help="--mode wave: grid edge instead of the recipe's")
@@ -442,17 +445,18 @@ def make_inputs(args, torch, ff, synth, dtype):
     return case, plan, G
 
 
-def time_fb(torch, plan, G, lam, steps, warmup):
+def time_fb(torch, plan, G, lam, steps, warmup, reg="l2"):
     h = torch.zeros(plan.shape, dtype=plan.dtype, device=G.device)
+    pos = reg == "l2"                  # the gradient prox has no positivity constraint
     t0 = time.perf_counter()
-    res = plan.reconstruct(G, lam, 0, step=0.0, n_power=20, h0=h)        # power iteration -> step
+    res = plan.reconstruct(G, lam, 0, step=0.0, n_power=20, h0=h, reg=reg, positivity=pos)   # power iteration
     torch.cuda.synchronize()
     t_power = time.perf_counter() - t0
     if warmup:
-        plan.reconstruct(G, lam, warmup, h0=h, use_plan_step=True)
+        plan.reconstruct(G, lam, warmup, h0=h, use_plan_step=True, reg=reg, positivity=pos)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = plan.reconstruct(G, lam, steps, h0=h, use_plan_step=True)
+    out = plan.reconstruct(G, lam, steps, h0=h, use_plan_step=True, reg=reg, positivity=pos)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     return t, t_power, out
@@ -687,7 +691,7 @@ def main():
     case, plan, G = make_inputs(args, torch, ff, synth, dtype)
     N, nang = case.n, len(case.angles)
     log(f"N={N} angles={nang} nt={plan.nt} dt={plan.dt:.6g}")
-    t, t_power, out = time_fb(torch, plan, G, case.lam, args.steps, args.warmup)
+    t, t_power, out = time_fb(torch, plan, G, case.lam, args.steps, args.warmup, args.reg)
     ms = 1e3 * t / args.steps
     log(f"FB {args.steps} iterations: {t:.3f}s ({ms:.2f} ms/iter), power iteration {t_power:.3f}s")
 
@@ -782,8 +786,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if dtype == torch.float32 else "f64",
         "data": "synthetic (seeded phantom: balls + tubes, smoothed; c: Gaussian bumps)",
-        "config": {"workload": f"{N}^3 grid, {nang} angles, T={case.T}, Algorithm 8 with positivity + "
-                               f"lambda={case.lam} l2 prox, "
+        "config": {"workload": f"{N}^3 grid, {nang} angles, T={case.T}, Algorithm 8 with "
+                               + (f"positivity + lambda={case.lam} l2 prox, " if args.reg == "l2" else
+                                  f"lambda={case.lam} gradient regulariser (CG prox), ")
                                + ("FP32 fields + FP64 reductions" if dtype == torch.float32 else "all-FP64"),
                    "grid": N, "angles": nang, "nt": plan.nt, "power_steps": 20,
                    "stencil": "naive" if args.naive_stencil else roof["kernel"]},

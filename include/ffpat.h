@@ -115,10 +115,13 @@ typedef struct {
   const uint8_t *support;   /* device [nz][ny][nx] mask chi_V (nonzero = inside), or NULL */
   const uint8_t *det_mask;  /* device [n_angles][nz][ns] mask chi_M (nonzero = measured), or NULL */
   double *objective;        /* host array of n_iter values J_k = 1/2<Lambda r_k, r_k> + lambda R(h_k), or NULL */
-  double cg_tol;            /* FFPAT_REG_GRAD prox: relative residual of the conjugate-gradient solve
-                               (0 selects 1e-12 for FP64 plans, 1e-6 for FP32) */
-  int32_t cg_maxit;         /* FFPAT_REG_GRAD prox: conjugate-gradient iterations per prox (0 selects 200);
-                               iterations after convergence are skipped on the device */
+  double cg_tol;            /* FFPAT_REG_GRAD prox (I + s lambda N)^-1, N = D^T D: with cg_tol and cg_maxit
+                               both 0 a 3D grid of at least nx^2 + ny^2 + nz^2 + nx + ny + nz points solves
+                               it directly (sine transforms along each axis diagonalise N); otherwise, and in
+                               2D mode, by conjugate gradients to this relative residual (0 selects 1e-12 for
+                               FP64 plans, 1e-6 for FP32) */
+  int32_t cg_maxit;         /* FFPAT_REG_GRAD prox by conjugate gradients: iterations per prox (0 selects
+                               200); iterations after convergence are skipped on the device */
 } ffpat_fb_params;
 
 /* Library version string. */

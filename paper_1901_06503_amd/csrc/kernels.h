@@ -218,6 +218,15 @@ hipError_t launch_cg_update(const Dims &d, T *x, T *r, const T *p, const T *q, c
                             double *partials, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_direction(const Dims &d, T *p, const T *r, const double *cg, hipStream_t s);
+// Direct prox of the gradient regulariser (3D): sine-transform tables (S_x, S_y, S_z
+// row-major, then the eigenvalues mu_x, mu_y, mu_z) into `tab` (at least nx^2 + ny^2 +
+// nz^2 + nx + ny + nz elements), one transform along `axis` (0 x, 1 y, 2 z), the scaling.
+template <typename T>
+hipError_t launch_dst_tables(const Dims &d, double dx, T *tab, hipStream_t s);
+template <typename T>
+hipError_t launch_dst_axis(const Dims &d, int axis, const T *in, T *out, const T *S, hipStream_t s);
+template <typename T>
+hipError_t launch_dst_scale(const Dims &d, T *u, const T *mu, const double *step, double lambda, hipStream_t s);
 // scalar steps: after init (done if rr <= tol^2 ff), alpha = rr / pq, then beta / convergence
 hipError_t launch_cg_check_init(double *cg, double tol, hipStream_t s);
 hipError_t launch_cg_alpha(double *cg, hipStream_t s);

@@ -472,6 +472,160 @@ hipError_t launch_vol_residual(T *w, const T *g, size_t n, double *partials, hip
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The gradient regulariser's prox solved directly (3D).  With zero values outside
+// the grid, the 7-point operator N is a sum over the axes of the 1D operator
+// (2 u_j - u_{j-1} - u_{j+1}) / dx^2, which the sine transform DST-I diagonalises:
+// S_kj = sin(pi (k+1)(j+1) / (n+1)) is symmetric with S S = (n+1)/2 I and
+// eigenvalues mu_k = (2 - 2 cos(pi (k+1) / (n+1))) / dx^2.  Hence
+// (I + tau N)^{-1} f = S3 D S3 f, S3 = S_x S_y S_z (one transform per axis) and
+// D = 8 / ((nx+1)(ny+1)(nz+1)) / (1 + tau (mu_x + mu_y + mu_z)): six transforms
+// and one scaling, exact up to rounding.
+// Tables (in a volume buffer of at least nx^2 + ny^2 + nz^2 + nx + ny + nz
+// elements): S_x, S_y, S_z row-major, then mu_x, mu_y, mu_z.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void dst_tables_kernel(T *tab, int nx, int ny, int nz, double inv_dx2)
+{
+  const long sx = (long)nx * nx, sy = (long)ny * ny, sz = (long)nz * nz;
+  const long total = sx + sy + sz + nx + ny + nz;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    long r = e;
+    if (r < sx + sy + sz) {
+      int n = nx;
+      if (r >= sx) {
+        r -= sx;
+        n = ny;
+        if (r >= sy) {
+          r -= sy;
+          n = nz;
+        }
+      }
+      const long k = r / n, j = r - k * n;
+      const long m = ((k + 1) * (j + 1)) % (2L * (n + 1));   // exact argument reduction
+      tab[e] = (T)sinpi((double)m / (double)(n + 1));
+    } else {
+      r -= sx + sy + sz;
+      int n = nx;
+      if (r >= nx) {
+        r -= nx;
+        n = ny;
+        if (r >= ny) {
+          r -= ny;
+          n = nz;
+        }
+      }
+      tab[e] = (T)((2.0 - 2.0 * cospi((double)(r + 1) / (double)(n + 1))) * inv_dx2);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_dst_tables(const Dims &d, double dx, T *tab, hipStream_t s)
+{
+  dst_tables_kernel<T><<<256, 256, 0, s>>>(tab, d.nx, d.ny, d.nz, 1.0 / (dx * dx));
+  return hipGetLastError();
+}
+
+// out = S in along one axis.  The volume is viewed as [A][n][B] (B = 1 for x, nx for
+// y, nx ny for z); column c = a B + b holds the n values at a n B + b + j B.  A
+// work-group takes 64 columns and every k, in tiles of 64 (16 per thread, the
+// thread's column fixed); j runs in chunks of 32 through LDS (the columns' values and
+// the transposed S tile), zero-filled beyond n and beyond the last column.
+template <typename T>
+__global__ void __launch_bounds__(256)
+dst_axis_kernel(const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ S, int n, long B, long ncols)
+{
+  constexpr int CT = 64, JC = 32, KT = 64, KP = KT + 4;
+  __shared__ T X[JC][CT + 1];
+  __shared__ __attribute__((aligned(16))) T St[JC][KP];
+  const int tid = threadIdx.x, col = tid & 63, kg = tid >> 6;
+  const long c0 = (long)blockIdx.x * CT;
+  const long cme = c0 + col;
+  const bool cin = cme < ncols;
+  long bme = 0;                               // offset of this thread's column (B > 1)
+  if (cin) {
+    const long a = cme / B;
+    bme = a * (long)n * B + (cme - a * B);
+  }
+  for (int k0 = 0; k0 < n; k0 += KT) {
+    T acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = T(0);
+    for (int j0 = 0; j0 < n; j0 += JC) {
+      __syncthreads();                        // the previous chunk's tiles are read
+      if (B == 1) {                           // x: each line contiguous, lanes along j
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int cc = (tid >> 5) + 8 * i, jj = tid & 31;
+          const long c = c0 + cc;
+          const int j = j0 + jj;
+          X[jj][cc] = (c < ncols && j < n) ? in[c * n + j] : T(0);
+        }
+      } else {                                // y, z: lanes along the columns
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int jj = (tid >> 6) + 4 * i;
+          const int j = j0 + jj;
+          X[jj][col] = (cin && j < n) ? in[bme + (long)j * B] : T(0);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = tid + 256 * i, kk = e >> 5, jj = e & 31;
+        const int k = k0 + kk, j = j0 + jj;
+        St[jj][kk] = (k < n && j < n) ? S[(long)k * n + j] : T(0);
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int jj = 0; jj < JC; ++jj) {
+        const T x = X[jj][col];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] += St[jj][kg * 16 + q] * x;
+      }
+    }
+    if (cin) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = k0 + kg * 16 + q;
+        if (k < n) out[(B == 1 ? cme * n : bme) + (long)k * B] = acc[q];
+      }
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_dst_axis(const Dims &d, int axis, const T *in, T *out, const T *S, hipStream_t s)
+{
+  const int n = axis == 0 ? d.nx : axis == 1 ? d.ny : d.nz;
+  const long B = axis == 0 ? 1L : axis == 1 ? (long)d.nx : (long)d.nx * d.ny;
+  const long ncols = (long)d.nvox() / n;
+  const long groups = (ncols + 63) / 64;
+  if (groups > 0x7fffffffL) return hipErrorInvalidValue;
+  dst_axis_kernel<T><<<(unsigned)groups, 256, 0, s>>>(in, out, S, n, B, ncols);
+  return hipGetLastError();
+}
+
+// u *= 8 / ((nx+1)(ny+1)(nz+1)) / (1 + step lambda (mu_x + mu_y + mu_z))
+template <typename T>
+__global__ void dst_scale_kernel(T *u, Dims d, const T *mu, const double *step, double lambda)
+{
+  const double tau = step[0] * lambda;
+  const double norm = 8.0 / (((double)d.nx + 1.0) * ((double)d.ny + 1.0) * ((double)d.nz + 1.0));
+  const T *mx = mu, *my = mu + d.nx, *mz = mu + d.nx + d.ny;
+  FFPAT_VOXEL_LOOP(d, i, x, y, z) {
+    const double den = 1.0 + tau * ((double)mx[x] + (double)my[y] + (double)mz[z]);
+    u[i] = (T)((double)u[i] * (norm / den));
+  }
+}
+
+template <typename T>
+hipError_t launch_dst_scale(const Dims &d, T *u, const T *mu, const double *step, double lambda, hipStream_t s)
+{
+  dst_scale_kernel<T><<<2048, 256, 0, s>>>(u, d, mu, step, lambda);
+  return hipGetLastError();
+}
+
 #define FFPAT_INST2(T)                                                                                          \
   template hipError_t launch_neglap_dot<T>(const Dims &, double, const T *, double *, hipStream_t);              \
   template hipError_t launch_cg_init<T>(const Dims &, double, const T *, const T *, T *, T *, const double *,     \
@@ -481,6 +635,9 @@ hipError_t launch_vol_residual(T *w, const T *g, size_t n, double *partials, hip
   template hipError_t launch_cg_update<T>(const Dims &, T *, T *, const T *, const T *, const double *, double *, \
                                           hipStream_t);                                                        \
   template hipError_t launch_cg_direction<T>(const Dims &, T *, const T *, const double *, hipStream_t);        \
+  template hipError_t launch_dst_tables<T>(const Dims &, double, T *, hipStream_t);                          \
+  template hipError_t launch_dst_axis<T>(const Dims &, int, const T *, T *, const T *, hipStream_t);          \
+  template hipError_t launch_dst_scale<T>(const Dims &, T *, const T *, const double *, double, hipStream_t); \
   template hipError_t launch_apply_support<T>(T *, const uint8_t *, size_t, hipStream_t);                       \
   template hipError_t launch_vol_residual<T>(T *, const T *, size_t, double *, hipStream_t);
 FFPAT_INST2(float)

@@ -608,9 +608,20 @@ int power_iteration(ffpat_plan *P, int n_power, bool two_step, bool precond, con
   return FFPAT_OK;
 }
 
+// Whether the gradient regulariser's prox is solved directly by sine transforms: 3D,
+// no conjugate-gradient controls given, and the transform tables fit in a volume.
+bool prox_by_sine_transforms(const ffpat_plan *P, const ffpat_fb_params *prm)
+{
+  const size_t nx = P->d.nx, ny = P->d.ny, nz = P->d.nz;
+  return P->d.ndim == 3 && prm->cg_tol <= 0 && prm->cg_maxit <= 0 &&
+         nx * nx + ny * ny + nz * nz + nx + ny + nz <= P->nvox;
+}
+
 // h <- prox_{s lambda R}(h - s grad), grad in V3.  l2 (+ positivity): closed form;
-// gradient regulariser: (I + s lambda N) h = f by conjugate gradients started from
-// h_k, with f in V1 and r, p, q in V2, V4, V3.  Support mask applied last.
+// gradient regulariser: (I + s lambda N) h = f with f in V1, either directly (three
+// sine transforms, the scaling, three transforms; tables in V3, ping-pong through V2
+// and V4) or by conjugate gradients started from h_k (r, p, q in V2, V4, V3).
+// Support mask applied last.
 template <typename T>
 int prox_step(ffpat_plan *P, T *h, const ffpat_fb_params *prm, hipStream_t s)
 {
@@ -626,6 +637,22 @@ int prox_step(ffpat_plan *P, T *h, const ffpat_fb_params *prm, hipStream_t s)
   double *cg = sc + SC_CG;
   double *pa = P->partials(), *pb = P->partials() + kReduceBlocks;
   HIP_TRY(launch_grad_step<T>(h, V3, V1, P->nvox, sc + SC_STEP, s));                 // f = h - s grad
+  if (prox_by_sine_transforms(P, prm)) {
+    const Dims &d = P->d;
+    T *tab = V3;                                                                       // grad is consumed
+    const T *Sx = tab, *Sy = Sx + (size_t)d.nx * d.nx, *Sz = Sy + (size_t)d.ny * d.ny;
+    const T *mu = Sz + (size_t)d.nz * d.nz;
+    HIP_TRY(launch_dst_tables<T>(d, P->dx, tab, s));
+    HIP_TRY(launch_dst_axis<T>(d, 0, V1, V2, Sx, s));
+    HIP_TRY(launch_dst_axis<T>(d, 1, V2, V4, Sy, s));
+    HIP_TRY(launch_dst_axis<T>(d, 2, V4, V2, Sz, s));
+    HIP_TRY(launch_dst_scale<T>(d, V2, mu, sc + SC_STEP, prm->lambda, s));
+    HIP_TRY(launch_dst_axis<T>(d, 0, V2, V4, Sx, s));
+    HIP_TRY(launch_dst_axis<T>(d, 1, V4, V2, Sy, s));
+    HIP_TRY(launch_dst_axis<T>(d, 2, V2, h, Sz, s));
+    if (prm->support) HIP_TRY(launch_apply_support<T>(h, prm->support, P->nvox, s));
+    return FFPAT_OK;
+  }
   HIP_TRY(launch_cg_init<T>(P->d, P->dx, V1, h, V2, V4, sc + SC_STEP, prm->lambda, pa, pb, s));
   HIP_TRY(launch_reduce_to(pa, kReduceBlocks, 1.0, cg + 0, s));
   HIP_TRY(launch_reduce_to(pb, kReduceBlocks, 1.0, cg + 1, s));

@@ -86,6 +86,27 @@ def test_gradient_regulariser_algorithm8(oracle, dtype):
     assert np.allclose(res.objective, obj_ref, rtol=tol, atol=0)
 
 
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("shape", [(12, 26, 30), (8, 20, 70)])
+def test_gradient_regulariser_direct_prox(oracle, dtype, shape):
+    """Without conjugate-gradient controls a 3D grid solves the prox (I + s lambda N)^-1
+    directly by sine transforms along each axis (Sec. 3.2, the prox of R = 1/2 ||D h||^2):
+    five FB iterations match the oracle, whose prox is conjugate gradients to 1e-13.
+    (8, 20, 70): x lines of 70 points take two k tiles and three j chunks of the
+    transform, and no axis has a multiple of 64 columns."""
+    nz, ny, nx = shape
+    assert nx * nx + ny * ny + nz * nz + nx + ny + nz <= nx * ny * nz     # tables fit: direct solve
+    g, c, h, G, P = _case(shape, 107, 18, dtype)
+    lam = 5e-4
+    h_ref, obj_ref, s_ref = oracle.fb(g, c, G, lam, n_iter=5, n_power=10, flags=oracle.PRECOND | oracle.REG_GRAD)
+    with P:
+        res = P.reconstruct(to_dev(G, dtype), lam, 5, n_power=10, reg="grad", positivity=False)
+    tol = TOL_FB[dtype]
+    assert res.step == pytest.approx(s_ref, rel=tol)
+    assert rel_l2(to_np(res.h), h_ref) <= tol
+    assert np.allclose(res.objective, obj_ref, rtol=tol, atol=0)
+
+
 def test_gradient_regulariser_rejects_positivity():
     import paper_1901_06503_amd as ff
     g, c, h, G, P = _case((4, 10, 12), 104, 5, F64)
