@@ -61,7 +61,7 @@ def test_report_covers_the_hot_kernels(report):
     for k in ("ffpat::wave_step3_wide<false, false>", "ffpat::wave_step3_wide<true, false>",
               "ffpat::wave_step3_wide<false, true>", "ffpat::project_lds_kernel<float, 8>",
               "ffpat::backproject_lds_kernel<float, 16>", "ffpat::residual_ramp_win_kernel<float>",
-              "ffpat::prox_l2_kernel<float>"):
+              "ffpat::prox_l2_kernel<float>", "ffpat::dst_axis_kernel<float>", "ffpat::dst_axis_kernel<double>"):
         assert k in report, f"{k} missing from the compiler's report"
 
 
